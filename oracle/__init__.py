@@ -1,0 +1,17 @@
+"""Plain FP64 CPU oracle for unfolded ISTA / Step-LISTA.
+
+TEST INFRASTRUCTURE ONLY. Nothing in the product path may import, call or
+link this package: only the test suite, the smoke check and the benchmark's
+CPU-baseline leg use it. It shares no code with the HIP library.
+"""
+from .slista import (  # noqa: F401
+    soft_threshold,
+    lipschitz,
+    lambda_max,
+    objective,
+    forward,
+    forward_backward,
+    kkt_residual,
+    lasso_solution,
+    brute_force_lasso,
+)

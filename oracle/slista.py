@@ -1,0 +1,277 @@
+"""FP64 oracle for the unfolded ISTA / Step-LISTA hot path.
+
+TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product path.
+
+Every function works in float64 with plain numpy / scipy primitives, follows
+the paper's formulas in the paper's order, and does no blocking or fusion.
+Layout is sample-major: X is [N, n], Z is [N, m] (row i = sample i), D is
+[n, m]. The paper's column vectors are the rows here, so D z_i is row i of
+Z @ D.T and D^T r_i is row i of R @ D.
+
+Paper: Ablin, Moreau, Massias, Gramfort, "Learning step sizes for unfolded
+sparse coding" (NeurIPS 2019, arXiv 1905.11071).
+
+Pins (tests that tie each function to something other than itself) are
+listed per function; none of them is left "parity unpinned".
+"""
+from __future__ import annotations
+
+from typing import Optional, Tuple
+
+import numpy as np
+import scipy.linalg
+
+__all__ = [
+    "soft_threshold",
+    "lipschitz",
+    "lambda_max",
+    "objective",
+    "forward",
+    "forward_backward",
+    "kkt_residual",
+    "lasso_solution",
+    "brute_force_lasso",
+]
+
+
+def _f64(a) -> np.ndarray:
+    return np.asarray(a, dtype=np.float64)
+
+
+def soft_threshold(u, theta):
+    """ST(u, theta) = sign(u) * max(|u| - theta, 0), with sign(0) = 0.
+
+    Section 1, the definition following Eq. (2); the sign convention is the
+    one of the Notation paragraph of Section 2.
+    Pinned by a hand-computed table (tests/golden/soft_threshold.json).
+    """
+    u = _f64(u)
+    return np.sign(u) * np.maximum(np.abs(u) - theta, 0.0)
+
+
+def lipschitz(D) -> float:
+    """L = greatest eigenvalue of D^T D (Section 1, after Eq. (2)).
+
+    LAPACK symmetric eigensolver on the m x m Gram matrix. Pinned against
+    the squared top singular value of D, the bounds 1 <= L <= m for
+    unit-norm columns, and L = 1 for an orthogonal D.
+    """
+    D = _f64(D)
+    return float(scipy.linalg.eigvalsh(D.T @ D)[-1])
+
+
+def lambda_max(D, X) -> np.ndarray:
+    """Per-sample lambda_max = ||D^T x||_inf (Section 2): below it the Lasso
+    solution is non-zero, at or above it the solution is exactly 0."""
+    return np.max(np.abs(_f64(X) @ _f64(D)), axis=1)
+
+
+def objective(D, X, Z, lam) -> np.ndarray:
+    """Per-sample Lasso cost F_x(z) = 1/2 ||x - D z||^2 + lam ||z||_1, Eq. (1).
+
+    Pinned by F(0) = 1/2 ||x||^2 and by the closed-form cost of the
+    Lemma 4.2 solution.
+    """
+    D, X, Z = _f64(D), _f64(X), _f64(Z)
+    R = X - Z @ D.T
+    return 0.5 * np.sum(R * R, axis=1) + lam * np.sum(np.abs(Z), axis=1)
+
+
+def forward(D, X, lam, alpha, return_iterates: bool = False):
+    """T layers of Step-LISTA / proximal gradient with a step sequence.
+
+    z^(0) = 0 and z^(t+1) = ST(z^(t) - alpha_t D^T (D z^(t) - x), lam alpha_t)
+    (Section 3, Eq. (5); Section 4, Eq. (14)). With alpha_t = 1/L for every
+    t this is ISTA, Eq. (2).
+
+    The gradient is taken in the paper's factored form D^T (D z - x): a
+    residual in R^n, then its correlation with the atoms.
+
+    Returns Z^(T) [N, m] and the objective trace F [T+1, N] with
+    F[t] = F_x(z^(t)). With return_iterates, also returns the list
+    [z^(0), ..., z^(T)].
+
+    Pins: monotone decrease of F for alpha_t <= 1/L (Section 3, Eq. (6)-(7)
+    majorization), the sublinear ISTA rate of Section 3 (after Prop. 3.2),
+    exact zeros when lam >= lambda_max (Section 2), one-step convergence for
+    an orthogonal dictionary (Section 3, after Prop. 3.2), KKT at
+    convergence (Lemma 2.1) and the Lemma 4.2 closed-form solution.
+    """
+    D, X = _f64(D), _f64(X)
+    alpha = _f64(alpha).reshape(-1)
+    N, m = X.shape[0], D.shape[1]
+    Z = np.zeros((N, m))
+    iterates = [Z]
+    trace = [objective(D, X, Z, lam)]
+    for a in alpha:
+        R = Z @ D.T - X                      # D z - x, per sample
+        U = Z - a * (R @ D)                  # z - alpha D^T (D z - x)
+        Z = soft_threshold(U, lam * a)
+        iterates.append(Z)
+        trace.append(objective(D, X, Z, lam))
+    F = np.stack(trace)
+    if return_iterates:
+        return Z, F, iterates
+    return Z, F
+
+
+def forward_backward(D, X, lam, alpha, dZ=None, dF=None) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Forward pass plus the reverse-mode derivative with respect to the steps.
+
+    The scalar differentiated is J = sum_i dF_i F_{x_i}(z_i^(T)) + <dZ, Z^(T)>.
+    With dF_i = 1/N and dZ = 0, J is the empirical unsupervised loss of
+    Section 4, Eq. (15), which the paper differentiates by automatic
+    differentiation (Appendix D, "Training the networks"). Here the
+    derivative is written out by hand:
+
+      seed       g = dZ + dF_i (D^T (D z^(T) - x) + lam sign z^(T))
+                 (a sub-gradient of F, sign(0) = 0)
+      for t = T-1 ... 0, with u = z^(t) - alpha_t D^T (D z^(t) - x):
+        mask     M = [ |u| > lam alpha_t ]   (derivative of ST; 0 at the kink)
+        v        = g * M
+        dJ/dalpha_t = - sum v * (D^T (D z^(t) - x) + lam sign u)
+        g        = v - alpha_t D^T D v       (back through the linear step)
+
+    Returns (Z^(T), F [T+1, N], dalpha [T]). Pinned against central finite
+    differences of `forward` and against the closed form for T = 1.
+    """
+    D, X = _f64(D), _f64(X)
+    alpha = _f64(alpha).reshape(-1)
+    N, m = X.shape[0], D.shape[1]
+    Z, F, iterates = forward(D, X, lam, alpha, return_iterates=True)
+    if dZ is None and dF is None:
+        raise ValueError("forward_backward needs dZ and/or dF")
+    g = np.zeros((N, m)) if dZ is None else _f64(dZ).copy()
+    if dF is not None:
+        dF = _f64(dF).reshape(-1)
+        grad_T = (Z @ D.T - X) @ D
+        g = g + dF[:, None] * (grad_T + lam * np.sign(Z))
+    dalpha = np.zeros_like(alpha)
+    for t in range(len(alpha) - 1, -1, -1):
+        a = alpha[t]
+        Zt = iterates[t]
+        grad = (Zt @ D.T - X) @ D            # D^T (D z^(t) - x)
+        U = Zt - a * grad
+        M = np.abs(U) > lam * a
+        v = np.where(M, g, 0.0)
+        dalpha[t] = -np.sum(v * (grad + lam * np.sign(U)))
+        g = v - a * ((v @ D.T) @ D)
+    return Z, F, dalpha
+
+
+def kkt_residual(D, X, Z, lam) -> np.ndarray:
+    """Per-sample distance to the Lasso optimality conditions, Lemma 2.1, Eq. (3).
+
+    With r_j = D_j^T (x - D z): for z_j != 0 the condition is
+    r_j = lam sign z_j, for z_j = 0 it is |r_j| <= lam. Returns
+    max_j of the violation (0 exactly at a solution).
+    """
+    D, X, Z = _f64(D), _f64(X), _f64(Z)
+    Rc = (X - Z @ D.T) @ D
+    viol = np.where(Z != 0.0, np.abs(Rc - lam * np.sign(Z)),
+                    np.maximum(np.abs(Rc) - lam, 0.0))
+    return np.max(viol, axis=1)
+
+
+def _polish(D, x, z, lam, tol):
+    """Exact solution on the support of z: solve the restricted optimality
+    system D_S^T D_S z_S = D_S^T x - lam s_S (Eq. (3) on the support) and
+    accept it only if it keeps the signs and satisfies Eq. (3) off the support.
+    Returns the polished vector or None."""
+    S = np.flatnonzero(z)
+    out = np.zeros_like(z)
+    if S.size:
+        s = np.sign(z[S])
+        DS = D[:, S]
+        try:
+            zS = np.linalg.solve(DS.T @ DS, DS.T @ x - lam * s)
+        except np.linalg.LinAlgError:
+            return None
+        if np.any(np.sign(zS) != s):
+            return None
+        out[S] = zS
+    r = D.T @ (x - D @ out)
+    off = np.ones(z.shape[0], bool)
+    off[S] = False
+    if off.any() and np.max(np.abs(r[off])) > lam + tol:
+        return None
+    return out
+
+
+def lasso_solution(D, X, lam, tol: float = 1e-10, max_iter: int = 200_000,
+                   chunk: int = 500) -> np.ndarray:
+    """The Lasso minimiser z*(x) of Eq. (1) for every sample, to machine precision.
+
+    FISTA (Beck and Teboulle 2009; the accelerated method the paper compares
+    against in Section 3) runs until every sample's support and signs are
+    stable, then each sample is polished on its support (see `_polish`) and
+    certified by the KKT conditions of Lemma 2.1 to `tol`. Unique under
+    Assumption 2.2 (continuous D). Pinned against `brute_force_lasso` for
+    m <= 8, against the Lemma 4.2 closed form, and by the KKT certificate.
+    """
+    D, X = _f64(D), _f64(X)
+    N, m = X.shape[0], D.shape[1]
+    L = lipschitz(D)
+    C = X @ D
+    G = D.T @ D
+    Z = np.zeros((N, m))
+    Y = Z.copy()
+    tk = 1.0
+    done = np.zeros(N, bool)
+    out = np.zeros((N, m))
+    it = 0
+    while it < max_iter:
+        for _ in range(chunk):
+            Zn = soft_threshold(Y - (Y @ G - C) / L, lam / L)
+            tn = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * tk * tk))
+            Y = Zn + ((tk - 1.0) / tn) * (Zn - Z)
+            Z, tk = Zn, tn
+        it += chunk
+        for i in np.flatnonzero(~done):
+            p = _polish(D, X[i], Z[i], lam, tol)
+            if p is not None and kkt_residual(D, X[i:i + 1], p[None], lam)[0] <= tol:
+                out[i] = p
+                done[i] = True
+        if done.all():
+            return out
+    raise RuntimeError(f"lasso_solution: {int((~done).sum())} samples not certified")
+
+
+def brute_force_lasso(D, x, lam) -> np.ndarray:
+    """Exact Lasso solution by enumerating all 3^m sign patterns (m <= 8).
+
+    For each pattern s in {-1, 0, +1}^m with support S (|S| <= n), the
+    smooth cost restricted to the open orthant face {sign z = s} has its
+    stationary point at D_S^T D_S z_S = D_S^T x - lam s_S; keep it if its
+    signs match s and return the candidate of least F_x (Eq. (1)). The
+    global minimiser lies in the relative interior of the face of its own
+    sign pattern, so it is among the candidates.
+    """
+    D, x = _f64(D), _f64(x).reshape(-1)
+    n, m = D.shape
+    if m > 8:
+        raise ValueError("brute_force_lasso is for m <= 8")
+    best, best_f = np.zeros(m), 0.5 * float(x @ x)
+    for code in range(3 ** m):
+        s = np.empty(m)
+        c = code
+        for j in range(m):
+            s[j] = (c % 3) - 1
+            c //= 3
+        S = np.flatnonzero(s)
+        if S.size == 0 or S.size > n:
+            continue
+        DS = D[:, S]
+        A = DS.T @ DS
+        if np.linalg.matrix_rank(A) < S.size:
+            continue
+        zS = np.linalg.solve(A, DS.T @ x - lam * s[S])
+        if np.any(np.sign(zS) != s[S]):
+            continue
+        z = np.zeros(m)
+        z[S] = zS
+        f = 0.5 * float(np.sum((x - D @ z) ** 2)) + lam * float(np.sum(np.abs(z)))
+        if f < best_f:
+            best, best_f = z, f
+    return best

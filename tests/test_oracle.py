@@ -1,0 +1,176 @@
+"""Pins for the FP64 oracle: every oracle function is checked against values,
+closed forms, invariants or brute force fixed by the paper and the
+mathematics, not against itself. CPU only."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import pins
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_soft_threshold_table():
+    with open(os.path.join(GOLDEN, "soft_threshold.json")) as f:
+        table = json.load(f)
+    for case in table["cases"]:
+        got = oracle.soft_threshold(np.array([case["u"]]), case["theta"])[0]
+        assert got == pytest.approx(case["st"], abs=1e-15), case
+        # sign(0) = 0: no negative zero leaks through as a non-zero
+        if case["st"] == 0.0:
+            assert got == 0.0
+
+
+def test_lipschitz_matches_svd_and_bounds():
+    pb = pins.small_problem(n=30, m=90, N=4)
+    L = oracle.lipschitz(pb.D)
+    s0 = np.linalg.svd(pb.D, compute_uv=False)[0]
+    assert L == pytest.approx(s0 * s0, rel=1e-12)
+    # unit-norm columns: diag(G) = 1 and trace(G) = m, so 1 <= L <= m
+    assert 1.0 <= L <= pb.m
+
+
+def test_lipschitz_orthogonal_is_one():
+    Q, _ = np.linalg.qr(np.random.default_rng(0).standard_normal((16, 16)))
+    assert oracle.lipschitz(Q) == pytest.approx(1.0, abs=1e-13)
+
+
+def test_objective_at_zero_and_lemma42():
+    pb = pins.small_problem()
+    F0 = oracle.objective(pb.D, pb.X, np.zeros((pb.N, pb.m)), pb.lam)
+    np.testing.assert_allclose(F0, 0.5 * np.sum(pb.X ** 2, axis=1), rtol=1e-14)
+    D, X, lam, zstar, Fstar = pins.lemma42_case()
+    assert oracle.objective(D, X, zstar, lam)[0] == pytest.approx(Fstar, rel=1e-13)
+
+
+def test_lambda_max_threshold():
+    pb = pins.small_problem()
+    lm = oracle.lambda_max(pb.D, pb.X)
+    assert np.all(lm >= 0) and np.max(lm) > 0   # all-zero codes give x = 0, lambda_max = 0
+    # lambda >= lambda_max(x) for every sample => every layer is exactly 0
+    L = oracle.lipschitz(pb.D)
+    Z, F = oracle.forward(pb.D, pb.X, float(np.max(lm)), np.full(25, 1.0 / L))
+    assert np.all(Z == 0.0)
+    np.testing.assert_array_equal(F[-1], F[0])
+
+
+def test_forward_monotone_ista():
+    pb = pins.small_problem()
+    assert pins.monotone_violation(oracle.forward, oracle.lipschitz, pb) <= 1e-14
+
+
+def test_forward_monotone_any_step_below_one_over_L():
+    pb = pins.small_problem(seed=9)
+    L = oracle.lipschitz(pb.D)
+    alpha = np.random.default_rng(1).uniform(0.1, 1.0, 60) / L
+    _, F = oracle.forward(pb.D, pb.X, pb.lam, alpha)
+    assert np.max(np.diff(F, axis=0)) <= 1e-13
+
+
+def test_forward_rate_bound():
+    pb = pins.small_problem(N=32)
+    zs = oracle.lasso_solution(pb.D, pb.X, pb.lam)
+    v = pins.rate_violation(oracle.forward, oracle.lipschitz, oracle.objective, zs, pb)
+    assert v <= 1e-12
+
+
+def test_forward_kkt_at_convergence():
+    pb = pins.small_problem(N=16)
+    assert pins.kkt_after_long_run(oracle.forward, oracle.kkt_residual, oracle.lipschitz, pb) <= 1e-9
+
+
+def test_forward_orthogonal_one_step():
+    assert pins.orthogonal_one_step_error(oracle.forward, oracle.kkt_residual) <= 1e-13
+
+
+def test_forward_reaches_lemma42_solution():
+    D, X, lam, zstar, Fstar = pins.lemma42_case()
+    L = oracle.lipschitz(D)
+    Z, F = oracle.forward(D, X, lam, np.full(3000, 1.0 / L))
+    np.testing.assert_allclose(Z, zstar, atol=1e-9)
+    assert F[-1, 0] == pytest.approx(Fstar, rel=1e-12)
+
+
+def test_forward_trace_matches_objective():
+    pb = pins.small_problem(N=8)
+    L = oracle.lipschitz(pb.D)
+    alpha = np.full(5, 1.0 / L)
+    Z, F, its = oracle.forward(pb.D, pb.X, pb.lam, alpha, return_iterates=True)
+    assert F.shape == (6, 8)
+    for t, Zt in enumerate(its):
+        np.testing.assert_allclose(F[t], oracle.objective(pb.D, pb.X, Zt, pb.lam), rtol=0)
+    np.testing.assert_array_equal(its[-1], Z)
+
+
+def test_zero_layers():
+    pb = pins.small_problem(N=4)
+    Z, F = oracle.forward(pb.D, pb.X, pb.lam, np.zeros(0))
+    assert np.all(Z == 0) and F.shape == (1, 4)
+    np.testing.assert_allclose(F[0], 0.5 * np.sum(pb.X ** 2, axis=1))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_lasso_solution_vs_brute_force(seed):
+    pb = synth.make_problem(5, 8, 6, 0.3, 0.05, 0.3, seed=100 + seed)
+    zs = oracle.lasso_solution(pb.D, pb.X, pb.lam)
+    for i in range(pb.N):
+        zb = oracle.brute_force_lasso(pb.D, pb.X[i], pb.lam)
+        np.testing.assert_allclose(zs[i], zb, atol=1e-10)
+        assert np.array_equal(np.sign(zs[i]), np.sign(zb))
+    assert np.max(oracle.kkt_residual(pb.D, pb.X, zs, pb.lam)) <= 1e-10
+
+
+def test_lasso_solution_lemma42():
+    D, X, lam, zstar, _ = pins.lemma42_case(seed=5)
+    np.testing.assert_allclose(oracle.lasso_solution(D, X, lam), zstar, atol=1e-12)
+
+
+def test_brute_force_zero_above_lambda_max():
+    pb = synth.make_problem(4, 6, 3, 0.3, 0.0, 0.5, seed=3)
+    for i in range(3):
+        lm = float(oracle.lambda_max(pb.D, pb.X[i:i + 1])[0])
+        assert np.all(oracle.brute_force_lasso(pb.D, pb.X[i], lm * 1.0001) == 0.0)
+        assert np.any(oracle.brute_force_lasso(pb.D, pb.X[i], lm * 0.5) != 0.0)
+
+
+def test_kkt_residual_definition_points():
+    D, X, lam, zstar, _ = pins.lemma42_case(seed=2)
+    assert oracle.kkt_residual(D, X, zstar, lam)[0] <= 1e-13
+    bad = zstar.copy()
+    bad[0, 5] *= 0.9
+    assert oracle.kkt_residual(D, X, bad, lam)[0] > 1e-3
+
+
+@pytest.mark.parametrize("use_dz", [False, True])
+def test_adjoint_vs_finite_differences(use_dz):
+    pb = synth.make_problem(8, 16, 24, 0.2, 0.01, 0.1, seed=21)
+    L = oracle.lipschitz(pb.D)
+    alpha = synth.perturbed_steps(L, 6, seed=4)
+    dF = np.full(pb.N, 1.0 / pb.N)
+    dZ = np.random.default_rng(5).standard_normal((pb.N, pb.m)) if use_dz else None
+    _, _, g = oracle.forward_backward(pb.D, pb.X, pb.lam, alpha, dZ=dZ, dF=dF)
+    fd = pins.fd_gradient(oracle.forward, pb.D, pb.X, pb.lam, alpha, dZ, dF)
+    assert np.max(np.abs(g - fd)) <= 1e-6 * np.max(np.abs(fd))
+
+
+def test_adjoint_one_layer_closed_form():
+    pb = synth.make_problem(8, 16, 24, 0.2, 0.01, 0.1, seed=22)
+    a = 0.7 / oracle.lipschitz(pb.D)
+    dF = np.random.default_rng(3).uniform(0.5, 1.5, pb.N)
+    _, _, g = oracle.forward_backward(pb.D, pb.X, pb.lam, np.array([a]), dF=dF)
+    assert g[0] == pytest.approx(pins.one_layer_gradient(pb.D, pb.X, pb.lam, a, dF), rel=1e-12)
+
+
+def test_adjoint_is_linear_in_seeds():
+    pb = synth.make_problem(6, 12, 10, 0.2, 0.0, 0.1, seed=23)
+    alpha = synth.perturbed_steps(oracle.lipschitz(pb.D), 5, seed=1)
+    rng = np.random.default_rng(8)
+    dZ, dF = rng.standard_normal((10, 12)), rng.standard_normal(10)
+    _, _, g1 = oracle.forward_backward(pb.D, pb.X, pb.lam, alpha, dZ=dZ)
+    _, _, g2 = oracle.forward_backward(pb.D, pb.X, pb.lam, alpha, dF=dF)
+    _, _, g3 = oracle.forward_backward(pb.D, pb.X, pb.lam, alpha, dZ=dZ, dF=dF)
+    np.testing.assert_allclose(g3, g1 + g2, rtol=1e-12, atol=1e-14)
