@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched Step-LISTA forward + backward on one MI355X.
+
+One step = one call of the whole hot path over the batch: correlations
+c = D^T x, T fused layers forward, the objective, the backward seed, T fused
+layers back and the reductions that give d(mean F)/d alpha. Inputs are
+resident in HBM before timing starts. Throughput is sample-layers per
+second (N * T per step). Both precisions of the contraction are timed (BF16
+operands on MFMA, and FP32); `value` is the BF16 figure, and the FP32 one and
+the objective gaps of both are reported beside it.
+
+Prints ONE JSON line. Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "sample-layers/s fwd+bwd (BF16-MFMA vs FP32) at fixed obj-gap; % MFMA/HBM peak"
+PEAK = {"bf16_tflops": 2500.0, "fp32_tflops": 157.3, "hbm_gbs": 8000.0}
+
+
+def roofline(kind: str, avg_ms: float, N: int, m: int, prec: str) -> dict:
+    """Roofline of one fused layer launch.
+
+    Algorithmic work per launch: 2 N m^2 flops (P = Z G). Algorithmic HBM
+    bytes per launch: forward layer 12 m N (read z^t and c, write z^{t+1});
+    backward layer 16 m N (read v^t, z^t, z^{t+1}, write v^{t-1})."""
+    flops = 2.0 * N * m * m
+    bytes_ = (12.0 if kind == "forward_layer" else 16.0) * m * N
+    peak_f = PEAK["bf16_tflops"] if prec == "bf16" else PEAK["fp32_tflops"]
+    ridge = peak_f * 1e12 / (PEAK["hbm_gbs"] * 1e9)
+    sec = avg_ms * 1e-3
+    if flops / bytes_ < ridge:
+        ach = bytes_ / sec / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                "frac": round(ach / PEAK["hbm_gbs"], 4), "traffic": None, "kernel": kind,
+                "avg_ms": round(avg_ms, 5), "mfma_frac": round(flops / sec / 1e12 / peak_f, 4)}
+    ach = flops / sec / 1e12
+    return {"bound": "mfma", "achieved": round(ach, 2), "peak": peak_f, "unit": "TFLOP/s",
+            "frac": round(ach / peak_f, 4), "traffic": None, "kernel": kind, "avg_ms": round(avg_ms, 5),
+            "hbm_frac": round(bytes_ / sec / 1e9 / PEAK["hbm_gbs"], 4)}
+
+
+def time_precision(sl, torch, d, X, lam, alpha, prec, steps, warmup, ckpt):
+    N, T = X.shape[0], alpha.shape[0]
+    ws = d.workspace(N, T, prec, ckpt)
+    for _ in range(warmup):
+        sl.forward_backward(d, X, lam, alpha, prec=prec, ckpt_every=ckpt, ws=ws)
+    torch.cuda.synchronize()
+    sl.profile_begin()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    out = None
+    for _ in range(steps):
+        out = sl.forward_backward(d, X, lam, alpha, prec=prec, ckpt_every=ckpt, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = sl.profile_end()
+    ms = e0.elapsed_time(e1) / steps
+    kernels = {k: v for k, v in prof.items() if k != "dropped" and v[0] > 0}
+    dom = max(kernels, key=lambda k: kernels[k][1])
+    Z, F, loss, dalpha, _ = out
+    del ws
+    return {"ms_per_step": ms, "wall_ms_per_step": wall * 1e3 / steps, "kernels": kernels, "dominant": dom,
+            "F": F, "loss": float(loss.item()), "dalpha_norm": float(dalpha.norm().item())}
+
+
+def gap_report(sl, torch, d, X, lam, alpha, F_by_prec, n_sub=4096, T_ref=3000):
+    """Objective gap of each precision on a sample subset, against a long
+    FP32 ISTA run (T_ref layers, alpha = 1/L) computed by the same library."""
+    sub = X[:n_sub].contiguous()
+    a_ref = torch.full((T_ref,), float(alpha[0].item()), device=X.device, dtype=torch.float32)
+    _, Fr, _, _ = sl.forward(d, sub, lam, a_ref, prec="fp32", want_loss=False, ckpt_every=0)
+    fr = Fr.double().mean().item()
+    out = {"reference": f"FP32 ISTA, {T_ref} layers, first {n_sub} samples"}
+    for p, F in F_by_prec.items():
+        out[f"gap_{p}"] = F[:n_sub].double().mean().item() - fr
+    if "bf16" in F_by_prec and "fp32" in F_by_prec:
+        out["bf16_vs_fp32_rel"] = abs(out["gap_bf16"] - out["gap_fp32"]) / abs(out["gap_fp32"])
+        out["within_2e-2"] = out["bf16_vs_fp32_rel"] <= 2e-2
+    return out
+
+
+def cpu_baseline(pb, alpha_np, n_sub: int) -> dict:
+    """The FP64 oracle (numpy/OpenBLAS, untuned) on the first n_sub samples."""
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    Xs = pb.X[:n_sub]
+    t0 = time.perf_counter()
+    oracle.forward_backward(pb.D, Xs, pb.lam, alpha_np, dF=np.full(n_sub, 1.0 / n_sub))
+    sec = time.perf_counter() - t0
+    T = len(alpha_np)
+    return {"value": round(n_sub * T / sec, 1), "unit": "sample-layers/s", "cores": int(threads),
+            "kind": "oracle", "sample": f"first {n_sub} of {pb.N} samples, all {T} layers, fwd+bwd, FP64 "
+                                        f"({sec:.1f} s)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="prec_256x1024")
+    ap.add_argument("--precs", default="bf16,fp32")
+    ap.add_argument("--ckpt-every", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gap", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the path needs no collectives); --gpus {args.gpus} "
+              f"is not supported", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1905_11071_amd as sl
+
+    cfg = synth.CONFIGS[args.workload]
+    print(f"[bench] generating {args.workload} {cfg}", file=sys.stderr, flush=True)
+    pb = synth.make_problem(cfg["n"], cfg["m"], cfg["N"], cfg["p"], cfg["sigma"], cfg["lam_frac"], cfg["seed"])
+    dev = torch.device("cuda:0")
+    D = torch.tensor(pb.D32(), device=dev)
+    X = torch.tensor(pb.X32(), device=dev)
+    d = sl.Dictionary(D)
+    L, iters = d.lipschitz(max_iter=200_000, rtol=1e-13)
+    T = cfg["T"]
+    alpha = torch.full((T,), float(np.float32(1.0 / L)), device=dev, dtype=torch.float32)
+    print(f"[bench] L={L:.9f} ({iters} power iterations)", file=sys.stderr, flush=True)
+
+    res = {}
+    for p in args.precs.split(","):
+        r = time_precision(sl, torch, d, X, pb.lam, alpha, p, args.steps, args.warmup, args.ckpt_every)
+        dk = r["dominant"]
+        n_l, tot = r["kernels"][dk]
+        r["roofline"] = roofline(dk, tot / n_l, pb.N, pb.m, p)
+        r["value"] = pb.N * T / (r["ms_per_step"] * 1e-3)
+        res[p] = r
+        print(f"[bench] {p}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4g} sample-layers/s, "
+              f"kernels={ {k: (v[0], round(v[1], 3)) for k, v in r['kernels'].items()} }",
+              file=sys.stderr, flush=True)
+
+    gap = None
+    if not args.no_gap:
+        gap = gap_report(sl, torch, d, X, pb.lam, alpha, {p: r["F"] for p, r in res.items()})
+        print(f"[bench] gap {gap}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(pb, np.asarray(alpha.cpu().numpy(), np.float64), min(args.cpu_sample, pb.N))
+        print(f"[bench] cpu baseline {cpu}", file=sys.stderr, flush=True)
+
+    head = "bf16" if "bf16" in res else next(iter(res))
+    h = res[head]
+    line = {
+        "metric": METRIC,
+        "value": round(h["value"], 1),
+        "unit": "sample-layers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(h["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": pb.n, "m": pb.m, "N": pb.N, "T": T,
+                   "pass": "forward+backward", "ckpt_every": args.ckpt_every, "alpha": "1/L",
+                   "contraction": "BF16 MFMA, FP32 accumulate" if head == "bf16" else "FP32 MFMA"},
+        "roofline": h["roofline"],
+        "cpu_baseline": cpu,
+        "per_precision": {p: {"value": round(r["value"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                              "roofline": r["roofline"],
+                              "kernels_ms": {k: [v[0], round(v[1] / args.steps, 4)] for k, v in r["kernels"].items()},
+                              "loss": r["loss"]}
+                          for p, r in res.items()},
+        "objective_gap": gap,
+    }
+    print(json.dumps(line))
+    d.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,199 @@
+/*
+ * slista.h -- C ABI of the MI355X (gfx950) library for batched unfolded ISTA /
+ * Step-LISTA.
+ *
+ * Paper: Ablin, Moreau, Massias, Gramfort, "Learning step sizes for unfolded
+ * sparse coding", NeurIPS 2019 (arXiv 1905.11071).
+ *
+ * The library evaluates, for a batch of N samples x_i in R^n, a dictionary
+ * D in R^{n x m}, a regularisation lambda > 0 and T step sizes alpha_t > 0,
+ * the Step-LISTA network of Section 4, Eq. (14):
+ *
+ *     z^(0) = 0,
+ *     z^(t+1) = ST( z^(t) - alpha_t D^T (D z^(t) - x), lambda alpha_t ),
+ *     ST(u, theta) = sign(u) max(|u| - theta, 0)        (Section 1, Eq. (2)),
+ *
+ * which is proximal gradient descent with a step sequence (Section 3, Eq. (5))
+ * and ISTA (Eq. (2)) when every alpha_t = 1/L. The Lasso cost it descends is
+ * F_x(z) = 1/2 ||x - D z||^2 + lambda ||z||_1 (Section 1, Eq. (1)); the
+ * training loss is its mean over the batch (Section 4, Eq. (15)), and the
+ * library returns the derivative of that loss with respect to every alpha_t.
+ *
+ * The device computes the gradient in Gram form, D^T (D z - x) = G z - c with
+ * G = D^T D (m x m) and c = D^T x, so that every layer is one dense
+ * contraction P = Z G over the batch, run on the MFMA units, followed by the
+ * step, the threshold and the objective in FP32.
+ *
+ * Conventions (every entry point)
+ *  - Pointers named "device" are HIP device pointers owned by the caller; the
+ *    library never frees or keeps them beyond the call. Only slista_dict
+ *    owns device memory (its Gram matrices), allocated in
+ *    slista_dict_create and released in slista_dict_destroy.
+ *  - All matrices are row-major and sample-major: X is [N, n] (row i is x_i),
+ *    Z and dZ are [N, m] (row i is z_i), D is [n, m].
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream). Work is
+ *    enqueued on it and the call returns without waiting, except where a
+ *    function says it synchronises.
+ *  - Every function returns an slista_status. Arguments are checked on the
+ *    host before anything is enqueued; a failed check enqueues nothing. The
+ *    text of the last failure on the calling thread is slista_last_error().
+ *  - Device values are not inspected: alpha_t > 0 (Section 4, parameters in
+ *    R+*) and finite inputs are preconditions. Non-finite inputs propagate
+ *    as IEEE NaN/Inf.
+ *  - Calls that overlap on the same workspace race; calls on distinct
+ *    workspaces may run concurrently on different streams.
+ */
+#ifndef SLISTA_H_
+#define SLISTA_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SLISTA_API __attribute__((visibility("default")))
+#define SLISTA_ABI_VERSION 1
+
+typedef enum {
+  SLISTA_OK = 0,
+  SLISTA_EINVAL = -1,     /* bad argument: size, null pointer, lambda, precision, workspace */
+  SLISTA_ENOMEM = -2,     /* device allocation failed (slista_dict_create only) */
+  SLISTA_EHIP = -3,       /* a HIP runtime call or kernel launch failed */
+  SLISTA_ENOTSUP = -4,    /* valid request this build does not support (e.g. no gfx950 device) */
+  SLISTA_ENOTCONV = -5    /* power iteration reached max_iter before rtol */
+} slista_status;
+
+/* Arithmetic of the contraction P = Z G. The step, threshold and objective
+ * are FP32 in both modes. */
+typedef enum {
+  SLISTA_FP32 = 0,  /* FP32 operands on MFMA (v_mfma_f32_16x16x4_f32), FP32 accumulate */
+  SLISTA_BF16 = 1   /* BF16 operands on MFMA (v_mfma_f32_16x16x32_bf16), FP32 accumulate;
+                       z is rounded to BF16 only as the operand of the product */
+} slista_prec;
+
+typedef struct slista_dict slista_dict;
+
+/* Version of this ABI (SLISTA_ABI_VERSION). */
+SLISTA_API int slista_abi_version(void);
+
+/* Static text for a status code. Never NULL. */
+SLISTA_API const char* slista_status_string(int status);
+
+/* Detail of the last failed call on the calling thread ("" if none). */
+SLISTA_API const char* slista_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Dictionary
+ * ------------------------------------------------------------------------- */
+
+/* Build the per-dictionary state from D (device, FP32, [n, m] row-major,
+ * 1 <= n <= 65536, 1 <= m <= 8192): the Gram matrix G = D^T D accumulated in
+ * FP64 and stored in FP32 and BF16, and D^T, each zero-padded to
+ * m_pad = m rounded up to a multiple of 64. Allocates device memory (the only
+ * allocation the library makes) and synchronises `stream` before returning.
+ * On success *out owns that memory until slista_dict_destroy. */
+SLISTA_API int slista_dict_create(const float* D, int n, int m, void* stream, slista_dict** out);
+
+/* Release a dictionary (NULL is accepted). Synchronises the device first. */
+SLISTA_API int slista_dict_destroy(slista_dict* dict);
+
+/* Sizes of a dictionary: n, m and the padded m used in the workspace. */
+SLISTA_API int slista_dict_dims(const slista_dict* dict, int* n, int* m, int* m_pad);
+
+/* Copy G = D^T D (FP32, [m, m], row-major) to device buffer G_out. */
+SLISTA_API int slista_dict_gram(const slista_dict* dict, float* G_out, void* stream);
+
+/* L = greatest eigenvalue of D^T D (Section 1, after Eq. (2)), by power
+ * iteration in FP64 on the FP32 Gram matrix, stopped when two successive
+ * Rayleigh quotients differ by at most rtol (relative) or after max_iter
+ * iterations (1 <= max_iter <= 10^7). Writes L to *L_out (host) and the
+ * iteration count to *iters (host, may be NULL). Synchronises `stream`.
+ * Returns SLISTA_ENOTCONV, with the last estimate in *L_out, if rtol was not
+ * reached. */
+SLISTA_API int slista_dict_lipschitz(slista_dict* dict, int max_iter, double rtol, double* L_out,
+                                     int* iters, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Forward and backward through T layers
+ *
+ * Common arguments:
+ *   X        device, FP32 [N, n]: the samples.           0 <= N <= 2^26
+ *   lambda   regularisation, finite and > 0 (Eq. (1)).
+ *   alpha    device, FP32 [T]: the step sizes alpha_0 .. alpha_{T-1} (Eq. (14)).
+ *   T        number of layers, 0 <= T <= 100000.
+ *   prec     slista_prec of the contraction.
+ *   ckpt_every  layer checkpointing of the tape kept for the backward:
+ *            0  = keep no tape (forward only),
+ *            1  = keep every iterate z^(1) .. z^(T),
+ *            k>1 = keep z^(k), z^(2k), ... and z^(T); the backward recomputes
+ *                  the layers in between, segment by segment.
+ *   ws, ws_bytes  device workspace of at least slista_workspace_size() bytes
+ *            for the same (dict, N, T, prec, ckpt_every); 256-byte aligned.
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes for the given sizes. */
+SLISTA_API int slista_workspace_size(const slista_dict* dict, int N, int T, int prec, int ckpt_every,
+                                     size_t* bytes);
+
+/* Forward pass. Writes
+ *   Z     device FP32 [N, m]: z^(T) (required),
+ *   F     device FP32: if f_trace == 0, [N] with F_{x_i}(z_i^(T)); if f_trace
+ *         != 0, [T+1, N] with row t = F_{x_i}(z_i^(t)) (Eq. (1)); NULL = skip,
+ *   loss  device FP32 [1]: mean_i F_{x_i}(z_i^(T)) (Eq. (15)); NULL = skip.
+ * F and loss are evaluated in FP32 from G z, c and ||x||^2 (monitoring
+ * accuracy). With ckpt_every >= 1 the workspace keeps the tape that
+ * slista_backward reads. */
+SLISTA_API int slista_forward(const slista_dict* dict, const float* X, int N, float lambda,
+                              const float* alpha, int T, int prec, float* Z, float* F, int f_trace,
+                              float* loss, int ckpt_every, void* ws, size_t ws_bytes, void* stream);
+
+/* Reverse pass (derivation in Section 4 / Appendix D: the paper uses
+ * automatic differentiation; here it is written out by hand). Differentiates
+ *     J = sum_i dF_i F_{x_i}(z_i^(T)) + <dZ, Z^(T)>
+ * with respect to alpha and writes dalpha (device FP32 [T]). dZ (device FP32
+ * [N, m]) and dF (device FP32 [N]) may each be NULL (= 0) but not both; with
+ * dF_i = 1/N and dZ = 0, J is the loss of Eq. (15). The derivative of ST is
+ * taken as 1 where |u| > lambda alpha_t and 0 elsewhere, and sign(0) = 0 in
+ * the sub-gradient of |z| (a valid sub-gradient at the kinks).
+ * Precondition: ws holds the tape of a slista_forward call with the same
+ * dict, X, N, lambda, alpha, T, prec and ckpt_every >= 1, and nothing has
+ * written to ws since. */
+SLISTA_API int slista_backward(const slista_dict* dict, const float* X, int N, float lambda,
+                               const float* alpha, int T, int prec, const float* dZ, const float* dF,
+                               float* dalpha, int ckpt_every, void* ws, size_t ws_bytes, void* stream);
+
+/* Forward and backward of the mean loss (Eq. (15)) in one call: Z, F (as
+ * slista_forward with f_trace = 0; may be NULL), loss (may be NULL) and
+ * dalpha = d loss / d alpha (required). ckpt_every must be >= 1. */
+SLISTA_API int slista_forward_backward(const slista_dict* dict, const float* X, int N, float lambda,
+                                       const float* alpha, int T, int prec, float* Z, float* F,
+                                       float* loss, float* dalpha, int ckpt_every, void* ws,
+                                       size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing (diagnostics)
+ *
+ * While recording is on, the library brackets every launch it makes with a
+ * pair of HIP events on the launch stream, keyed by kernel class:
+ *   0 correlation product c = D^T x     1 forward layer (fused)
+ *   2 objective F(z^T) (fused)          3 backward seed (fused)
+ *   4 backward layer (fused)            5 elementwise and reductions
+ * slista_profile_end synchronises on the recorded events and returns, per
+ * class, the number of launches and the summed event-measured time in
+ * milliseconds. Up to 65536 launches are recorded per begin/end pair; later
+ * launches are counted in *dropped. Recording creates HIP events, so it must
+ * not be on during stream capture. Process-wide, not thread-safe.
+ * ------------------------------------------------------------------------- */
+#define SLISTA_PROFILE_KINDS 6
+
+SLISTA_API int slista_profile_begin(void);
+
+/* launches[6], total_ms[6] (host arrays); dropped may be NULL. */
+SLISTA_API int slista_profile_end(int* launches, double* total_ms, int* dropped);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLISTA_H_ */

@@ -1,0 +1,17 @@
+"""MI355X (gfx950) library for batched unfolded ISTA / Step-LISTA.
+
+The computation lives in libslista.so (HIP kernels behind the C ABI of
+include/slista.h); this package is its thin PyTorch binding.
+"""
+from .ops import (  # noqa: F401
+    PRECISIONS,
+    Dictionary,
+    SlistaError,
+    backward,
+    forward,
+    forward_backward,
+    profile_begin,
+    profile_end,
+    slista,
+    SlistaFunction,
+)

@@ -1,0 +1,547 @@
+// C ABI of libslista: argument checks, workspace layout and the stream-ordered
+// sequence of launches for the forward and reverse passes of Step-LISTA.
+//
+// Forward (Section 4, Eq. (14)), z^(0) = 0:
+//   prep     c = D^T x (FP32 MFMA product with D^T), ||x||^2 (FP64)
+//   layer 0  z^(1) = ST(a_0 c, lam a_0)                       (elementwise)
+//   layer t  z^(t+1) = ST(z^t - a_t (G z^t - c), lam a_t)     (fused MFMA kernel)
+//   final    F(z^T) from G z^T                                (fused MFMA kernel)
+// Reverse (hand-derived; the paper differentiates by autodiff, Appendix D):
+//   seed     v^{T-1} = [z^T != 0] (dF (G z^T - c + lam sign z^T) + dZ)
+//   layer t  dJ/da_t = -(1/a_t) sum v^t (z^t - z^{t+1});
+//            v^{t-1} = [z^t != 0] (v^t - a_t G v^t)           (fused MFMA kernel)
+//   layer 0  dJ/da_0 from v^0 and z^(1) only                  (elementwise)
+// With checkpointing every k layers the forward keeps z^k, z^2k, ... and z^T;
+// the reverse pass recomputes each segment's interior before walking it.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/slista.h"
+#include "common.hpp"
+
+struct slista_dict {
+  slista::Dict d;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(SLISTA_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+// ---------------------------------------------------------------- timing
+// Event pairs around every launch while recording is on (slista_profile_*).
+enum Kind { kKCorr = 0, kKFwd = 1, kKFinal = 2, kKSeed = 3, kKBwd = 4, kKOther = 5 };
+constexpr size_t kMaxRecords = 65536;
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, size_t>> recs;
+  int dropped = 0;
+};
+Profiler g_prof;
+
+struct ProfScope {
+  size_t idx = (size_t)-1;
+  int kind;
+  hipStream_t s;
+  ProfScope(int k, hipStream_t st) : kind(k), s(st) {
+    if (!g_prof.on) return;
+    if (g_prof.recs.size() >= kMaxRecords) {
+      ++g_prof.dropped;
+      return;
+    }
+    const size_t i = 2 * g_prof.recs.size();
+    while (g_prof.pool.size() < i + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      g_prof.pool.push_back(e);
+    }
+    if (hipEventRecord(g_prof.pool[i], s) == hipSuccess) idx = i;
+  }
+  ~ProfScope() {
+    if (idx == (size_t)-1) return;
+    if (hipEventRecord(g_prof.pool[idx + 1], s) == hipSuccess) g_prof.recs.emplace_back(kind, idx);
+  }
+};
+
+#define LAUNCH(kind, stream, expr)     \
+  do {                                 \
+    ProfScope ps_((kind), (stream));   \
+    HIP_TRY(expr);                     \
+  } while (0)
+
+constexpr int kMaxN = 1 << 26;
+constexpr int kMaxT = 100000;
+constexpr int kMaxM = 8192;
+constexpr int kMaxn = 65536;
+constexpr int kTileRows = 128;  // rows of the fused kernel's workgroup tile
+constexpr int kTileCols = 128;  // columns of the fused kernel's workgroup tile
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t C = 0, xsq = 0, Fd = 0, fpart = 0, dpart = 0, pp = 0, ckpt = 0, seg = 0, vbuf = 0;
+  size_t total = 0;
+  size_t zbytes = 0;
+  int k = 0, nckpt = 0, nseg = 0, col_tiles = 0, P = 0;
+};
+
+Layout make_layout(const slista::Dict& d, int N, int T, int k) {
+  Layout L;
+  L.k = k;
+  L.zbytes = (size_t)N * d.m_pad * sizeof(float);
+  const int row_tiles = (N + kTileRows - 1) / kTileRows;
+  L.col_tiles = (d.m_pad + kTileCols - 1) / kTileCols;
+  int P = row_tiles * L.col_tiles;
+  const int p0 = slista::bwd0_blocks(N, d.m_pad);
+  L.P = P > p0 ? P : p0;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  L.C = take(L.zbytes);
+  L.xsq = take((size_t)N * sizeof(double));
+  L.Fd = take((size_t)N * sizeof(double));
+  L.fpart = take((size_t)L.col_tiles * N * sizeof(double));
+  if (k == 0) {
+    L.pp = take(2 * L.zbytes);
+  } else {
+    L.nckpt = (T + k - 1) / k;
+    L.nseg = k - 1;
+    L.ckpt = take((size_t)L.nckpt * L.zbytes);
+    L.seg = take((size_t)L.nseg * L.zbytes);
+    L.vbuf = take(2 * L.zbytes);
+    L.dpart = take((size_t)T * L.P * sizeof(double));
+  }
+  L.total = off;
+  return L;
+}
+
+struct Run {
+  const slista::Dict* d;
+  Layout L;
+  char* ws;
+  int N, T;
+  hipStream_t s;
+
+  float* C() const { return (float*)(ws + L.C); }
+  double* xsq() const { return (double*)(ws + L.xsq); }
+  double* Fd() const { return (double*)(ws + L.Fd); }
+  double* fpart() const { return (double*)(ws + L.fpart); }
+  double* dpart() const { return (double*)(ws + L.dpart); }
+  float* vbuf(int i) const { return (float*)(ws + L.vbuf + (size_t)(i & 1) * L.zbytes); }
+  // Where z^(t), t >= 1, lives.
+  float* slot(int t) const {
+    if (L.k == 0) return (float*)(ws + L.pp + (size_t)(t & 1) * L.zbytes);
+    if (t % L.k == 0 || t == T) return (float*)(ws + L.ckpt + (size_t)((t + L.k - 1) / L.k - 1) * L.zbytes);
+    return (float*)(ws + L.seg + (size_t)(t % L.k - 1) * L.zbytes);
+  }
+};
+
+slista::GemmArgs base_args(const Run& r, const float* alpha, float lam) {
+  slista::GemmArgs g;
+  std::memset(&g, 0, sizeof g);
+  g.rows = r.N;
+  g.ncols = r.d->m_pad;
+  g.K = r.d->m_pad;
+  g.lda = r.d->m_pad;
+  g.ldb = r.d->m_pad;
+  g.ldz = r.d->m_pad;
+  g.alpha = alpha;
+  g.lam = lam;
+  g.C = r.C();
+  g.m = r.d->m;
+  slista::gemm_grid(r.N, r.d->m_pad, g);
+  return g;
+}
+
+const void* gram_for(const slista::Dict& d, int prec) {
+  return prec == slista::kF32 ? (const void*)d.G32 : (const void*)d.Gb;
+}
+
+// One forward layer t >= 1: z^(t+1) from z^(t).
+int fwd_layer(const Run& r, int prec, const float* alpha, float lam, int t, double* fpart) {
+  slista::GemmArgs g = base_args(r, alpha, lam);
+  g.A = r.slot(t);
+  g.Bt = gram_for(*r.d, prec);
+  g.t = t;
+  g.Zt = r.slot(t);
+  g.Out = r.slot(t + 1);
+  g.fpart = fpart;
+  LAUNCH(kKFwd, r.s, slista::launch_gemm(prec, slista::kEpiFwd, false, g, r.s));
+  return SLISTA_OK;
+}
+
+int prep(const Run& r, const float* X) {
+  slista::GemmArgs g;
+  std::memset(&g, 0, sizeof g);
+  g.A = X;
+  g.lda = r.d->n;
+  g.Bt = r.d->Dt;
+  g.ldb = r.d->n;
+  g.rows = r.N;
+  g.ncols = r.d->m_pad;
+  g.K = r.d->n;
+  g.Out = r.C();
+  g.ldz = r.d->m_pad;
+  slista::gemm_grid(r.N, r.d->m_pad, g);
+  LAUNCH(kKCorr, r.s, slista::launch_gemm(slista::kF32, slista::kEpiCorr, true, g, r.s));
+  LAUNCH(kKOther, r.s, slista::launch_xsq(X, r.N, r.d->n, r.xsq(), r.s));
+  return SLISTA_OK;
+}
+
+int check_common(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha, int T,
+                 int prec, int ckpt_every, void* ws, size_t ws_bytes, size_t* need) {
+  if (!dict) return fail(SLISTA_EINVAL, "dict is NULL");
+  if (N < 0 || N > kMaxN) return fail(SLISTA_EINVAL, "N=%d outside [0, %d]", N, kMaxN);
+  if (T < 0 || T > kMaxT) return fail(SLISTA_EINVAL, "T=%d outside [0, %d]", T, kMaxT);
+  if (!(lambda > 0.f) || !std::isfinite(lambda))
+    return fail(SLISTA_EINVAL, "lambda=%g must be finite and > 0", (double)lambda);
+  if (prec != SLISTA_FP32 && prec != SLISTA_BF16) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
+  if (ckpt_every < 0 || ckpt_every > kMaxT)
+    return fail(SLISTA_EINVAL, "ckpt_every=%d outside [0, %d]", ckpt_every, kMaxT);
+  if (N > 0 && !X) return fail(SLISTA_EINVAL, "X is NULL");
+  if (T > 0 && !alpha) return fail(SLISTA_EINVAL, "alpha is NULL");
+  const Layout L = make_layout(dict->d, N, T, ckpt_every);
+  *need = L.total;
+  if (L.total > 0) {
+    if (!ws) return fail(SLISTA_EINVAL, "workspace is NULL (%zu bytes needed)", L.total);
+    if (((uintptr_t)ws & 255) != 0) return fail(SLISTA_EINVAL, "workspace not 256-byte aligned");
+    if (ws_bytes < L.total)
+      return fail(SLISTA_EINVAL, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+  }
+  return SLISTA_OK;
+}
+
+// Forward pass into the workspace. want_final: evaluate F(z^T) here (else
+// the caller's seed contraction does it).
+int run_forward(const Run& r, const float* X, float lam, const float* alpha, int prec, float* Z, float* F,
+                int f_trace, float* loss, bool want_final) {
+  const int N = r.N, T = r.T, mp = r.d->m_pad;
+  int st;
+  if ((st = prep(r, X)) != SLISTA_OK) return st;
+  const bool want_f = (F != nullptr) || (loss != nullptr);
+  if (T == 0) {
+    LAUNCH(kKOther, r.s, slista::launch_fill(Z, (size_t)N * r.d->m, 0.f, r.s));
+    if (want_f) {
+      LAUNCH(kKOther, r.s, slista::launch_reduce_f(r.xsq(), r.fpart(), 0, N, F, r.Fd(), r.s));
+      if (loss) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
+    }
+    return SLISTA_OK;
+  }
+  if (F && f_trace) LAUNCH(kKOther, r.s, slista::launch_reduce_f(r.xsq(), r.fpart(), 0, N, F, nullptr, r.s));
+  LAUNCH(kKOther, r.s, slista::launch_layer0(r.C(), N, mp, alpha, lam, r.slot(1), r.s));
+  for (int t = 1; t < T; ++t) {
+    const bool tr = F && f_trace;
+    if ((st = fwd_layer(r, prec, alpha, lam, t, tr ? r.fpart() : nullptr)) != SLISTA_OK) return st;
+    if (tr) LAUNCH(kKOther, r.s, slista::launch_reduce_f(r.xsq(), r.fpart(), r.L.col_tiles, N, F + (size_t)t * N, nullptr, r.s));
+  }
+  LAUNCH(kKOther, r.s, slista::launch_copy_out(r.slot(T), N, mp, r.d->m, Z, r.s));
+  if (want_f && want_final) {
+    slista::GemmArgs g = base_args(r, alpha, lam);
+    g.A = r.slot(T);
+    g.Bt = gram_for(*r.d, prec);
+    g.t = T - 1;
+    g.Zt = r.slot(T);
+    g.fpart = r.fpart();
+    LAUNCH(kKFinal, r.s, slista::launch_gemm(prec, slista::kEpiFinal, false, g, r.s));
+    float* Fout = F ? (f_trace ? F + (size_t)T * N : F) : nullptr;
+    LAUNCH(kKOther, r.s, slista::launch_reduce_f(r.xsq(), r.fpart(), r.L.col_tiles, N, Fout, r.Fd(), r.s));
+    if (loss) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
+  }
+  return SLISTA_OK;
+}
+
+// Reverse pass over a workspace holding the forward tape. If seed_fpart, the
+// seed contraction also produces F(z^T) (into F / loss).
+int run_backward(const Run& r, float lam, const float* alpha, int prec, const float* dZ, const float* dF,
+                 float dF_scalar, float* dalpha, bool seed_fpart, float* F, float* loss) {
+  const int N = r.N, T = r.T, k = r.L.k;
+  if (T == 0) return SLISTA_OK;
+  int st;
+  {
+    slista::GemmArgs g = base_args(r, alpha, lam);
+    g.A = r.slot(T);
+    g.Bt = gram_for(*r.d, prec);
+    g.t = T - 1;
+    g.Zt = r.slot(T);
+    g.Out = r.vbuf(T - 1);
+    g.dF = dF;
+    g.dF_scalar = dF_scalar;
+    g.dZ = dZ;
+    g.fpart = seed_fpart ? r.fpart() : nullptr;
+    LAUNCH(kKSeed, r.s, slista::launch_gemm(prec, slista::kEpiSeed, false, g, r.s));
+    if (seed_fpart) {
+      LAUNCH(kKOther, r.s, slista::launch_reduce_f(r.xsq(), r.fpart(), r.L.col_tiles, N, F, r.Fd(), r.s));
+      if (loss) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
+    }
+  }
+  const int nseg = (T + k - 1) / k;
+  for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+    const int a = sgi * k;
+    const int b = (a + k < T) ? a + k : T;
+    // Recompute the interior z^(a+1) .. z^(b-1) unless the forward left it.
+    if (sgi != nseg - 1) {
+      for (int t = a + 1; t < b; ++t) {
+        if (t == 1)
+          LAUNCH(kKOther, r.s, slista::launch_layer0(r.C(), N, r.d->m_pad, alpha, lam, r.slot(1), r.s));
+        else if ((st = fwd_layer(r, prec, alpha, lam, t - 1, nullptr)) != SLISTA_OK)
+          return st;
+      }
+    }
+    for (int t = b - 1; t >= a; --t) {
+      double* dp = r.dpart() + (size_t)t * r.L.P;
+      if (t == 0) {
+        LAUNCH(kKOther, r.s, slista::launch_bwd0(r.vbuf(0), r.slot(1), N, r.d->m_pad, dp, slista::bwd0_blocks(N, r.d->m_pad), r.s));
+      } else {
+        slista::GemmArgs g = base_args(r, alpha, lam);
+        g.A = r.vbuf(t);
+        g.Vin = r.vbuf(t);
+        g.Bt = gram_for(*r.d, prec);
+        g.t = t;
+        g.Zt = r.slot(t);
+        g.Zt1 = r.slot(t + 1);
+        g.Out = r.vbuf(t - 1);
+        g.dpart = dp;
+        LAUNCH(kKBwd, r.s, slista::launch_gemm(prec, slista::kEpiBwd, false, g, r.s));
+      }
+    }
+  }
+  // Layer 0 wrote bwd0_blocks partials, every other layer one per tile.
+  slista::GemmArgs g = base_args(r, alpha, lam);
+  LAUNCH(kKOther, r.s, slista::launch_reduce_dalpha(r.dpart(), T, r.L.P, slista::bwd0_blocks(N, r.d->m_pad),
+                                       g.row_tiles * g.col_tiles, alpha, dalpha, r.s));
+  return SLISTA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int slista_abi_version(void) { return SLISTA_ABI_VERSION; }
+
+int slista_profile_begin(void) {
+  g_prof.on = true;
+  g_prof.recs.clear();
+  g_prof.dropped = 0;
+  return SLISTA_OK;
+}
+
+int slista_profile_end(int* launches, double* total_ms, int* dropped) {
+  if (!launches || !total_ms) return fail(SLISTA_EINVAL, "launches or total_ms is NULL");
+  g_prof.on = false;
+  for (int k = 0; k < SLISTA_PROFILE_KINDS; ++k) {
+    launches[k] = 0;
+    total_ms[k] = 0.0;
+  }
+  for (const auto& r : g_prof.recs) {
+    HIP_TRY(hipEventSynchronize(g_prof.pool[r.second + 1]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, g_prof.pool[r.second], g_prof.pool[r.second + 1]));
+    launches[r.first] += 1;
+    total_ms[r.first] += ms;
+  }
+  if (dropped) *dropped = g_prof.dropped;
+  g_prof.recs.clear();
+  return SLISTA_OK;
+}
+
+const char* slista_status_string(int status) {
+  switch (status) {
+    case SLISTA_OK: return "ok";
+    case SLISTA_EINVAL: return "invalid argument";
+    case SLISTA_ENOMEM: return "device allocation failed";
+    case SLISTA_EHIP: return "HIP runtime error";
+    case SLISTA_ENOTSUP: return "not supported";
+    case SLISTA_ENOTCONV: return "power iteration did not converge";
+    default: return "unknown status";
+  }
+}
+
+const char* slista_last_error(void) { return g_last_error.c_str(); }
+
+int slista_dict_create(const float* D, int n, int m, void* stream, slista_dict** out) {
+  if (!out) return fail(SLISTA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!D) return fail(SLISTA_EINVAL, "D is NULL");
+  if (n < 1 || n > kMaxn) return fail(SLISTA_EINVAL, "n=%d outside [1, %d]", n, kMaxn);
+  if (m < 1 || m > kMaxM) return fail(SLISTA_EINVAL, "m=%d outside [1, %d]", m, kMaxM);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(SLISTA_ENOTSUP, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+  hipStream_t s = (hipStream_t)stream;
+  slista_dict* h = new (std::nothrow) slista_dict;
+  if (!h) return fail(SLISTA_ENOMEM, "host allocation failed");
+  slista::Dict& d = h->d;
+  d.n = n;
+  d.m = m;
+  d.m_pad = (m + slista::kPadM - 1) / slista::kPadM * slista::kPadM;
+  d.device = dev;
+  d.G32 = nullptr;
+  d.Gb = nullptr;
+  d.Dt = nullptr;
+  d.pwork = nullptr;
+  const size_t mp = d.m_pad;
+  bool ok = hipMalloc(&d.G32, mp * mp * sizeof(float)) == hipSuccess &&
+            hipMalloc(&d.Gb, mp * mp * sizeof(uint16_t)) == hipSuccess &&
+            hipMalloc(&d.Dt, mp * (size_t)n * sizeof(float)) == hipSuccess &&
+            hipMalloc(&d.pwork, (2 * mp + 4) * sizeof(double)) == hipSuccess;
+  if (!ok) {
+    hipFree(d.G32);
+    hipFree(d.Gb);
+    hipFree(d.Dt);
+    hipFree(d.pwork);
+    delete h;
+    (void)hipGetLastError();
+    return fail(SLISTA_ENOMEM, "hipMalloc of the Gram matrices (m_pad=%d) failed", d.m_pad);
+  }
+  hipError_t e = slista::launch_gram(D, n, m, d.m_pad, d.G32, d.Gb, d.Dt, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    slista_dict_destroy(h);
+    return fail(SLISTA_EHIP, "Gram matrix: %s", hipGetErrorString(e));
+  }
+  *out = h;
+  return SLISTA_OK;
+}
+
+int slista_dict_destroy(slista_dict* dict) {
+  if (!dict) return SLISTA_OK;
+  (void)hipDeviceSynchronize();
+  hipFree(dict->d.G32);
+  hipFree(dict->d.Gb);
+  hipFree(dict->d.Dt);
+  hipFree(dict->d.pwork);
+  delete dict;
+  return SLISTA_OK;
+}
+
+int slista_dict_dims(const slista_dict* dict, int* n, int* m, int* m_pad) {
+  if (!dict) return fail(SLISTA_EINVAL, "dict is NULL");
+  if (n) *n = dict->d.n;
+  if (m) *m = dict->d.m;
+  if (m_pad) *m_pad = dict->d.m_pad;
+  return SLISTA_OK;
+}
+
+int slista_dict_gram(const slista_dict* dict, float* G_out, void* stream) {
+  if (!dict || !G_out) return fail(SLISTA_EINVAL, "dict or G_out is NULL");
+  const slista::Dict& d = dict->d;
+  HIP_TRY(hipMemcpy2DAsync(G_out, (size_t)d.m * sizeof(float), d.G32, (size_t)d.m_pad * sizeof(float),
+                           (size_t)d.m * sizeof(float), d.m, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return SLISTA_OK;
+}
+
+int slista_dict_lipschitz(slista_dict* dict, int max_iter, double rtol, double* L_out, int* iters,
+                          void* stream) {
+  if (!dict || !L_out) return fail(SLISTA_EINVAL, "dict or L_out is NULL");
+  if (max_iter < 1 || max_iter > 10000000) return fail(SLISTA_EINVAL, "max_iter=%d outside [1, 1e7]", max_iter);
+  if (!(rtol >= 0.0) || !std::isfinite(rtol)) return fail(SLISTA_EINVAL, "rtol must be finite and >= 0");
+  slista::Dict& d = dict->d;
+  hipStream_t s = (hipStream_t)stream;
+  LAUNCH(kKOther, s, slista::launch_power(d.G32, d.m, d.m_pad, max_iter, rtol, d.pwork, s));
+  double res[3];
+  HIP_TRY(hipMemcpyAsync(res, d.pwork + 2 * (size_t)d.m_pad, sizeof res, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *L_out = res[0];
+  if (iters) *iters = (int)res[1];
+  if (res[2] == 0.0) return fail(SLISTA_ENOTCONV, "power iteration: %d iterations without rtol=%g", (int)res[1], rtol);
+  return SLISTA_OK;
+}
+
+int slista_workspace_size(const slista_dict* dict, int N, int T, int prec, int ckpt_every, size_t* bytes) {
+  if (!dict || !bytes) return fail(SLISTA_EINVAL, "dict or bytes is NULL");
+  if (N < 0 || N > kMaxN || T < 0 || T > kMaxT || ckpt_every < 0 || ckpt_every > kMaxT)
+    return fail(SLISTA_EINVAL, "sizes out of range");
+  if (prec != SLISTA_FP32 && prec != SLISTA_BF16) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
+  *bytes = make_layout(dict->d, N, T, ckpt_every).total;
+  return SLISTA_OK;
+}
+
+int slista_forward(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha, int T,
+                   int prec, float* Z, float* F, int f_trace, float* loss, int ckpt_every, void* ws,
+                   size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  int st = check_common(dict, X, N, lambda, alpha, T, prec, ckpt_every, ws, ws_bytes, &need);
+  if (st != SLISTA_OK) return st;
+  if (N > 0 && !Z) return fail(SLISTA_EINVAL, "Z is NULL");
+  if (loss && N == 0) {
+    LAUNCH(kKOther, (hipStream_t)stream, slista::launch_fill(loss, 1, 0.f, (hipStream_t)stream));
+    return SLISTA_OK;
+  }
+  if (N == 0) return SLISTA_OK;
+  Run r{&dict->d, make_layout(dict->d, N, T, ckpt_every), (char*)ws, N, T, (hipStream_t)stream};
+  return run_forward(r, X, lambda, alpha, prec, Z, F, f_trace, loss, true);
+}
+
+int slista_backward(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha, int T,
+                    int prec, const float* dZ, const float* dF, float* dalpha, int ckpt_every, void* ws,
+                    size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  int st = check_common(dict, X, N, lambda, alpha, T, prec, ckpt_every, ws, ws_bytes, &need);
+  if (st != SLISTA_OK) return st;
+  if (ckpt_every < 1) return fail(SLISTA_EINVAL, "backward needs the tape of a forward with ckpt_every >= 1");
+  if (!dZ && !dF) return fail(SLISTA_EINVAL, "dZ and dF are both NULL");
+  if (T > 0 && !dalpha) return fail(SLISTA_EINVAL, "dalpha is NULL");
+  if (T == 0) return SLISTA_OK;
+  if (N == 0) {
+    LAUNCH(kKOther, (hipStream_t)stream, slista::launch_fill(dalpha, T, 0.f, (hipStream_t)stream));
+    return SLISTA_OK;
+  }
+  Run r{&dict->d, make_layout(dict->d, N, T, ckpt_every), (char*)ws, N, T, (hipStream_t)stream};
+  return run_backward(r, lambda, alpha, prec, dZ, dF, 0.f, dalpha, false, nullptr, nullptr);
+}
+
+int slista_forward_backward(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha,
+                            int T, int prec, float* Z, float* F, float* loss, float* dalpha, int ckpt_every,
+                            void* ws, size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  int st = check_common(dict, X, N, lambda, alpha, T, prec, ckpt_every, ws, ws_bytes, &need);
+  if (st != SLISTA_OK) return st;
+  if (ckpt_every < 1) return fail(SLISTA_EINVAL, "forward_backward needs ckpt_every >= 1");
+  if (N > 0 && !Z) return fail(SLISTA_EINVAL, "Z is NULL");
+  if (T > 0 && !dalpha) return fail(SLISTA_EINVAL, "dalpha is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if (N == 0) {
+    if (T > 0) LAUNCH(kKOther, s, slista::launch_fill(dalpha, T, 0.f, s));
+    if (loss) LAUNCH(kKOther, s, slista::launch_fill(loss, 1, 0.f, s));
+    return SLISTA_OK;
+  }
+  Run r{&dict->d, make_layout(dict->d, N, T, ckpt_every), (char*)ws, N, T, s};
+  if (T == 0) return run_forward(r, X, lambda, alpha, prec, Z, F, 0, loss, true);
+  if ((st = run_forward(r, X, lambda, alpha, prec, Z, nullptr, 0, nullptr, false)) != SLISTA_OK) return st;
+  return run_backward(r, lambda, alpha, prec, nullptr, nullptr, (float)(1.0 / N), dalpha, F || loss, F, loss);
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Internal definitions shared by the HIP translation units of libslista.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace slista {
+
+// m is zero-padded to a multiple of kPadM inside the library (Gram matrices,
+// correlations, iterates); padded coordinates stay exactly 0 in every layer
+// because their rows and columns of G and their correlations are 0.
+constexpr int kPadM = 64;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+enum Prec : int { kF32 = 0, kBF16 = 1 };
+
+// Epilogues fused behind the contraction P = A * B^T (B^T stored K-contiguous).
+enum Epi : int {
+  kEpiCorr = 0,   // C = X D: store P                                   (prep)
+  kEpiFwd = 1,    // z^{t+1} = ST(z^t - a (P - c), lam a); F(z^t) partial  (one layer)
+  kEpiFinal = 2,  // F(z^T) partial only                                 (objective)
+  kEpiSeed = 3,   // v^{T-1} = [z^T != 0] (dF (P - c + lam sign z^T) + dZ)  (backward seed)
+  kEpiBwd = 4     // dalpha_t partial; v^{t-1} = [z^t != 0] (v^t - a P)  (one layer back)
+};
+
+struct Dict {
+  int n, m, m_pad;
+  int device;
+  float* G32;      // [m_pad][m_pad] FP32 Gram matrix, zero padded
+  uint16_t* Gb;    // [m_pad][m_pad] BF16 copy (bit pattern), zero padded
+  float* Dt;       // [m_pad][n]     D^T, zero rows for j >= m
+  double* pwork;   // power iteration scratch: [2 * m_pad + 4]
+};
+
+// Arguments of one fused contraction launch. All matrices row-major.
+struct GemmArgs {
+  const float* A;     // [rows][lda] FP32 (rounded to BF16 while staging in BF16 mode)
+  const void* Bt;     // [ncols][ldb] FP32 or BF16: row j holds B[:, j]
+  int lda, ldb;
+  int rows;           // valid rows of A / output (N)
+  int ncols;          // valid output columns (rows of Bt)
+  int K;              // contraction length
+  int row_tiles, col_tiles, tiles_per_xcd;
+  // epilogue
+  const float* alpha; // device step sizes; alpha[t]
+  int t;
+  float lam;
+  const float* C;     // [rows][ldz] correlations c = D^T x
+  const float* Zt;    // [rows][ldz] z^t   (kEpiFwd, kEpiFinal, kEpiSeed, kEpiBwd)
+  const float* Zt1;   // [rows][ldz] z^{t+1} (kEpiBwd)
+  const float* Vin;   // [rows][ldz] v^t (kEpiBwd; FP32 copy of the A operand)
+  float* Out;         // [rows][ldz] output
+  int ldz;
+  double* fpart;      // [col_tiles][rows] objective partial sums, or null
+  double* dpart;      // [row_tiles * col_tiles] dalpha partial sums (kEpiBwd)
+  const float* dF;    // [rows] seed weights, or null -> dF_scalar
+  float dF_scalar;
+  const float* dZ;    // [rows][m] upstream gradient of z^T, or null
+  int m;
+};
+
+// Launchers (kernels_gemm.hip)
+hipError_t launch_gemm(int prec, int epi, bool safe, const GemmArgs& a, hipStream_t s);
+void gemm_grid(int rows, int ncols, GemmArgs& a);  // fills the tile counts
+
+// Launchers (kernels_misc.hip)
+hipError_t launch_gram(const float* D, int n, int m, int m_pad, float* G32, uint16_t* Gb, float* Dt,
+                       hipStream_t s);
+hipError_t launch_power(const float* G32, int m, int m_pad, int max_iter, double rtol, double* work,
+                        hipStream_t s);
+hipError_t launch_xsq(const float* X, int N, int n, double* xsq, hipStream_t s);
+hipError_t launch_layer0(const float* C, int N, int ldz, const float* alpha, float lam, float* Z1,
+                         hipStream_t s);
+hipError_t launch_copy_out(const float* Zs, int N, int ldz, int m, float* Z, hipStream_t s);
+hipError_t launch_fill(float* p, size_t count, float v, hipStream_t s);
+hipError_t launch_reduce_f(const double* xsq, const double* fpart, int col_tiles, int N, float* F,
+                           double* Fd, hipStream_t s);
+hipError_t launch_reduce_loss(const double* Fd, int N, float* loss, hipStream_t s);
+hipError_t launch_bwd0(const float* V0, const float* Z1, int N, int ldz, double* dpart, int nblocks,
+                       hipStream_t s);
+hipError_t launch_reduce_dalpha(const double* dpart, int T, int P, int count0, int count, const float* alpha,
+                                float* dalpha, hipStream_t s);
+int bwd0_blocks(int N, int ldz);
+
+}  // namespace slista

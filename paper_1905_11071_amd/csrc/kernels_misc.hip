@@ -1,0 +1,292 @@
+// Preparation, elementwise and reduction kernels around the fused layer
+// contraction: Gram matrix, power iteration for L, ||x||^2, the first layer
+// (z^(0) = 0 makes it elementwise), the copy of z^(T) to the caller's
+// layout, and the fixed-order reductions of the objective and of
+// d loss / d alpha.
+//
+// Every reduction runs in a fixed order that depends only on the sizes, so
+// results are bitwise reproducible run to run; no floating-point atomics.
+#include "common.hpp"
+
+namespace slista {
+namespace {
+
+constexpr int kRedThreads = 256;
+
+// Fixed-order block reduction of one double per thread (tree over LDS).
+__device__ double block_sum(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// G = D^T D accumulated in FP64, rounded to FP32 and BF16; D^T stored
+// K-contiguous for the correlation product. One thread per entry of G.
+__global__ void k_gram(const float* __restrict__ D, int n, int m, int mp, float* __restrict__ G32,
+                       uint16_t* __restrict__ Gb) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= mp) return;
+  double s = 0.0;
+  if (i < m && j < m)
+    for (int k = 0; k < n; ++k) s += (double)D[(size_t)k * m + i] * (double)D[(size_t)k * m + j];
+  const float f = (float)s;
+  G32[(size_t)i * mp + j] = f;
+  Gb[(size_t)i * mp + j] = __builtin_bit_cast(uint16_t, (__bf16)f);
+}
+
+__global__ void k_transpose(const float* __restrict__ D, int n, int m, int mp, float* __restrict__ Dt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (k >= n) return;
+  Dt[(size_t)j * n + k] = j < m ? D[(size_t)k * m + j] : 0.f;
+}
+
+// Deterministic start vector in [0.5, 1.5): an integer hash of the index.
+__device__ double start_value(int j) {
+  uint32_t h = (uint32_t)j * 2654435761u + 0x9e3779b9u;
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  return 0.5 + (double)(h & 0xffffff) / 16777216.0;
+}
+
+// Power iteration for the top eigenvalue of G (FP64 arithmetic on the FP32
+// entries), one workgroup of 1024 threads. v and w live in `work`:
+// work[0 .. mp) = v, work[mp .. 2mp) = w, work[2mp] = L, work[2mp+1] = iters,
+// work[2mp+2] = converged flag. Stops when successive Rayleigh quotients
+// agree to rtol.
+__global__ __launch_bounds__(1024) void k_power(const float* __restrict__ G, int m, int mp,
+                                                int max_iter, double rtol, double* work) {
+  __shared__ double sh[1024];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  double* v = work;
+  double* w = work + mp;
+  double nrm = 0.0;
+  for (int j = tid; j < m; j += blockDim.x) nrm += start_value(j) * start_value(j);
+  nrm = sqrt(block_sum(nrm, sh));
+  for (int j = tid; j < mp; j += blockDim.x) v[j] = j < m ? start_value(j) / nrm : 0.0;
+  __syncthreads();
+  double prev = 0.0, rq = 0.0;
+  int it = 0, conv = 0;
+  while (it < max_iter) {
+    ++it;
+    for (int i = wave; i < m; i += nwaves) {
+      double s = 0.0;
+      for (int j = lane; j < m; j += 64) s += (double)G[(size_t)i * mp + j] * v[j];
+      for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+      if (lane == 0) w[i] = s;
+    }
+    __threadfence_block();
+    __syncthreads();
+    double pr = 0.0, pw = 0.0;
+    for (int j = tid; j < m; j += blockDim.x) {
+      pr += v[j] * w[j];
+      pw += w[j] * w[j];
+    }
+    rq = block_sum(pr, sh);
+    const double nw = sqrt(block_sum(pw, sh));
+    if (nw == 0.0) break;
+    for (int j = tid; j < m; j += blockDim.x) v[j] = w[j] / nw;
+    __threadfence_block();
+    __syncthreads();
+    if (it > 1 && fabs(rq - prev) <= rtol * fabs(rq)) {
+      conv = 1;
+      break;
+    }
+    prev = rq;
+  }
+  if (tid == 0) {
+    work[2 * mp] = rq;
+    work[2 * mp + 1] = (double)it;
+    work[2 * mp + 2] = (double)conv;
+  }
+}
+
+// ||x_i||^2 in FP64, one wave per sample.
+__global__ void k_xsq(const float* __restrict__ X, int N, int n, double* __restrict__ xsq) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= N) return;
+  double s = 0.0;
+  for (int k = lane; k < n; k += 64) {
+    const double x = X[(size_t)i * n + k];
+    s += x * x;
+  }
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) xsq[i] = s;
+}
+
+// First layer from z^(0) = 0: the product vanishes, so
+// z^(1) = ST(0 - a (0 - c), lam a) with the same FP32 operation order as the
+// fused layer epilogue.
+__global__ void k_layer0(const float4* __restrict__ C, size_t n4, const float* __restrict__ alpha,
+                         float lam, float4* __restrict__ Z1) {
+  const float a = alpha[0], th = lam * a;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const float4 c = C[i];
+    float4 z;
+    float u;
+    u = 0.f - a * (0.f - c.x); z.x = fabsf(u) - th > 0.f ? copysignf(fabsf(u) - th, u) : 0.f;
+    u = 0.f - a * (0.f - c.y); z.y = fabsf(u) - th > 0.f ? copysignf(fabsf(u) - th, u) : 0.f;
+    u = 0.f - a * (0.f - c.z); z.z = fabsf(u) - th > 0.f ? copysignf(fabsf(u) - th, u) : 0.f;
+    u = 0.f - a * (0.f - c.w); z.w = fabsf(u) - th > 0.f ? copysignf(fabsf(u) - th, u) : 0.f;
+    Z1[i] = z;
+  }
+}
+
+__global__ void k_copy_out(const float* __restrict__ Zs, int N, int ldz, int m, float* __restrict__ Z) {
+  const size_t total = (size_t)N * m;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = e / m, j = e - i * m;
+    Z[e] = Zs[i * ldz + j];
+  }
+}
+
+__global__ void k_fill(float* __restrict__ p, size_t count, float v) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count;
+       e += (size_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+// F_i = 1/2 ||x_i||^2 + sum over column tiles of the fused partials
+// (1/2 z.Gz - z.c + lam |z|), i.e. Eq. (1) in Gram form.
+__global__ void k_reduce_f(const double* __restrict__ xsq, const double* __restrict__ fpart,
+                           int col_tiles, int N, float* __restrict__ F, double* __restrict__ Fd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double s = 0.5 * xsq[i];
+  for (int c = 0; c < col_tiles; ++c) s += fpart[(size_t)c * N + i];
+  if (F) F[i] = (float)s;
+  if (Fd) Fd[i] = s;
+}
+
+__global__ void k_reduce_loss(const double* __restrict__ Fd, int N, float* __restrict__ loss) {
+  __shared__ double sh[kRedThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) s += Fd[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) *loss = N > 0 ? (float)(s / N) : 0.f;
+}
+
+// Layer 0 of the adjoint: z^(0) = 0, so the partial is sum v^0 (0 - z^(1)).
+__global__ void k_bwd0(const float* __restrict__ V0, const float* __restrict__ Z1, size_t total,
+                       double* __restrict__ dpart) {
+  __shared__ double sh[kRedThreads];
+  double s = 0.0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x)
+    s += (double)V0[e] * (0.0 - (double)Z1[e]);
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) dpart[blockIdx.x] = s;
+}
+
+// dalpha_t = -(1/alpha_t) sum_p dpart[t][p]: on the active set,
+// z^t - z^{t+1} = alpha_t (G z^t - c + lam sign u), so this equals
+// -sum v (G z^t - c + lam sign u), the derivative of the layer output in a_t.
+__global__ void k_reduce_dalpha(const double* __restrict__ dpart, int P, int count0, int count,
+                                const float* __restrict__ alpha, float* __restrict__ dalpha) {
+  __shared__ double sh[kRedThreads];
+  const int t = blockIdx.x;
+  const int n = t == 0 ? count0 : count;
+  double s = 0.0;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) s += dpart[(size_t)t * P + p];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) dalpha[t] = (float)(-s / (double)alpha[t]);
+}
+
+int grid_for(size_t work, int per_block) {
+  size_t b = (work + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > 16384) b = 16384;
+  return (int)b;
+}
+
+}  // namespace
+
+hipError_t launch_gram(const float* D, int n, int m, int mp, float* G32, uint16_t* Gb, float* Dt,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_gram, dim3((mp + 255) / 256, mp), dim3(256), 0, s, D, n, m, mp, G32, Gb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_transpose, dim3((n + 255) / 256, mp), dim3(256), 0, s, D, n, m, mp, Dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_power(const float* G32, int m, int mp, int max_iter, double rtol, double* work,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_power, dim3(1), dim3(1024), 0, s, G32, m, mp, max_iter, rtol, work);
+  return hipGetLastError();
+}
+
+hipError_t launch_xsq(const float* X, int N, int n, double* xsq, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_xsq, dim3((N + 3) / 4), dim3(256), 0, s, X, N, n, xsq);
+  return hipGetLastError();
+}
+
+hipError_t launch_layer0(const float* C, int N, int ldz, const float* alpha, float lam, float* Z1,
+                         hipStream_t s) {
+  const size_t n4 = (size_t)N * ldz / 4;
+  if (n4 == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_layer0, dim3(grid_for(n4, 256 * 4)), dim3(256), 0, s, (const float4*)C, n4,
+                     alpha, lam, (float4*)Z1);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_out(const float* Zs, int N, int ldz, int m, float* Z, hipStream_t s) {
+  const size_t total = (size_t)N * m;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_out, dim3(grid_for(total, 256 * 8)), dim3(256), 0, s, Zs, N, ldz, m, Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, size_t count, float v, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(count, 256 * 8)), dim3(256), 0, s, p, count, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_f(const double* xsq, const double* fpart, int col_tiles, int N, float* F,
+                           double* Fd, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_f, dim3((N + 255) / 256), dim3(256), 0, s, xsq, fpart, col_tiles, N, F, Fd);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_loss(const double* Fd, int N, float* loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(kRedThreads), 0, s, Fd, N, loss);
+  return hipGetLastError();
+}
+
+int bwd0_blocks(int N, int ldz) {
+  const size_t total = (size_t)N * ldz;
+  size_t b = (total + 256 * 16 - 1) / (256 * 16);
+  if (b < 1) b = 1;
+  if (b > 4096) b = 4096;
+  return (int)b;
+}
+
+hipError_t launch_bwd0(const float* V0, const float* Z1, int N, int ldz, double* dpart, int nblocks,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_bwd0, dim3(nblocks), dim3(kRedThreads), 0, s, V0, Z1, (size_t)N * ldz, dpart);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_dalpha(const double* dpart, int T, int P, int count0, int count, const float* alpha,
+                                float* dalpha, hipStream_t s) {
+  if (T == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_dalpha, dim3(T), dim3(kRedThreads), 0, s, dpart, P, count0, count, alpha, dalpha);
+  return hipGetLastError();
+}
+
+}  // namespace slista

@@ -1,0 +1,210 @@
+"""PyTorch binding of the Step-LISTA library: argument marshalling only.
+
+Every computation runs in libslista's HIP kernels; torch provides device
+memory (the tensors and the workspace) and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+import torch
+
+from ._lib import SlistaError, check, lib  # noqa: F401
+
+PRECISIONS = {"fp32": 0, "bf16": 1}
+
+
+def _prec(prec) -> int:
+    if isinstance(prec, int):
+        return prec
+    try:
+        return PRECISIONS[prec]
+    except KeyError:
+        raise ValueError(f"precision must be one of {list(PRECISIONS)}") from None
+
+
+def _stream(device: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _dev_f32(t: torch.Tensor, name: str, shape=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.contiguous()
+
+
+class Dictionary:
+    """Per-dictionary device state: G = D^T D (FP32 and BF16) and D^T."""
+
+    def __init__(self, D: torch.Tensor):
+        D = _dev_f32(D, "D")
+        if D.dim() != 2:
+            raise ValueError("D must be [n, m]")
+        self.device = D.device
+        self.n, self.m = int(D.shape[0]), int(D.shape[1])
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().slista_dict_create(D.data_ptr(), self.n, self.m, _stream(self.device), ctypes.byref(h)))
+        self._h = h
+        mp = ctypes.c_int()
+        check(lib().slista_dict_dims(self._h, None, None, ctypes.byref(mp)))
+        self.m_pad = mp.value
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def gram(self) -> torch.Tensor:
+        G = torch.empty(self.m, self.m, device=self.device, dtype=torch.float32)
+        check(lib().slista_dict_gram(self._h, G.data_ptr(), _stream(self.device)))
+        return G
+
+    def lipschitz(self, max_iter: int = 100_000, rtol: float = 1e-13) -> Tuple[float, int]:
+        """(L, iterations): FP64 power iteration on G. Raises if rtol is not met."""
+        L = ctypes.c_double()
+        it = ctypes.c_int()
+        with torch.cuda.device(self.device):
+            check(lib().slista_dict_lipschitz(self._h, max_iter, rtol, ctypes.byref(L), ctypes.byref(it),
+                                              _stream(self.device)))
+        return L.value, it.value
+
+    def workspace_bytes(self, N: int, T: int, prec="fp32", ckpt_every: int = 0) -> int:
+        b = ctypes.c_size_t()
+        check(lib().slista_workspace_size(self._h, N, T, _prec(prec), ckpt_every, ctypes.byref(b)))
+        return b.value
+
+    def workspace(self, N: int, T: int, prec="fp32", ckpt_every: int = 0) -> torch.Tensor:
+        nbytes = self.workspace_bytes(N, T, prec, ckpt_every)
+        return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().slista_dict_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_inputs(d: Dictionary, X: torch.Tensor, alpha: torch.Tensor):
+    X = _dev_f32(X, "X")
+    if X.dim() != 2 or X.shape[1] != d.n:
+        raise ValueError(f"X must be [N, {d.n}]")
+    alpha = _dev_f32(alpha, "alpha")
+    if alpha.dim() != 1:
+        raise ValueError("alpha must be [T]")
+    return X, alpha
+
+
+def forward(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, prec="fp32",
+            f_trace: bool = False, want_f: bool = True, want_loss: bool = True, ckpt_every: int = 0,
+            ws: Optional[torch.Tensor] = None):
+    """z^(T) for every sample, plus F (per sample, or the [T+1, N] trace) and
+    the mean loss. Returns (Z, F or None, loss or None, ws)."""
+    X, alpha = _check_inputs(d, X, alpha)
+    N, T = int(X.shape[0]), int(alpha.shape[0])
+    p = _prec(prec)
+    if ws is None:
+        ws = d.workspace(N, T, p, ckpt_every)
+    Z = torch.empty(N, d.m, device=d.device, dtype=torch.float32)
+    F = None
+    if want_f:
+        F = torch.empty((T + 1, N) if f_trace else (N,), device=d.device, dtype=torch.float32)
+    loss = torch.empty(1, device=d.device, dtype=torch.float32) if want_loss else None
+    check(lib().slista_forward(d.handle, X.data_ptr(), N, float(lam), alpha.data_ptr(), T, p, Z.data_ptr(),
+                               _ptr(F), int(bool(f_trace)), _ptr(loss), ckpt_every, ws.data_ptr(), ws.numel(),
+                               _stream(d.device)))
+    return Z, F, loss, ws
+
+
+def backward(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, ws: torch.Tensor,
+             dZ: Optional[torch.Tensor] = None, dF: Optional[torch.Tensor] = None, prec="fp32",
+             ckpt_every: int = 1) -> torch.Tensor:
+    """d J / d alpha for J = sum dF_i F_i(z^T) + <dZ, Z^T>, from the tape a
+    forward() call with the same arguments left in ws."""
+    X, alpha = _check_inputs(d, X, alpha)
+    N, T = int(X.shape[0]), int(alpha.shape[0])
+    if dZ is not None:
+        dZ = _dev_f32(dZ, "dZ", (N, d.m))
+    if dF is not None:
+        dF = _dev_f32(dF, "dF", (N,))
+    dalpha = torch.empty(T, device=d.device, dtype=torch.float32)
+    check(lib().slista_backward(d.handle, X.data_ptr(), N, float(lam), alpha.data_ptr(), T, _prec(prec),
+                                _ptr(dZ), _ptr(dF), dalpha.data_ptr(), ckpt_every, ws.data_ptr(), ws.numel(),
+                                _stream(d.device)))
+    return dalpha
+
+
+def forward_backward(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, prec="fp32",
+                     ckpt_every: int = 1, ws: Optional[torch.Tensor] = None, want_f: bool = True):
+    """Forward plus d(mean F)/d alpha in one call. Returns (Z, F, loss, dalpha, ws)."""
+    X, alpha = _check_inputs(d, X, alpha)
+    N, T = int(X.shape[0]), int(alpha.shape[0])
+    p = _prec(prec)
+    if ws is None:
+        ws = d.workspace(N, T, p, ckpt_every)
+    Z = torch.empty(N, d.m, device=d.device, dtype=torch.float32)
+    F = torch.empty(N, device=d.device, dtype=torch.float32) if want_f else None
+    loss = torch.empty(1, device=d.device, dtype=torch.float32)
+    dalpha = torch.empty(T, device=d.device, dtype=torch.float32)
+    check(lib().slista_forward_backward(d.handle, X.data_ptr(), N, float(lam), alpha.data_ptr(), T, p,
+                                        Z.data_ptr(), _ptr(F), loss.data_ptr(), dalpha.data_ptr(), ckpt_every,
+                                        ws.data_ptr(), ws.numel(), _stream(d.device)))
+    return Z, F, loss, dalpha, ws
+
+
+def profile_begin() -> None:
+    """Start recording HIP-event timings of every library launch."""
+    check(lib().slista_profile_begin())
+
+
+def profile_end() -> dict:
+    """Stop recording; {kernel class: (launches, total milliseconds)}."""
+    from ._lib import PROFILE_KINDS
+    n = len(PROFILE_KINDS)
+    launches = (ctypes.c_int * n)()
+    total = (ctypes.c_double * n)()
+    dropped = ctypes.c_int()
+    check(lib().slista_profile_end(launches, total, ctypes.byref(dropped)))
+    out = {k: (launches[i], total[i]) for i, k in enumerate(PROFILE_KINDS)}
+    out["dropped"] = (dropped.value, 0.0)
+    return out
+
+
+class SlistaFunction(torch.autograd.Function):
+    """Step-LISTA as an autograd node: alpha -> (z^(T), F(z^(T))).
+
+    Only the step sizes are learned (Section 4, Step-LISTA); the backward
+    runs the library's hand-written adjoint kernels over the tape the
+    forward kept in its workspace."""
+
+    @staticmethod
+    def forward(ctx, alpha, d: Dictionary, X, lam, prec="fp32", ckpt_every=1):
+        Z, F, _, ws = forward(d, X, lam, alpha, prec=prec, want_loss=False, ckpt_every=ckpt_every)
+        ctx.save_for_backward(alpha, X)
+        ctx.d, ctx.lam, ctx.prec, ctx.ckpt, ctx.ws = d, lam, prec, ckpt_every, ws
+        return Z, F
+
+    @staticmethod
+    def backward(ctx, gZ, gF):
+        alpha, X = ctx.saved_tensors
+        dalpha = backward(ctx.d, X, ctx.lam, alpha, ctx.ws, dZ=None if gZ is None else gZ.contiguous(),
+                          dF=None if gF is None else gF.contiguous(), prec=ctx.prec, ckpt_every=ctx.ckpt)
+        return dalpha, None, None, None, None, None
+
+
+def slista(alpha: torch.Tensor, d: Dictionary, X: torch.Tensor, lam: float, prec="fp32", ckpt_every: int = 1):
+    """Differentiable Step-LISTA network: returns (Z, F) with gradients to alpha."""
+    return SlistaFunction.apply(alpha, d, X, lam, prec, ckpt_every)

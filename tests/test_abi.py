@@ -1,0 +1,74 @@
+"""The C ABI library loads and exports every symbol include/slista.h declares,
+and its host-side argument checks reject bad calls before any device work.
+CPU only: none of these calls reaches the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "slista.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"SLISTA_API\s+[\w\s\*]+?\b(slista_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1905_11071_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libslista.so is not built (run __graft_entry__.build())")
+    return _lib.lib()
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for want in ["slista_dict_create", "slista_dict_lipschitz", "slista_forward", "slista_backward",
+                 "slista_forward_backward", "slista_workspace_size"]:
+        assert want in syms
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1905_11071_amd import _lib
+    syms = declared_symbols()
+    assert syms, "no declarations parsed"
+    for s in syms:
+        assert hasattr(lib, s), f"{s} declared but not exported"
+        assert s in _lib.SIGNATURES, f"{s} has no ctypes signature in the binding"
+    assert set(_lib.SIGNATURES) == set(syms)
+
+
+def test_abi_version_and_status_strings(lib):
+    assert lib.slista_abi_version() == 1
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.slista_status_string(code)
+    assert lib.slista_status_string(12345) == b"unknown status"
+
+
+def test_null_dict_rejected(lib):
+    vp = ctypes.c_void_p
+    st = lib.slista_forward(None, vp(16), 4, 0.1, vp(16), 3, 0, vp(16), None, 0, None, 0, vp(256), 1 << 20, None)
+    assert st == -1
+    assert b"dict" in lib.slista_last_error()
+    st = lib.slista_backward(None, vp(16), 4, 0.1, vp(16), 3, 0, None, None, vp(16), 1, vp(256), 1 << 20, None)
+    assert st == -1
+
+
+def test_dict_create_rejects_bad_sizes(lib):
+    h = ctypes.c_void_p()
+    assert lib.slista_dict_create(None, 4, 8, None, ctypes.byref(h)) == -1
+    assert lib.slista_dict_create(ctypes.c_void_p(256), 0, 8, None, ctypes.byref(h)) == -1
+    assert lib.slista_dict_create(ctypes.c_void_p(256), 4, 0, None, ctypes.byref(h)) == -1
+    assert lib.slista_dict_create(ctypes.c_void_p(256), 4, 9000, None, ctypes.byref(h)) == -1
+    assert h.value is None
+    assert lib.slista_dict_destroy(None) == 0
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    import paper_1905_11071_amd as sl
+    with pytest.raises(ValueError):
+        sl.Dictionary(torch.zeros(4, 8))
