@@ -68,10 +68,12 @@ def test_gram_and_lipschitz(sl):
     d.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32"])
 def test_forward_ista_10x20_trace(sl, prec):
     """Plain ISTA on the 10x20 dictionary, N=1000, T=100, alpha = 1/L, with the
-    per-iteration objective trace."""
+    per-iteration objective trace. This workload is specified in FP64; the
+    device computes it in FP32 and is held to the FP32 tolerances (BF16
+    operands are specified for the 256x1024 precision workload, not here)."""
     cfg = synth.CONFIGS["ista_10x20"]
     pb = synth.make_problem(cfg["n"], cfg["m"], cfg["N"], cfg["p"], cfg["sigma"], cfg["lam_frac"], cfg["seed"])
     T = cfg["T"]
@@ -279,3 +281,44 @@ def test_error_paths_reach_no_kernel(sl):
     with pytest.raises(sl.SlistaError, match="EINVAL"):
         sl.backward(d, X, 0.1, a, d.workspace(70, 4, "fp32", 1), ckpt_every=1)
     d.close()
+
+
+@pytest.fixture(scope="module")
+def full_prec_problem():
+    cfg = synth.CONFIGS["prec_256x1024"]
+    pb = synth.make_problem(cfg["n"], cfg["m"], cfg["N"], cfg["p"], cfg["sigma"], cfg["lam_frac"], cfg["seed"])
+    rows = np.arange(0, pb.N, 256)      # 256 sampled rows, the same on both sides
+    return pb, cfg["T"], rows
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_full_size_256x1024(sl, full_prec_problem, prec):
+    """The benchmark's workload and launch configuration (N=65536, m=1024,
+    T=50, fused forward+backward, every iterate kept): sampled rows of z^(T)
+    against the oracle run on those rows alone (samples are independent), and
+    d alpha of the loss restricted to those rows (dF = 1/256 on them, 0
+    elsewhere) against the oracle's."""
+    pb, T, rows = full_prec_problem
+    _say(f"[{prec}] full size N={pb.N} m={pb.m} T={T}")
+    d = sl.Dictionary(_gpu(pb.D))
+    L, _ = d.lipschitz(max_iter=200_000, rtol=1e-13)
+    alpha = np.full(T, np.float32(1.0 / L), dtype=np.float64)
+    X, a = _gpu(pb.X), _gpu(alpha)
+    Z, F, loss, _, ws = sl.forward_backward(d, X, pb.lam, a, prec=prec, ckpt_every=1)
+    dF = np.zeros(pb.N)
+    dF[rows] = 1.0 / len(rows)
+    da = sl.backward(d, X, pb.lam, a, ws, dF=_gpu(dF), prec=prec, ckpt_every=1)
+    torch.cuda.synchronize()
+    Zg = Z.cpu().numpy().astype(np.float64)[rows]
+    da = da.cpu().numpy().astype(np.float64)
+    del ws
+    d.close()
+    Xs = pb.X[rows]
+    Zo, Fo, dao = oracle.forward_backward(pb.D, Xs, pb.lam, alpha, dF=np.full(len(rows), 1.0 / len(rows)))
+    zs = oracle.lasso_solution(pb.D, Xs, pb.lam)
+    rel, gg, go = mean_gap_rel_error(pb.D, Xs, pb.lam, Zg, Zo, zs)
+    derr = float(np.max(np.abs(da - dao)) / np.max(np.abs(dao)))
+    _say(f"[{prec}] 256x1024 gap gpu={gg:.4e} oracle={go:.4e} rel={rel:.2e} dalpha rel={derr:.2e} "
+         f"max|dZ|={np.max(np.abs(Zg - Zo)):.2e}")
+    assert rel <= GAP_TOL[prec]
+    assert derr <= DALPHA_TOL[prec]
