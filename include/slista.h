@@ -172,6 +172,21 @@ SLISTA_API int slista_forward_backward(const slista_dict* dict, const float* X, 
                                        size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Options (process-wide, not thread-safe; set before enqueuing work)
+ *
+ * SLISTA_OPT_KERNEL_FAMILY: which kernels run the layers.
+ *   0 (default) automatic: the persistent kernels (one workgroup carries a
+ *     tile of samples through all layers) when m_pad <= 2048, else the
+ *     per-layer kernels (one fused contraction launch per layer);
+ *   1 always the per-layer kernels;
+ *   2 the persistent kernels where they apply.
+ * Both families compute bitwise-identical iterates and step-size gradients.
+ * ------------------------------------------------------------------------- */
+#define SLISTA_OPT_KERNEL_FAMILY 1
+
+SLISTA_API int slista_set_option(int option, int value);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (diagnostics)
  *
  * While recording is on, the library brackets every launch it makes with a

@@ -12,6 +12,7 @@ from .ops import (  # noqa: F401
     forward_backward,
     profile_begin,
     profile_end,
+    set_kernel_family,
     slista,
     SlistaFunction,
 )

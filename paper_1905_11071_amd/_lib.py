@@ -38,6 +38,7 @@ SIGNATURES = {
                                  _vp, _size_t, _vp]),
     "slista_forward_backward": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _vp, _vp, _vp,
                                          _vp, _c_int, _vp, _size_t, _vp]),
+    "slista_set_option": (_c_int, [_c_int, _c_int]),
     "slista_profile_begin": (_c_int, []),
     "slista_profile_end": (_c_int, [ctypes.POINTER(_c_int), ctypes.POINTER(_c_double), ctypes.POINTER(_c_int)]),
 }

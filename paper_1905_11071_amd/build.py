@@ -23,11 +23,14 @@ HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: no v_pk_{add,mul,fma}_f32 in device code (the host pass
 # warns that it does not know the feature; that is expected).
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                # the persistent kernels unroll their column passes fully so that the
+                # master iterate stays in registers (the default limit leaves it in scratch)
+                "-mllvm", "-pragma-unroll-threshold=1000000"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-fvisibility=hidden", "-Wall", "-Wno-unused-result",
           f"-I{os.path.join(ROOT, 'include')}"]
 
-SOURCES = ["kernels_gemm.hip", "kernels_misc.hip", "api.cpp"]
+SOURCES = ["kernels_gemm.hip", "kernels_misc.hip", "kernels_persist.hip", "api.cpp"]
 
 
 def _compile(src: str) -> str:

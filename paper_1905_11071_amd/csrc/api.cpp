@@ -26,6 +26,7 @@
 
 #include "../../include/slista.h"
 #include "common.hpp"
+#include "persist.hpp"
 
 struct slista_dict {
   slista::Dict d;
@@ -96,6 +97,11 @@ struct ProfScope {
     HIP_TRY(expr);                     \
   } while (0)
 
+// Kernel family: 0 = automatic (persistent kernels when m_pad <= 2048),
+// 1 = per-layer kernels, 2 = persistent kernels (falls back to per-layer
+// where they do not apply). Set through slista_set_option.
+int g_kernel_family = 0;
+
 constexpr int kMaxN = 1 << 26;
 constexpr int kMaxT = 100000;
 constexpr int kMaxM = 8192;
@@ -120,7 +126,9 @@ Layout make_layout(const slista::Dict& d, int N, int T, int k) {
   L.col_tiles = (d.m_pad + kTileCols - 1) / kTileCols;
   int P = row_tiles * L.col_tiles;
   const int p0 = slista::bwd0_blocks(N, d.m_pad);
+  const int pt = (N + 15) / 16;  // persistent tiles have at least 16 rows
   L.P = P > p0 ? P : p0;
+  if (pt > L.P) L.P = pt;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -187,6 +195,33 @@ const void* gram_for(const slista::Dict& d, int prec) {
   return prec == slista::kF32 ? (const void*)d.G32 : (const void*)d.Gb;
 }
 
+bool use_persist(const Run& r, int prec) {
+  if (g_kernel_family == 1) return false;
+  return slista::persist_rows(prec, r.d->m_pad) > 0;
+}
+
+slista::PersistArgs persist_args(const Run& r, int prec, const float* alpha, float lam) {
+  slista::PersistArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.Gsw = prec == slista::kF32 ? (const void*)r.d->Gsf : (const void*)r.d->Gsb;
+  a.m_pad = r.d->m_pad;
+  a.KC = r.d->m_pad * (prec == slista::kF32 ? 4 : 2) / 64;
+  a.N = r.N;
+  a.m = r.d->m;
+  a.C = r.C();
+  a.alpha = alpha;
+  a.lam = lam;
+  a.ckpt = r.ws + r.L.ckpt;
+  a.seg = r.ws + r.L.seg;
+  a.zbytes = r.L.zbytes;
+  a.k = r.L.k;
+  a.T = r.T;
+  a.a_last = r.L.k > 0 && r.T > 0 ? ((r.T - 1) / r.L.k) * r.L.k : 0;
+  a.xsq = r.xsq();
+  a.P_stride = r.L.P;
+  return a;
+}
+
 // One forward layer t >= 1: z^(t+1) from z^(t).
 int fwd_layer(const Run& r, int prec, const float* alpha, float lam, int t, double* fpart) {
   slista::GemmArgs g = base_args(r, alpha, lam);
@@ -244,7 +279,7 @@ int check_common(const slista_dict* dict, const float* X, int N, float lambda, c
 // Forward pass into the workspace. want_final: evaluate F(z^T) here (else
 // the caller's seed contraction does it).
 int run_forward(const Run& r, const float* X, float lam, const float* alpha, int prec, float* Z, float* F,
-                int f_trace, float* loss, bool want_final) {
+                int f_trace, float* loss, bool want_final, float* seed_vout = nullptr, float seed_dF = 0.f) {
   const int N = r.N, T = r.T, mp = r.d->m_pad;
   int st;
   if ((st = prep(r, X)) != SLISTA_OK) return st;
@@ -255,6 +290,29 @@ int run_forward(const Run& r, const float* X, float lam, const float* alpha, int
       LAUNCH(kKOther, r.s, slista::launch_reduce_f(r.xsq(), r.fpart(), 0, N, F, r.Fd(), r.s));
       if (loss) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
     }
+    return SLISTA_OK;
+  }
+  if (use_persist(r, prec)) {
+    slista::PersistArgs a = persist_args(r, prec, alpha, lam);
+    a.t_begin = 0;
+    a.t_end = T;
+    if (want_f && want_final) {
+      a.mode |= slista::kModeF;
+      a.F = F ? (f_trace ? F + (size_t)T * N : F) : nullptr;
+      a.Fd = r.Fd();
+    }
+    if (F && f_trace) {
+      a.mode |= slista::kModeTrace;
+      a.Ftrace = F;
+    }
+    a.Zuser = Z;
+    if (seed_vout) {
+      a.mode |= slista::kModeSeed;
+      a.dF_scalar = seed_dF;
+      a.Vout = seed_vout;
+    }
+    LAUNCH(kKFwd, r.s, slista::launch_persist(true, prec, a, r.s));
+    if (loss && want_final) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
     return SLISTA_OK;
   }
   if (F && f_trace) LAUNCH(kKOther, r.s, slista::launch_reduce_f(r.xsq(), r.fpart(), 0, N, F, nullptr, r.s));
@@ -283,10 +341,50 @@ int run_forward(const Run& r, const float* X, float lam, const float* alpha, int
 // Reverse pass over a workspace holding the forward tape. If seed_fpart, the
 // seed contraction also produces F(z^T) (into F / loss).
 int run_backward(const Run& r, float lam, const float* alpha, int prec, const float* dZ, const float* dF,
-                 float dF_scalar, float* dalpha, bool seed_fpart, float* F, float* loss) {
+                 float dF_scalar, float* dalpha, bool seed_fpart, float* F, float* loss, bool seeded = false) {
   const int N = r.N, T = r.T, k = r.L.k;
   if (T == 0) return SLISTA_OK;
   int st;
+  if (use_persist(r, prec)) {
+    slista::PersistArgs a = persist_args(r, prec, alpha, lam);
+    if (!seeded) {
+      a.t_begin = a.t_end = T;
+      a.mode = slista::kModeSeed;
+      a.dF = dF;
+      a.dF_scalar = dF_scalar;
+      a.dZ = dZ;
+      a.Vout = r.vbuf(0);
+      if (seed_fpart) {
+        a.mode |= slista::kModeF;
+        a.F = F;
+        a.Fd = r.Fd();
+      }
+      LAUNCH(kKSeed, r.s, slista::launch_persist(true, prec, a, r.s));
+      if (seed_fpart && loss) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
+    }
+    const int nseg = (T + k - 1) / k;
+    for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+      const int a0 = sgi * k;
+      const int b = (a0 + k < T) ? a0 + k : T;
+      if (sgi != nseg - 1 && b - 1 > a0) {
+        slista::PersistArgs f = persist_args(r, prec, alpha, lam);
+        f.t_begin = a0;
+        f.t_end = b - 1;
+        f.store_all = 1;
+        LAUNCH(kKFwd, r.s, slista::launch_persist(true, prec, f, r.s));
+      }
+      slista::PersistArgs bw = persist_args(r, prec, alpha, lam);
+      bw.t_hi = b - 1;
+      bw.t_lo = a0;
+      bw.Vio = r.vbuf(0);
+      bw.dpart = r.dpart();
+      LAUNCH(kKBwd, r.s, slista::launch_persist(false, prec, bw, r.s));
+    }
+    const int rows = slista::persist_rows(prec, r.d->m_pad);
+    const int tiles = (N + rows - 1) / rows;
+    LAUNCH(kKOther, r.s, slista::launch_reduce_dalpha(r.dpart(), T, r.L.P, tiles, tiles, alpha, dalpha, r.s));
+    return SLISTA_OK;
+  }
   {
     slista::GemmArgs g = base_args(r, alpha, lam);
     g.A = r.slot(T);
@@ -347,6 +445,15 @@ int run_backward(const Run& r, float lam, const float* alpha, int prec, const fl
 extern "C" {
 
 int slista_abi_version(void) { return SLISTA_ABI_VERSION; }
+
+int slista_set_option(int option, int value) {
+  if (option == SLISTA_OPT_KERNEL_FAMILY) {
+    if (value < 0 || value > 2) return fail(SLISTA_EINVAL, "kernel family %d outside [0, 2]", value);
+    g_kernel_family = value;
+    return SLISTA_OK;
+  }
+  return fail(SLISTA_EINVAL, "unknown option %d", option);
+}
 
 int slista_profile_begin(void) {
   g_prof.on = true;
@@ -412,21 +519,28 @@ int slista_dict_create(const float* D, int n, int m, void* stream, slista_dict**
   d.Gb = nullptr;
   d.Dt = nullptr;
   d.pwork = nullptr;
+  d.Gsb = nullptr;
+  d.Gsf = nullptr;
   const size_t mp = d.m_pad;
   bool ok = hipMalloc(&d.G32, mp * mp * sizeof(float)) == hipSuccess &&
             hipMalloc(&d.Gb, mp * mp * sizeof(uint16_t)) == hipSuccess &&
             hipMalloc(&d.Dt, mp * (size_t)n * sizeof(float)) == hipSuccess &&
-            hipMalloc(&d.pwork, (2 * mp + 4) * sizeof(double)) == hipSuccess;
+            hipMalloc(&d.pwork, (2 * mp + 4) * sizeof(double)) == hipSuccess &&
+            hipMalloc(&d.Gsb, mp * mp * sizeof(uint16_t)) == hipSuccess &&
+            hipMalloc(&d.Gsf, mp * mp * sizeof(float)) == hipSuccess;
   if (!ok) {
     hipFree(d.G32);
     hipFree(d.Gb);
     hipFree(d.Dt);
     hipFree(d.pwork);
+    hipFree(d.Gsb);
+    hipFree(d.Gsf);
     delete h;
     (void)hipGetLastError();
     return fail(SLISTA_ENOMEM, "hipMalloc of the Gram matrices (m_pad=%d) failed", d.m_pad);
   }
   hipError_t e = slista::launch_gram(D, n, m, d.m_pad, d.G32, d.Gb, d.Dt, s);
+  if (e == hipSuccess) e = slista::launch_swizzle(d.G32, d.m_pad, d.Gsb, d.Gsf, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     slista_dict_destroy(h);
@@ -443,6 +557,8 @@ int slista_dict_destroy(slista_dict* dict) {
   hipFree(dict->d.Gb);
   hipFree(dict->d.Dt);
   hipFree(dict->d.pwork);
+  hipFree(dict->d.Gsb);
+  hipFree(dict->d.Gsf);
   delete dict;
   return SLISTA_OK;
 }
@@ -540,6 +656,12 @@ int slista_forward_backward(const slista_dict* dict, const float* X, int N, floa
   }
   Run r{&dict->d, make_layout(dict->d, N, T, ckpt_every), (char*)ws, N, T, s};
   if (T == 0) return run_forward(r, X, lambda, alpha, prec, Z, F, 0, loss, true);
+  if (use_persist(r, prec)) {
+    // one persistent launch runs the forward, F(z^T) and the seed of the mean loss
+    if ((st = run_forward(r, X, lambda, alpha, prec, Z, F, 0, loss, true, r.vbuf(0), (float)(1.0 / N))) != SLISTA_OK)
+      return st;
+    return run_backward(r, lambda, alpha, prec, nullptr, nullptr, 0.f, dalpha, false, nullptr, nullptr, true);
+  }
   if ((st = run_forward(r, X, lambda, alpha, prec, Z, nullptr, 0, nullptr, false)) != SLISTA_OK) return st;
   return run_backward(r, lambda, alpha, prec, nullptr, nullptr, (float)(1.0 / N), dalpha, F || loss, F, loss);
 }

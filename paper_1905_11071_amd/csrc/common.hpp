@@ -33,6 +33,8 @@ struct Dict {
   uint16_t* Gb;    // [m_pad][m_pad] BF16 copy (bit pattern), zero padded
   float* Dt;       // [m_pad][n]     D^T, zero rows for j >= m
   double* pwork;   // power iteration scratch: [2 * m_pad + 4]
+  uint16_t* Gsb;   // BF16 G in MFMA fragment order (persistent kernels)
+  float* Gsf;      // FP32 G in MFMA fragment order (persistent kernels)
 };
 
 // Arguments of one fused contraction launch. All matrices row-major.

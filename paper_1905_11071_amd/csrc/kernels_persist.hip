@@ -1,0 +1,467 @@
+// Persistent Step-LISTA kernels: one workgroup carries a tile of R samples
+// through a whole range of layers (Section 4, Eq. (14)), forward or back.
+//
+// On-chip state of a tile (4 wave64s, 1 workgroup per CU for the large shapes):
+//   LDS        the tile's iterate in the contraction's precision (BF16 or
+//              FP32), [R][m_pad], the A operand of P = Z G for every layer;
+//   registers  the FP32 master iterate (forward: z; backward: the adjoint v)
+//              in the MFMA accumulator layout, so the step, the threshold and
+//              the objective never re-read z from memory.
+// G streams from L2 in a fragment-ordered copy built with the dictionary:
+// the 16 x 32 (BF16) or 16 x 16 (FP32) fragment a wave needs for one K step
+// is 1 KiB contiguous, one 16-byte load per lane, issued PF steps ahead.
+// Each wave owns 64-column slabs of the output (4 slabs = one pass of 256
+// columns); the tile's rows are shared by all waves through LDS.
+//
+// Per sample and layer the forward reads c = D^T x (4 m bytes) and writes
+// the kept iterate (4 m bytes); the backward reads z^t and z^{t+1}.
+//
+// The K order, the per-lane K assignment and every epilogue expression are
+// the same as in the per-layer kernel (kernels_gemm.hip), so both give
+// bitwise-identical iterates.
+#include "common.hpp"
+#include "persist.hpp"
+
+namespace slista {
+namespace {
+
+constexpr int PT = 256;  // threads per workgroup
+constexpr int PF = 3;    // K steps of G fragments in flight
+
+template <int P> struct Elem;
+template <> struct Elem<kF32> { static constexpr int bytes = 4; };
+template <> struct Elem<kBF16> { static constexpr int bytes = 2; };
+
+__device__ __forceinline__ float soft_thresh(float u, float th) {
+  const float au = fabsf(u) - th;
+  return au > 0.f ? copysignf(au, u) : 0.f;
+}
+__device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
+
+// Raw buffer descriptors (CDNA): a uniform base and byte range in SGPRs, so
+// each access needs one per-lane VGPR offset; the row part of an offset goes
+// into the SGPR soffset and the column part into the instruction's immediate.
+constexpr int kRsrcWord3 = 0x00020000;
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, size_t bytes) {
+  const int n = bytes > 0x7fffffffu ? 0x7fffffff : (int)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, kRsrcWord3);
+}
+__device__ __forceinline__ float bload(Rsrc r, int voff, int soff) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(float v, Rsrc r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, soff, 0);
+}
+
+__device__ __forceinline__ float* slot_ptr(const PersistArgs& g, int t) {
+  const int k = g.k;
+  if (t % k == 0 || t == g.T) return (float*)(g.ckpt + (size_t)((t + k - 1) / k - 1) * g.zbytes);
+  return (float*)(g.seg + (size_t)(t % k - 1) * g.zbytes);
+}
+
+template <int P>
+__device__ __forceinline__ void mfma_pair(f32x4& acc, const uint4& a, const uint4& b) {
+  if constexpr (P == kF32) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
+  } else {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                   acc, 0, 0, 0);
+  }
+}
+
+// acc[fm][f] = sum_k A[16 fm + row][k] G[k][64 slab + 16 f + col] over the
+// whole K range, A from the LDS tile, G fragments from global memory.
+template <int P, int FM>
+__device__ __forceinline__ void contract(const PersistArgs& g, const char* lds, int rowb, int slab, int lane,
+                                         f32x4 (&acc)[FM][4]) {
+  const int lr = lane & 15, lg = lane >> 4;
+  const int KC = g.KC;
+  // the 4 * KC fragments of this slab: 4 KC KiB starting at fragment (4 slab, 0)
+  const Rsrc rg = make_rsrc((const char*)g.Gsw + (size_t)(4 * slab) * KC * 1024, (size_t)4 * KC * 1024);
+  const int lo = lane * 16;
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int f = 0; f < 4; ++f) acc[fm][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint4 bq[PF][4];
+#pragma unroll
+  for (int i = 0; i < PF - 1; ++i)
+    if (i < KC)
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+        bq[i][f] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rg, lo, (f * KC + i) * 1024, 0));
+  const char* arow = lds + lr * rowb + 16 * lg;
+  for (int kc0 = 0; kc0 < KC; kc0 += PF) {
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const int kc = kc0 + j;
+      if (kc < KC) {
+        const int nk = kc + PF - 1;
+        if (nk < KC)
+#pragma unroll
+          for (int f = 0; f < 4; ++f)
+            bq[(j + PF - 1) % PF][f] =
+                __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rg, lo, (f * KC + nk) * 1024, 0));
+        uint4 av[FM];
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm) av[fm] = *(const uint4*)(arow + fm * 16 * rowb + kc * 64);
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+          for (int f = 0; f < 4; ++f) mfma_pair<P>(acc[fm][f], av[fm], bq[j][f]);
+      }
+    }
+  }
+}
+
+// Master registers -> LDS tile (the next contraction's A operand).
+template <int P, int FM, int NP>
+__device__ __forceinline__ void master_to_lds(const float (&zm)[NP][FM][4][4], char* lds, int rowb, int npass,
+                                              int m_pad, int wave, int lane) {
+  const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int slab = 4 * p + wave;
+    if (p < npass && slab * 64 < m_pad) {
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) {
+            const int row = 16 * fm + 4 * lg + r4, col = 64 * slab + 16 * f + lr;
+            char* dst = lds + row * rowb + col * Elem<P>::bytes;
+            if constexpr (P == kF32)
+              *(float*)dst = zm[p][fm][f][r4];
+            else
+              *(__bf16*)dst = (__bf16)zm[p][fm][f][r4];
+          }
+    }
+  }
+}
+
+// Per-row objective of the tile from per-lane partials: reduce over the 16
+// lanes of a row group, then over the 4 waves (fixed order), add 1/2 ||x||^2.
+template <int FM>
+__device__ __forceinline__ void finish_rows(const float (&fs)[FM][4], float* red, int wave, int lane, int tid, int row0, int N,
+                            const double* xsq, float* Fout, double* Fd) {
+  const int lr = lane & 15, lg = lane >> 4;
+  constexpr int R = FM * 16;
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) {
+      float v = fs[fm][r4];
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
+      v += __shfl_xor(v, 4);
+      v += __shfl_xor(v, 8);
+      if (lr == 0) red[wave * R + 16 * fm + 4 * lg + r4] = v;
+    }
+  __syncthreads();
+  if (tid < R && row0 + tid < N) {
+    const double s = 0.5 * xsq[row0 + tid] + (((double)red[tid] + red[R + tid]) + red[2 * R + tid]) + red[3 * R + tid];
+    if (Fout) Fout[row0 + tid] = (float)s;
+    if (Fd) Fd[row0 + tid] = s;
+  }
+  __syncthreads();
+}
+
+// Loads the tile's [R][m_pad] FP32 rows of `src` (row stride m_pad) into the
+// master registers; rows past N read as 0.
+template <int FM, int NP>
+__device__ __forceinline__ void load_master(float (&zm)[NP][FM][4][4], const float* src, int row0, int N,
+                                            int m_pad, int npass, int wave, int lane) {
+  const int lr = lane & 15, lg = lane >> 4;
+  constexpr int R = FM * 16;
+  const int nrows = (N - row0) < R ? (N - row0) : R;
+  const Rsrc rs = make_rsrc(src + (size_t)row0 * m_pad, (size_t)nrows * m_pad * 4);
+  const int rstride = m_pad * 4;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int slab = 4 * p + wave;
+    const bool act = p < npass && slab * 64 < m_pad;
+    const int lo = (4 * lg * m_pad + 64 * slab + lr) * 4;
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) {
+        const bool ok = act && (16 * fm + 4 * lg + r4) < nrows;
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+          zm[p][fm][f][r4] = ok ? bload(rs, lo + 64 * f, (16 * fm + r4) * rstride) : 0.f;
+      }
+  }
+}
+
+template <int P, int R, int NP>
+__global__ __launch_bounds__(PT, 1) void fwd_persist(PersistArgs g) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  constexpr int FM = R / 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int row0 = blockIdx.x * R;
+  const int m_pad = g.m_pad, N = g.N, m = g.m;
+  const int rowb = m_pad * Elem<P>::bytes + 16;
+  const int npass = (m_pad + 255) / 256;
+  const int nrows = (N - row0) < R ? (N - row0) : R;
+  const int rstride = m_pad * 4;      // bytes per row of the [N][m_pad] buffers
+  const int ustride = m * 4;          // bytes per row of the caller's [N][m] buffers
+  float* red = (float*)(lds + R * rowb);
+  const Rsrc rC = make_rsrc(g.C + (size_t)row0 * m_pad, (size_t)nrows * rstride);
+  const Rsrc rZu = make_rsrc(g.Zuser ? g.Zuser + (size_t)row0 * m : nullptr, g.Zuser ? (size_t)nrows * ustride : 0);
+  const Rsrc rV = make_rsrc(g.Vout ? g.Vout + (size_t)row0 * m_pad : nullptr, g.Vout ? (size_t)nrows * rstride : 0);
+  const Rsrc rdZ = make_rsrc(g.dZ ? g.dZ + (size_t)row0 * m : nullptr, g.dZ ? (size_t)nrows * ustride : 0);
+
+  float zm[NP][FM][4][4];
+  if (g.t_begin == 0) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) zm[p][fm][f][r4] = 0.f;
+  } else {
+    load_master<FM, NP>(zm, slot_ptr(g, g.t_begin), row0, N, m_pad, npass, wave, lane);
+  }
+  master_to_lds<P, FM, NP>(zm, lds, rowb, npass, m_pad, wave, lane);
+  __syncthreads();
+
+  const bool want_final = (g.mode & (kModeF | kModeSeed)) != 0;
+  const bool seed = (g.mode & kModeSeed) != 0;
+  for (int t = g.t_begin; t <= g.t_end; ++t) {
+    const bool fin = (t == g.t_end);
+    if (fin && !want_final) break;
+    const float a = fin ? 0.f : g.alpha[t];
+    const float lam = g.lam, th = lam * a;
+    const bool want_f = fin ? ((g.mode & kModeF) != 0) : ((g.mode & kModeTrace) != 0);
+    const bool store = !fin && g.k > 0 &&
+                       (g.store_all || (t + 1) % g.k == 0 || t + 1 == g.T || t + 1 > g.a_last);
+    const Rsrc rD = make_rsrc(store ? slot_ptr(g, t + 1) + (size_t)row0 * m_pad : nullptr,
+                              store ? (size_t)nrows * rstride : 0);
+    const bool copy_out = !fin && (t + 1 == g.T) && g.Zuser;
+    float fs[FM][4];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) fs[fm][r4] = 0.f;
+
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int slab = 4 * p + wave;
+      if (!(p < npass && slab * 64 < m_pad)) continue;
+      f32x4 acc[FM][4];
+      if (t > 0) {
+        contract<P, FM>(g, lds, rowb, slab, lane, acc);
+      } else {
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+          for (int f = 0; f < 4; ++f) acc[fm][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      const int colb = 64 * slab + lr;                 // column of block f = 0
+      const int lo = (4 * lg * m_pad + colb) * 4;      // per-lane offset, [N][m_pad] buffers
+      const int lou = (4 * lg * m + colb) * 4;         // per-lane offset, [N][m] buffers
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+          const int rl = 16 * fm + 4 * lg + r4;
+          if (rl >= nrows) continue;
+          const int so = (16 * fm + r4) * rstride, sou = (16 * fm + r4) * ustride;
+          float w = 0.f;
+          if (fin && seed) w = g.dF ? g.dF[row0 + rl] : g.dF_scalar;
+#pragma unroll
+          for (int f = 0; f < 4; ++f) {
+            const float z = zm[p][fm][f][r4];
+            const float c = bload(rC, lo + 64 * f, so);
+            const float pv = acc[fm][f][r4];
+            if (want_f) fs[fm][r4] += 0.5f * z * pv - z * c + lam * fabsf(z);
+            if (!fin) {
+              const float zn = soft_thresh(z - a * (pv - c), th);
+              zm[p][fm][f][r4] = zn;
+              if (store) bstore(zn, rD, lo + 64 * f, so);
+              if (copy_out && colb + 16 * f < m) bstore(zn, rZu, lou + 64 * f, sou);
+            } else if (seed) {
+              float gv = w * (pv - c + lam * sgnf(z));
+              if (g.dZ && colb + 16 * f < m) gv += bload(rdZ, lou + 64 * f, sou);
+              bstore((z != 0.f) ? gv : 0.f, rV, lo + 64 * f, so);
+            }
+          }
+        }
+    }
+    if (want_f) {
+      float* Fo = fin ? g.F : (g.Ftrace ? g.Ftrace + (size_t)t * N : nullptr);
+      finish_rows<FM>(fs, red, wave, lane, tid, row0, N, g.xsq, Fo, fin ? g.Fd : nullptr);
+    }
+    if (!fin) {
+      __syncthreads();
+      master_to_lds<P, FM, NP>(zm, lds, rowb, npass, m_pad, wave, lane);
+      __syncthreads();
+    }
+  }
+}
+
+template <int P, int R, int NP>
+__global__ __launch_bounds__(PT, 1) void bwd_persist(PersistArgs g) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  constexpr int FM = R / 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int row0 = blockIdx.x * R;
+  const int m_pad = g.m_pad, N = g.N;
+  const int rowb = m_pad * Elem<P>::bytes + 16;
+  const int npass = (m_pad + 255) / 256;
+  const int nrows = (N - row0) < R ? (N - row0) : R;
+  const int rstride = m_pad * 4;
+  double* dred = (double*)(lds + R * rowb);
+
+  float vm[NP][FM][4][4];
+  load_master<FM, NP>(vm, g.Vio, row0, N, m_pad, npass, wave, lane);
+  master_to_lds<P, FM, NP>(vm, lds, rowb, npass, m_pad, wave, lane);
+  __syncthreads();
+
+  for (int t = g.t_hi; t >= g.t_lo; --t) {
+    const float a = g.alpha[t];
+    const Rsrc rz0 = make_rsrc(t >= 1 ? slot_ptr(g, t) + (size_t)row0 * m_pad : nullptr,
+                               t >= 1 ? (size_t)nrows * rstride : 0);
+    const Rsrc rz1 = make_rsrc(slot_ptr(g, t + 1) + (size_t)row0 * m_pad, (size_t)nrows * rstride);
+    double dsum = 0.0;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int slab = 4 * p + wave;
+      if (!(p < npass && slab * 64 < m_pad)) continue;
+      f32x4 acc[FM][4];
+      if (t >= 1) contract<P, FM>(g, lds, rowb, slab, lane, acc);
+      const int lo = (4 * lg * m_pad + 64 * slab + lr) * 4;
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+          if (16 * fm + 4 * lg + r4 >= nrows) continue;
+          const int so = (16 * fm + r4) * rstride;
+#pragma unroll
+          for (int f = 0; f < 4; ++f) {
+            const float v = vm[p][fm][f][r4];
+            const float z0 = t >= 1 ? bload(rz0, lo + 64 * f, so) : 0.f;
+            const float z1 = bload(rz1, lo + 64 * f, so);
+            dsum += (double)v * ((double)z0 - (double)z1);
+            if (t >= 1) vm[p][fm][f][r4] = (z0 != 0.f) ? v - a * acc[fm][f][r4] : 0.f;
+          }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) dsum += __shfl_xor(dsum, o);
+    if (lane == 0) dred[wave] = dsum;
+    __syncthreads();
+    if (tid == 0) g.dpart[(size_t)t * g.P_stride + blockIdx.x] = ((dred[0] + dred[1]) + dred[2]) + dred[3];
+    if (t >= 1 && t > g.t_lo) master_to_lds<P, FM, NP>(vm, lds, rowb, npass, m_pad, wave, lane);
+    __syncthreads();
+  }
+  if (g.t_lo >= 1) {
+    const Rsrc rv = make_rsrc(g.Vio + (size_t)row0 * m_pad, (size_t)nrows * rstride);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int slab = 4 * p + wave;
+      if (!(p < npass && slab * 64 < m_pad)) continue;
+      const int lo = (4 * lg * m_pad + 64 * slab + lr) * 4;
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+          if (16 * fm + 4 * lg + r4 >= nrows) continue;
+#pragma unroll
+          for (int f = 0; f < 4; ++f) bstore(vm[p][fm][f][r4], rv, lo + 64 * f, (16 * fm + r4) * rstride);
+        }
+    }
+  }
+}
+
+// Fragment-ordered copies of G for the persistent kernels.
+// BF16: fragment (cb, kc) = G[16 cb + l % 16][32 kc + 8 (l / 16) + e], e < 8.
+// FP32: fragment (cb, kc) = G[16 cb + l % 16][16 kc + 4 (l / 16) + e], e < 4.
+__global__ void k_swizzle(const float* __restrict__ G, int mp, uint16_t* __restrict__ Gsb, float* __restrict__ Gsf) {
+  const size_t total = (size_t)mp * mp;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    {
+      const int e = i & 7, l = (i >> 3) & 63;
+      const size_t frag = i >> 9;
+      const int KC = mp / 32;
+      const int kc = frag % KC, cb = frag / KC;
+      const float v = G[(size_t)(16 * cb + (l & 15)) * mp + 32 * kc + 8 * (l >> 4) + e];
+      Gsb[i] = __builtin_bit_cast(uint16_t, (__bf16)v);
+    }
+    {
+      const int e = i & 3, l = (i >> 2) & 63;
+      const size_t frag = i >> 8;
+      const int KC = mp / 16;
+      const int kc = frag % KC, cb = frag / KC;
+      Gsf[i] = G[(size_t)(16 * cb + (l & 15)) * mp + 16 * kc + 4 * (l >> 4) + e];
+    }
+  }
+}
+
+template <int P, int R, int NP>
+hipError_t launch_pair(bool fwd, const PersistArgs& a, hipStream_t s) {
+  const int tiles = (a.N + R - 1) / R;
+  if (tiles == 0) return hipSuccess;
+  const size_t lds = (size_t)R * (a.m_pad * Elem<P>::bytes + 16) + 4 * R * sizeof(float) + 64;
+  if (fwd) {
+    hipError_t e = hipFuncSetAttribute((const void*)fwd_persist<P, R, NP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((fwd_persist<P, R, NP>), dim3(tiles), dim3(PT), lds, s, a);
+  } else {
+    hipError_t e = hipFuncSetAttribute((const void*)bwd_persist<P, R, NP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((bwd_persist<P, R, NP>), dim3(tiles), dim3(PT), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int persist_rows(int prec, int m_pad) {
+  if (prec == kBF16) {
+    if (m_pad <= 1024) return 64;
+    if (m_pad <= 2048) return 32;
+    return 0;
+  }
+  if (m_pad <= 512) return 64;
+  if (m_pad <= 1024) return 32;
+  if (m_pad <= 2048) return 16;
+  return 0;
+}
+
+hipError_t launch_persist(bool fwd, int prec, const PersistArgs& a, hipStream_t s) {
+  const int mp = a.m_pad;
+  if (prec == kBF16) {
+    if (mp <= 256) return launch_pair<kBF16, 64, 1>(fwd, a, s);
+    if (mp <= 512) return launch_pair<kBF16, 64, 2>(fwd, a, s);
+    if (mp <= 1024) return launch_pair<kBF16, 64, 4>(fwd, a, s);
+    if (mp <= 2048) return launch_pair<kBF16, 32, 8>(fwd, a, s);
+    return hipErrorInvalidValue;
+  }
+  if (mp <= 256) return launch_pair<kF32, 64, 1>(fwd, a, s);
+  if (mp <= 512) return launch_pair<kF32, 64, 2>(fwd, a, s);
+  if (mp <= 1024) return launch_pair<kF32, 32, 4>(fwd, a, s);
+  if (mp <= 2048) return launch_pair<kF32, 16, 8>(fwd, a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_swizzle(const float* G32, int mp, uint16_t* Gsb, float* Gsf, hipStream_t s) {
+  const size_t total = (size_t)mp * mp;
+  size_t blocks = (total + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_swizzle, dim3((unsigned)blocks), dim3(256), 0, s, G32, mp, Gsb, Gsf);
+  return hipGetLastError();
+}
+
+}  // namespace slista

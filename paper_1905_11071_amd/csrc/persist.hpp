@@ -1,0 +1,49 @@
+// Arguments of the persistent Step-LISTA kernels (kernels_persist.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace slista {
+
+enum PersistMode : int {
+  kModeF = 1,      // objective F(z^{t_end}) per sample (into F, Fd)
+  kModeSeed = 2,   // backward seed v^{T-1} from G z^T (into Vout)
+  kModeTrace = 4   // objective F(z^t) for every t in [t_begin, t_end) (into Ftrace)
+};
+
+struct PersistArgs {
+  const void* Gsw;    // fragment-ordered G (BF16 or FP32)
+  int m_pad, KC;      // KC = number of 64-byte K steps per row
+  int N, m;
+  const float* C;     // [N][m_pad]
+  const float* alpha;
+  float lam;
+  // where z^t lives (see the workspace layout in api.cpp)
+  char* ckpt;
+  char* seg;
+  size_t zbytes;
+  int k, T, a_last;
+  int store_all;
+  // forward range and outputs
+  int t_begin, t_end, mode;
+  float* F;
+  double* Fd;
+  float* Ftrace;
+  const double* xsq;
+  float* Zuser;
+  float* Vout;
+  const float* dF;
+  float dF_scalar;
+  const float* dZ;
+  // backward range and outputs
+  float* Vio;
+  double* dpart;
+  int P_stride, t_hi, t_lo;
+};
+
+// Rows per tile the persistent kernels use for (prec, m_pad); 0 = not handled.
+int persist_rows(int prec, int m_pad);
+hipError_t launch_persist(bool fwd, int prec, const PersistArgs& a, hipStream_t s);
+hipError_t launch_swizzle(const float* G32, int m_pad, uint16_t* Gsb, float* Gsf, hipStream_t s);
+
+}  // namespace slista

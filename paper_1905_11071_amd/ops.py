@@ -165,6 +165,15 @@ def forward_backward(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Te
     return Z, F, loss, dalpha, ws
 
 
+KERNEL_FAMILIES = {"auto": 0, "layer": 1, "persistent": 2}
+
+
+def set_kernel_family(name: str) -> None:
+    """Select the layer kernels: 'auto', 'layer' (one launch per layer) or
+    'persistent' (one workgroup per sample tile through all layers)."""
+    check(lib().slista_set_option(1, KERNEL_FAMILIES[name]))
+
+
 def profile_begin() -> None:
     """Start recording HIP-event timings of every library launch."""
     check(lib().slista_profile_begin())
