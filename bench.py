@@ -27,26 +27,41 @@ METRIC = "sample-layers/s fwd+bwd (BF16-MFMA vs FP32) at fixed obj-gap; % MFMA/H
 PEAK = {"bf16_tflops": 2500.0, "fp32_tflops": 157.3, "hbm_gbs": 8000.0}
 
 
-def roofline(kind: str, avg_ms: float, N: int, m: int, prec: str) -> dict:
-    """Roofline of one fused layer launch.
+def launch_work(kind: str, N: int, m: int, T: int):
+    """Algorithmic flops and HBM bytes of one launch of a persistent kernel.
 
-    Algorithmic work per launch: 2 N m^2 flops (P = Z G). Algorithmic HBM
-    bytes per launch: forward layer 12 m N (read z^t and c, write z^{t+1});
-    backward layer 16 m N (read v^t, z^t, z^{t+1}, write v^{t-1})."""
-    flops = 2.0 * N * m * m
-    bytes_ = (12.0 if kind == "forward_layer" else 16.0) * m * N
+    Units: one contraction of one sample costs 2 m^2 flops (P = Z G); one
+    layer of one sample moves 8 m bytes (forward: read c, write the kept
+    iterate; backward: read z^t and z^{t+1}).
+      forward launch (all T layers + the final contraction for F and the
+        seed): T contractions (layer 0 has none since z^0 = 0, the final one
+        is G z^T); bytes 4 m N (2T + 3): T reads of c and T iterate writes,
+        plus the final c read, the copy of z^T and the seed v^{T-1}.
+      backward launch (all T layers): T - 1 contractions; bytes 4 m N * 2T:
+        z^{t+1} for every t, z^t for t >= 1, and the seed read."""
+    if kind == "forward_layer":
+        return 2.0 * N * m * m * T, 4.0 * m * N * (2 * T + 3)
+    if kind == "backward_layer":
+        return 2.0 * N * m * m * (T - 1), 4.0 * m * N * 2 * T
+    raise ValueError(kind)
+
+
+def roofline(kind: str, avg_ms: float, N: int, m: int, T: int, prec: str) -> dict:
+    flops, bytes_ = launch_work(kind, N, m, T)
     peak_f = PEAK["bf16_tflops"] if prec == "bf16" else PEAK["fp32_tflops"]
     ridge = peak_f * 1e12 / (PEAK["hbm_gbs"] * 1e9)
     sec = avg_ms * 1e-3
+    tflops = flops / sec / 1e12
+    gbs = bytes_ / sec / 1e9
+    out = {"kernel": kind, "avg_ms": round(avg_ms, 4), "flops_per_launch": flops, "bytes_per_launch": bytes_,
+           "mfma_frac": round(tflops / peak_f, 4), "hbm_frac": round(gbs / PEAK["hbm_gbs"], 4), "traffic": None}
     if flops / bytes_ < ridge:
-        ach = bytes_ / sec / 1e9
-        return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-                "frac": round(ach / PEAK["hbm_gbs"], 4), "traffic": None, "kernel": kind,
-                "avg_ms": round(avg_ms, 5), "mfma_frac": round(flops / sec / 1e12 / peak_f, 4)}
-    ach = flops / sec / 1e12
-    return {"bound": "mfma", "achieved": round(ach, 2), "peak": peak_f, "unit": "TFLOP/s",
-            "frac": round(ach / peak_f, 4), "traffic": None, "kernel": kind, "avg_ms": round(avg_ms, 5),
-            "hbm_frac": round(bytes_ / sec / 1e9 / PEAK["hbm_gbs"], 4)}
+        out.update({"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                    "frac": round(gbs / PEAK["hbm_gbs"], 4)})
+    else:
+        out.update({"bound": "mfma", "achieved": round(tflops, 2), "peak": peak_f, "unit": "TFLOP/s",
+                    "frac": round(tflops / peak_f, 4)})
+    return out
 
 
 def time_precision(sl, torch, d, X, lam, alpha, prec, steps, warmup, ckpt):
@@ -68,24 +83,25 @@ def time_precision(sl, torch, d, X, lam, alpha, prec, steps, warmup, ckpt):
     prof = sl.profile_end()
     ms = e0.elapsed_time(e1) / steps
     kernels = {k: v for k, v in prof.items() if k != "dropped" and v[0] > 0}
-    dom = max(kernels, key=lambda k: kernels[k][1])
+    dom = max((k for k in kernels if k in ("forward_layer", "backward_layer")), key=lambda k: kernels[k][1])
     Z, F, loss, dalpha, _ = out
     del ws
     return {"ms_per_step": ms, "wall_ms_per_step": wall * 1e3 / steps, "kernels": kernels, "dominant": dom,
-            "F": F, "loss": float(loss.item()), "dalpha_norm": float(dalpha.norm().item())}
+            "Z": Z, "loss": float(loss.item()), "dalpha_norm": float(dalpha.norm().item())}
 
 
-def gap_report(sl, torch, d, X, lam, alpha, F_by_prec, n_sub=4096, T_ref=3000):
-    """Objective gap of each precision on a sample subset, against a long
-    FP32 ISTA run (T_ref layers, alpha = 1/L) computed by the same library."""
+def gap_report(sl, torch, d, X, lam, alpha, Z_by_prec, n_sub=4096, T_ref=3000):
+    """Objective gap of each precision's z^(T) on a sample subset, against a
+    long FP32 ISTA run (T_ref layers, alpha = 1/L), all F evaluated the same
+    way (slista_objective: FP32 residual, FP64 sums)."""
     sub = X[:n_sub].contiguous()
     a_ref = torch.full((T_ref,), float(alpha[0].item()), device=X.device, dtype=torch.float32)
-    _, Fr, _, _ = sl.forward(d, sub, lam, a_ref, prec="fp32", want_loss=False, ckpt_every=0)
-    fr = Fr.double().mean().item()
-    out = {"reference": f"FP32 ISTA, {T_ref} layers, first {n_sub} samples"}
-    for p, F in F_by_prec.items():
-        out[f"gap_{p}"] = F[:n_sub].double().mean().item() - fr
-    if "bf16" in F_by_prec and "fp32" in F_by_prec:
+    Zr, _, _, _ = sl.forward(d, sub, lam, a_ref, prec="fp32", want_f=False, want_loss=False, ckpt_every=0)
+    fr = sl.objective(d, sub, lam, Zr).double().mean().item()
+    out = {"reference": f"FP32 ISTA, {T_ref} layers, first {n_sub} samples; F by slista_objective"}
+    for p, Z in Z_by_prec.items():
+        out[f"gap_{p}"] = sl.objective(d, sub, lam, Z[:n_sub].contiguous()).double().mean().item() - fr
+    if "bf16" in Z_by_prec and "fp32" in Z_by_prec:
         out["bf16_vs_fp32_rel"] = abs(out["gap_bf16"] - out["gap_fp32"]) / abs(out["gap_fp32"])
         out["within_2e-2"] = out["bf16_vs_fp32_rel"] <= 2e-2
     return out
@@ -118,9 +134,12 @@ def main() -> int:
     ap.add_argument("--workload", default="prec_256x1024")
     ap.add_argument("--precs", default="bf16,fp32")
     ap.add_argument("--ckpt-every", type=int, default=1)
+    ap.add_argument("--variant", type=int, default=0, help="tile variant of the persistent kernels (0 = default)")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gap", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the path needs no collectives); --gpus {args.gpus} "
@@ -129,6 +148,16 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.copy_calib:
+        n = 1 << 28  # 2^28 float32 = 1 GiB read + 1 GiB written per copy
+        src = torch.ones(n, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_each_way": n * 4, "copies": args.steps}))
+        return 0
 
     import synth
     import paper_1905_11071_amd as sl
@@ -140,6 +169,7 @@ def main() -> int:
     D = torch.tensor(pb.D32(), device=dev)
     X = torch.tensor(pb.X32(), device=dev)
     d = sl.Dictionary(D)
+    sl.set_tile_variant(args.variant)
     L, iters = d.lipschitz(max_iter=200_000, rtol=1e-13)
     T = cfg["T"]
     alpha = torch.full((T,), float(np.float32(1.0 / L)), device=dev, dtype=torch.float32)
@@ -150,7 +180,7 @@ def main() -> int:
         r = time_precision(sl, torch, d, X, pb.lam, alpha, p, args.steps, args.warmup, args.ckpt_every)
         dk = r["dominant"]
         n_l, tot = r["kernels"][dk]
-        r["roofline"] = roofline(dk, tot / n_l, pb.N, pb.m, p)
+        r["roofline"] = roofline(dk, tot / n_l, pb.N, pb.m, T, p)
         r["value"] = pb.N * T / (r["ms_per_step"] * 1e-3)
         res[p] = r
         print(f"[bench] {p}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4g} sample-layers/s, "
@@ -159,7 +189,7 @@ def main() -> int:
 
     gap = None
     if not args.no_gap:
-        gap = gap_report(sl, torch, d, X, pb.lam, alpha, {p: r["F"] for p, r in res.items()})
+        gap = gap_report(sl, torch, d, X, pb.lam, alpha, {p: r["Z"] for p, r in res.items()})
         print(f"[bench] gap {gap}", file=sys.stderr, flush=True)
 
     cpu = None

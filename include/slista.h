@@ -148,6 +148,15 @@ SLISTA_API int slista_forward(const slista_dict* dict, const float* X, int N, fl
                               const float* alpha, int T, int prec, float* Z, float* F, int f_trace,
                               float* loss, int ckpt_every, void* ws, size_t ws_bytes, void* stream);
 
+/* Lasso cost of given codes, Eq. (1): F[i] = 1/2 ||x_i - D z_i||^2 + lambda ||z_i||_1
+ * for Z (device FP32 [N, m]), written to F (device FP32 [N]). The residual is
+ * formed in FP32 from the non-zero coordinates of z_i (one wave per sample,
+ * columns of D read K-contiguously) and the sums are accumulated in FP64, so
+ * the value does not depend on the precision that produced Z. Needs no
+ * workspace. */
+SLISTA_API int slista_objective(const slista_dict* dict, const float* X, int N, float lambda, const float* Z,
+                                float* F, void* stream);
+
 /* Reverse pass (derivation in Section 4 / Appendix D: the paper uses
  * automatic differentiation; here it is written out by hand). Differentiates
  *     J = sum_i dF_i F_{x_i}(z_i^(T)) + <dZ, Z^(T)>
@@ -183,6 +192,13 @@ SLISTA_API int slista_forward_backward(const slista_dict* dict, const float* X, 
  * Both families compute bitwise-identical iterates and step-size gradients.
  * ------------------------------------------------------------------------- */
 #define SLISTA_OPT_KERNEL_FAMILY 1
+/* SLISTA_OPT_PERSIST_VARIANT: tile configuration of the persistent kernels.
+ *   0 (default) the library's choice for (precision, m);
+ *   1 tiles of 64 samples (32 for FP32 with m_pad > 512, 16 above 1024),
+ *     one workgroup per CU;
+ *   2 tiles of half that many samples, two workgroups per CU (m_pad <= 1024).
+ * Results are bitwise identical across variants. */
+#define SLISTA_OPT_PERSIST_VARIANT 2
 
 SLISTA_API int slista_set_option(int option, int value);
 

@@ -10,9 +10,11 @@ from .ops import (  # noqa: F401
     backward,
     forward,
     forward_backward,
+    objective,
     profile_begin,
     profile_end,
     set_kernel_family,
+    set_tile_variant,
     slista,
     SlistaFunction,
 )

@@ -34,6 +34,7 @@ SIGNATURES = {
     "slista_workspace_size": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_size_t)]),
     "slista_forward": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _vp, _vp, _c_int, _vp,
                                 _c_int, _vp, _size_t, _vp]),
+    "slista_objective": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _vp, _vp]),
     "slista_backward": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _vp, _vp, _vp, _c_int,
                                  _vp, _size_t, _vp]),
     "slista_forward_backward": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _vp, _vp, _vp,

@@ -101,6 +101,8 @@ struct ProfScope {
 // 1 = per-layer kernels, 2 = persistent kernels (falls back to per-layer
 // where they do not apply). Set through slista_set_option.
 int g_kernel_family = 0;
+// Tile variant of the persistent kernels (0 = default; see persist_rows).
+int g_persist_variant = 0;
 
 constexpr int kMaxN = 1 << 26;
 constexpr int kMaxT = 100000;
@@ -197,7 +199,7 @@ const void* gram_for(const slista::Dict& d, int prec) {
 
 bool use_persist(const Run& r, int prec) {
   if (g_kernel_family == 1) return false;
-  return slista::persist_rows(prec, r.d->m_pad) > 0;
+  return slista::persist_rows(prec, r.d->m_pad, g_persist_variant) > 0;
 }
 
 slista::PersistArgs persist_args(const Run& r, int prec, const float* alpha, float lam) {
@@ -311,7 +313,7 @@ int run_forward(const Run& r, const float* X, float lam, const float* alpha, int
       a.dF_scalar = seed_dF;
       a.Vout = seed_vout;
     }
-    LAUNCH(kKFwd, r.s, slista::launch_persist(true, prec, a, r.s));
+    LAUNCH(kKFwd, r.s, slista::launch_persist(true, prec, a, r.s, g_persist_variant));
     if (loss && want_final) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
     return SLISTA_OK;
   }
@@ -359,28 +361,31 @@ int run_backward(const Run& r, float lam, const float* alpha, int prec, const fl
         a.F = F;
         a.Fd = r.Fd();
       }
-      LAUNCH(kKSeed, r.s, slista::launch_persist(true, prec, a, r.s));
+      LAUNCH(kKSeed, r.s, slista::launch_persist(true, prec, a, r.s, g_persist_variant));
       if (seed_fpart && loss) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
     }
-    const int nseg = (T + k - 1) / k;
+    // With every iterate kept (k = 1) nothing is recomputed: one launch walks
+    // all layers; otherwise one recompute + one backward launch per segment.
+    const int seg_len = k == 1 ? T : k;
+    const int nseg = (T + seg_len - 1) / seg_len;
     for (int sgi = nseg - 1; sgi >= 0; --sgi) {
-      const int a0 = sgi * k;
-      const int b = (a0 + k < T) ? a0 + k : T;
-      if (sgi != nseg - 1 && b - 1 > a0) {
+      const int a0 = sgi * seg_len;
+      const int b = (a0 + seg_len < T) ? a0 + seg_len : T;
+      if (k > 1 && sgi != nseg - 1 && b - 1 > a0) {
         slista::PersistArgs f = persist_args(r, prec, alpha, lam);
         f.t_begin = a0;
         f.t_end = b - 1;
         f.store_all = 1;
-        LAUNCH(kKFwd, r.s, slista::launch_persist(true, prec, f, r.s));
+        LAUNCH(kKFwd, r.s, slista::launch_persist(true, prec, f, r.s, g_persist_variant));
       }
       slista::PersistArgs bw = persist_args(r, prec, alpha, lam);
       bw.t_hi = b - 1;
       bw.t_lo = a0;
       bw.Vio = r.vbuf(0);
       bw.dpart = r.dpart();
-      LAUNCH(kKBwd, r.s, slista::launch_persist(false, prec, bw, r.s));
+      LAUNCH(kKBwd, r.s, slista::launch_persist(false, prec, bw, r.s, g_persist_variant));
     }
-    const int rows = slista::persist_rows(prec, r.d->m_pad);
+    const int rows = slista::persist_rows(prec, r.d->m_pad, g_persist_variant);
     const int tiles = (N + rows - 1) / rows;
     LAUNCH(kKOther, r.s, slista::launch_reduce_dalpha(r.dpart(), T, r.L.P, tiles, tiles, alpha, dalpha, r.s));
     return SLISTA_OK;
@@ -450,6 +455,11 @@ int slista_set_option(int option, int value) {
   if (option == SLISTA_OPT_KERNEL_FAMILY) {
     if (value < 0 || value > 2) return fail(SLISTA_EINVAL, "kernel family %d outside [0, 2]", value);
     g_kernel_family = value;
+    return SLISTA_OK;
+  }
+  if (option == SLISTA_OPT_PERSIST_VARIANT) {
+    if (value < 0 || value > 2) return fail(SLISTA_EINVAL, "tile variant %d outside [0, 2]", value);
+    g_persist_variant = value;
     return SLISTA_OK;
   }
   return fail(SLISTA_EINVAL, "unknown option %d", option);
@@ -619,6 +629,18 @@ int slista_forward(const slista_dict* dict, const float* X, int N, float lambda,
   if (N == 0) return SLISTA_OK;
   Run r{&dict->d, make_layout(dict->d, N, T, ckpt_every), (char*)ws, N, T, (hipStream_t)stream};
   return run_forward(r, X, lambda, alpha, prec, Z, F, f_trace, loss, true);
+}
+
+int slista_objective(const slista_dict* dict, const float* X, int N, float lambda, const float* Z, float* F,
+                     void* stream) {
+  if (!dict) return fail(SLISTA_EINVAL, "dict is NULL");
+  if (N < 0 || N > kMaxN) return fail(SLISTA_EINVAL, "N=%d outside [0, %d]", N, kMaxN);
+  if (!(lambda >= 0.f) || !std::isfinite(lambda)) return fail(SLISTA_EINVAL, "lambda must be finite and >= 0");
+  if (N > 0 && (!X || !Z || !F)) return fail(SLISTA_EINVAL, "X, Z or F is NULL");
+  if (dict->d.n > 512) return fail(SLISTA_ENOTSUP, "slista_objective supports n <= 512 (n=%d)", dict->d.n);
+  LAUNCH(kKOther, (hipStream_t)stream,
+         slista::launch_objective(X, dict->d.Dt, N, dict->d.n, dict->d.m, lambda, Z, F, (hipStream_t)stream));
+  return SLISTA_OK;
 }
 
 int slista_backward(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha, int T,

@@ -86,5 +86,7 @@ hipError_t launch_bwd0(const float* V0, const float* Z1, int N, int ldz, double*
 hipError_t launch_reduce_dalpha(const double* dpart, int T, int P, int count0, int count, const float* alpha,
                                 float* dalpha, hipStream_t s);
 int bwd0_blocks(int N, int ldz);
+hipError_t launch_objective(const float* X, const float* Dt, int N, int n, int m, float lam, const float* Z,
+                            float* F, hipStream_t s);
 
 }  // namespace slista

@@ -129,25 +129,27 @@ __device__ __forceinline__ void compute_stage(const char* buf, f32x4 (&acc)[4][4
       av[f] = *(const uint4*)(buf + (wm * 64 + f * 16 + lr) * ROWB + 64 * c + 16 * lg);
       bv[f] = *(const uint4*)(buf + A_BYTES + (wn * 64 + f * 16 + lr) * ROWB + 64 * c + 16 * lg);
     }
+    if constexpr (P == kF32) {
+      // K sub-step e outermost: consecutive MFMAs update independent accumulators
 #pragma unroll
-    for (int fm = 0; fm < 4; ++fm) {
+      for (int e = 0; e < 4; ++e)
 #pragma unroll
-      for (int fn = 0; fn < 4; ++fn) {
-        if constexpr (P == kF32) {
-          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[fm].x),
-                                                              __uint_as_float(bv[fn].x), acc[fm][fn], 0, 0, 0);
-          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[fm].y),
-                                                              __uint_as_float(bv[fn].y), acc[fm][fn], 0, 0, 0);
-          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[fm].z),
-                                                              __uint_as_float(bv[fn].z), acc[fm][fn], 0, 0, 0);
-          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[fm].w),
-                                                              __uint_as_float(bv[fn].w), acc[fm][fn], 0, 0, 0);
-        } else {
+        for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+          for (int fn = 0; fn < 4; ++fn) {
+            const uint32_t ae = e == 0 ? av[fm].x : e == 1 ? av[fm].y : e == 2 ? av[fm].z : av[fm].w;
+            const uint32_t be = e == 0 ? bv[fn].x : e == 1 ? bv[fn].y : e == 2 ? bv[fn].z : bv[fn].w;
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(ae), __uint_as_float(be),
+                                                                acc[fm][fn], 0, 0, 0);
+          }
+    } else {
+#pragma unroll
+      for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn)
           acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[fm]),
                                                                  __builtin_bit_cast(bf16x8, bv[fn]),
                                                                  acc[fm][fn], 0, 0, 0);
-        }
-      }
     }
   }
 }

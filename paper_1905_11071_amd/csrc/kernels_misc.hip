@@ -204,6 +204,42 @@ __global__ void k_reduce_dalpha(const double* __restrict__ dpart, int P, int cou
   if (threadIdx.x == 0) dalpha[t] = (float)(-s / (double)alpha[t]);
 }
 
+// F_i = 1/2 ||x_i - D z_i||^2 + lam ||z_i||_1 (Eq. (1)), one wave per sample.
+// Each lane owns coordinates j = lane, lane + 64, ... of the residual (at most
+// 8 per lane: n <= 512); the loop over the coordinates k of z skips zeros
+// (a wave-uniform branch) and adds z_k D[:, k] from the K-contiguous row k of D^T.
+constexpr int kObjMaxPerLane = 8;
+__global__ void k_objective(const float* __restrict__ X, const float* __restrict__ Dt, int N, int n, int m,
+                            float lam, const float* __restrict__ Z, float* __restrict__ F) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= N) return;
+  float r[kObjMaxPerLane];
+#pragma unroll
+  for (int q = 0; q < kObjMaxPerLane; ++q) {
+    const int j = lane + 64 * q;
+    r[q] = j < n ? X[(size_t)i * n + j] : 0.f;
+  }
+  double l1 = 0.0;
+  const float* zi = Z + (size_t)i * m;
+  for (int k = 0; k < m; ++k) {
+    const float zk = zi[k];
+    if (zk == 0.f) continue;
+    if (lane == 0) l1 += fabs((double)zk);
+    const float* dk = Dt + (size_t)k * n;
+#pragma unroll
+    for (int q = 0; q < kObjMaxPerLane; ++q) {
+      const int j = lane + 64 * q;
+      if (j < n) r[q] -= zk * dk[j];
+    }
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < kObjMaxPerLane; ++q) s += (double)r[q] * (double)r[q];
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) F[i] = (float)(0.5 * s + (double)lam * l1);
+}
+
 int grid_for(size_t work, int per_block) {
   size_t b = (work + per_block - 1) / per_block;
   if (b < 1) b = 1;
@@ -265,6 +301,14 @@ hipError_t launch_reduce_f(const double* xsq, const double* fpart, int col_tiles
 
 hipError_t launch_reduce_loss(const double* Fd, int N, float* loss, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(kRedThreads), 0, s, Fd, N, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_objective(const float* X, const float* Dt, int N, int n, int m, float lam, const float* Z,
+                            float* F, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  if (n > 64 * kObjMaxPerLane) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_objective, dim3((N + 3) / 4), dim3(256), 0, s, X, Dt, N, n, m, lam, Z, F);
   return hipGetLastError();
 }
 

@@ -41,9 +41,11 @@ struct PersistArgs {
   int P_stride, t_hi, t_lo;
 };
 
-// Rows per tile the persistent kernels use for (prec, m_pad); 0 = not handled.
-int persist_rows(int prec, int m_pad);
-hipError_t launch_persist(bool fwd, int prec, const PersistArgs& a, hipStream_t s);
+// Tile variants available for m_pad (0 = not handled by the persistent kernels).
+int persist_variants(int m_pad);
+// Rows per tile for (prec, m_pad, variant); variant 0 = the default one.
+int persist_rows(int prec, int m_pad, int variant);
+hipError_t launch_persist(bool fwd, int prec, const PersistArgs& a, hipStream_t s, int variant);
 hipError_t launch_swizzle(const float* G32, int m_pad, uint16_t* Gsb, float* Gsf, hipStream_t s);
 
 }  // namespace slista

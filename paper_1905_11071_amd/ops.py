@@ -129,6 +129,17 @@ def forward(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, pre
     return Z, F, loss, ws
 
 
+def objective(d: Dictionary, X: torch.Tensor, lam: float, Z: torch.Tensor) -> torch.Tensor:
+    """F_i = 1/2 ||x_i - D z_i||^2 + lam ||z_i||_1 for given codes (FP32 residual,
+    FP64 sums), independent of the precision that produced Z."""
+    X = _dev_f32(X, "X")
+    Z = _dev_f32(Z, "Z", (X.shape[0], d.m))
+    F = torch.empty(X.shape[0], device=d.device, dtype=torch.float32)
+    check(lib().slista_objective(d.handle, X.data_ptr(), int(X.shape[0]), float(lam), Z.data_ptr(), F.data_ptr(),
+                                 _stream(d.device)))
+    return F
+
+
 def backward(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, ws: torch.Tensor,
              dZ: Optional[torch.Tensor] = None, dF: Optional[torch.Tensor] = None, prec="fp32",
              ckpt_every: int = 1) -> torch.Tensor:
@@ -172,6 +183,11 @@ def set_kernel_family(name: str) -> None:
     """Select the layer kernels: 'auto', 'layer' (one launch per layer) or
     'persistent' (one workgroup per sample tile through all layers)."""
     check(lib().slista_set_option(1, KERNEL_FAMILIES[name]))
+
+
+def set_tile_variant(v: int) -> None:
+    """Tile configuration of the persistent kernels (0 = library default, 1, 2)."""
+    check(lib().slista_set_option(2, int(v)))
 
 
 def profile_begin() -> None:

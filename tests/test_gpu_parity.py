@@ -351,3 +351,18 @@ def test_kernel_families_agree(sl, prec, shape):
         np.testing.assert_allclose(da, ref[2], rtol=1e-6, atol=1e-12 * np.max(np.abs(ref[2])))
         np.testing.assert_allclose(F, ref[1], rtol=1e-5)
     d.close()
+
+
+def test_objective_entry_point(sl):
+    """slista_objective evaluates Eq. (1) for given codes; compared with the
+    oracle's FP64 objective on sparse and dense codes (FP32 residual: the
+    relative error is a few units of 2^-24 times the cancellation factor)."""
+    pb = synth.make_problem(64, 256, 777, 0.05, 0.01, 0.1, seed=19)
+    d = sl.Dictionary(_gpu(pb.D))
+    rng = np.random.default_rng(3)
+    for Z in (pb.Z0, rng.standard_normal((pb.N, pb.m)) * (rng.random((pb.N, pb.m)) < 0.3)):
+        Z = Z.astype(np.float32).astype(np.float64)
+        Fg = sl.objective(d, _gpu(pb.X), pb.lam, _gpu(Z)).cpu().numpy()
+        Fo = oracle.objective(pb.D, pb.X, Z, pb.lam)
+        np.testing.assert_allclose(Fg, Fo, rtol=2e-5, atol=1e-6)
+    d.close()
