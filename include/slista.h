@@ -196,7 +196,8 @@ SLISTA_API int slista_forward_backward(const slista_dict* dict, const float* X, 
  *   0 (default) the library's choice for (precision, m);
  *   1 tiles of 64 samples (32 for FP32 with m_pad > 512, 16 above 1024),
  *     one workgroup per CU;
- *   2 tiles of half that many samples, two workgroups per CU (m_pad <= 1024).
+ *   2 tiles of half that many samples, two workgroups per CU (m_pad <= 1024);
+ *   3 the tiles of variant 1 in one 8-wave workgroup (m_pad <= 1024).
  * Results are bitwise identical across variants. */
 #define SLISTA_OPT_PERSIST_VARIANT 2
 

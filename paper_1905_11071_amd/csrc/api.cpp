@@ -458,7 +458,7 @@ int slista_set_option(int option, int value) {
     return SLISTA_OK;
   }
   if (option == SLISTA_OPT_PERSIST_VARIANT) {
-    if (value < 0 || value > 2) return fail(SLISTA_EINVAL, "tile variant %d outside [0, 2]", value);
+    if (value < 0 || value > 3) return fail(SLISTA_EINVAL, "tile variant %d outside [0, 3]", value);
     g_persist_variant = value;
     return SLISTA_OK;
   }

@@ -185,12 +185,12 @@ __device__ __forceinline__ void master_to_lds(const float (&zm)[NP][FM][4][4], c
 }
 
 // Per-row objective of the tile from per-lane partials: reduce over the 16
-// lanes of a row group, then over the 4 waves (fixed order), add 1/2 ||x||^2.
-template <int FM>
-__device__ __forceinline__ void finish_rows(const float (&fs)[FM][4], float* red, int wave, int lane, int tid, int row0, int N,
-                            const double* xsq, float* Fout, double* Fd) {
+// lanes of a row group, then over the 4 column waves (fixed order), add
+// 1/2 ||x||^2. Rows of this wave start at rbase within the R-row tile.
+template <int FM, int R>
+__device__ __forceinline__ void finish_rows(const float (&fs)[FM][4], float* red, int wc, int rbase, int lane,
+                                            int tid, int row0, int N, const double* xsq, float* Fout, double* Fd) {
   const int lr = lane & 15, lg = lane >> 4;
-  constexpr int R = FM * 16;
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
@@ -200,7 +200,7 @@ __device__ __forceinline__ void finish_rows(const float (&fs)[FM][4], float* red
       v += __shfl_xor(v, 2);
       v += __shfl_xor(v, 4);
       v += __shfl_xor(v, 8);
-      if (lr == 0) red[wave * R + 16 * fm + 4 * lg + r4] = v;
+      if (lr == 0) red[wc * R + rbase + 16 * fm + 4 * lg + r4] = v;
     }
   __syncthreads();
   if (tid < R && row0 + tid < N) {
@@ -211,8 +211,8 @@ __device__ __forceinline__ void finish_rows(const float (&fs)[FM][4], float* red
   __syncthreads();
 }
 
-// Loads the tile's [R][m_pad] FP32 rows of `src` (row stride m_pad) into the
-// master registers; rows past N read as 0.
+// Loads this wave's 16 FM rows (from row0) of `src` ([N][m_pad] FP32) into
+// the master registers; rows past N read as 0.
 template <int FM, int NP>
 __device__ __forceinline__ void load_master(float (&zm)[NP][FM][4][4], const float* src, int row0, int N,
                                             int m_pad, int npass, int wave, int lane) {
@@ -241,13 +241,15 @@ __device__ __forceinline__ void load_master(float (&zm)[NP][FM][4][4], const flo
 // Forward over layers [t_begin, t_end): z^(t+1) = ST(z^t - a_t (G z^t - c), lam a_t),
 // keeping the tape; with TRACE also F(z^t) for each t. Then, if asked, one
 // more contraction G z^(t_end) for F(z^(t_end)) and the backward seed.
-template <int P, int R, int NP, bool TRACE, int PF, int OCC>
-__global__ __launch_bounds__(PT, OCC) void fwd_persist(PersistArgs g) {
+template <int P, int R, int NP, bool TRACE, int PF, int OCC, int WR>
+__global__ __launch_bounds__(PT * WR, OCC) void fwd_persist(PersistArgs g) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  constexpr int FM = R / 16;
+  constexpr int FM = R / (16 * WR);  // 16-row blocks per wave
   const int tid = threadIdx.x, lane = tid & 63;
   // wave-uniform, and known to be: descriptors built from it stay in SGPRs
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wave = wid & 3;                 // column wave: slab 4 p + wave of pass p
+  const int rbase = (wid >> 2) * 16 * FM;   // first tile row of this wave
   const int lr = lane & 15, lg = lane >> 4;
   const int row0 = blockIdx.x * R;
   const int m_pad = g.m_pad, N = g.N, m = g.m;
@@ -271,9 +273,9 @@ __global__ __launch_bounds__(PT, OCC) void fwd_persist(PersistArgs g) {
 #pragma unroll
           for (int r4 = 0; r4 < 4; ++r4) zm[p][fm][f][r4] = 0.f;
   } else {
-    load_master<FM, NP>(zm, slot_ptr(g, g.t_begin), row0, N, m_pad, npass, wave, lane);
+    load_master<FM, NP>(zm, slot_ptr(g, g.t_begin), row0 + rbase, N, m_pad, npass, wave, lane);
   }
-  master_to_lds<P, FM, NP>(zm, lds, rowb, npass, m_pad, wave, lane);
+  master_to_lds<P, FM, NP>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
   __syncthreads();
 
   for (int t = g.t_begin; t < g.t_end; ++t) {
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(PT, OCC) void fwd_persist(PersistArgs g) {
       if (!(p < npass && slab * 64 < m_pad)) continue;
       f32x4 acc[FM][4];
       if (t > 0) {
-        contract<P, FM, PF>(g, lds, rowb, slab, lane, acc);
+        contract<P, FM, PF>(g, lds + rbase * rowb, rowb, slab, lane, acc);
       } else {
 #pragma unroll
         for (int fm = 0; fm < FM; ++fm)
@@ -310,8 +312,8 @@ __global__ __launch_bounds__(PT, OCC) void fwd_persist(PersistArgs g) {
       for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
         for (int r4 = 0; r4 < 4; ++r4) {
-          if (16 * fm + 4 * lg + r4 >= nrows) continue;
-          const int so = (16 * fm + r4) * rstride, sou = (16 * fm + r4) * ustride;
+          if (rbase + 16 * fm + 4 * lg + r4 >= nrows) continue;
+          const int so = (rbase + 16 * fm + r4) * rstride, sou = (rbase + 16 * fm + r4) * ustride;
 #pragma unroll
           for (int f = 0; f < 4; ++f) {
             const float z = zm[p][fm][f][r4];
@@ -325,9 +327,9 @@ __global__ __launch_bounds__(PT, OCC) void fwd_persist(PersistArgs g) {
           }
         }
     }
-    if constexpr (TRACE) finish_rows<FM>(fs, red, wave, lane, tid, row0, N, g.xsq, g.Ftrace + (size_t)t * N, nullptr);
+    if constexpr (TRACE) finish_rows<FM, R>(fs, red, wave, rbase, lane, tid, row0, N, g.xsq, g.Ftrace + (size_t)t * N, nullptr);
     __syncthreads();
-    master_to_lds<P, FM, NP>(zm, lds, rowb, npass, m_pad, wave, lane);
+    master_to_lds<P, FM, NP>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
     __syncthreads();
   }
 
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(PT, OCC) void fwd_persist(PersistArgs g) {
     const int slab = 4 * p + wave;
     if (!(p < npass && slab * 64 < m_pad)) continue;
     f32x4 acc[FM][4];
-    contract<P, FM, PF>(g, lds, rowb, slab, lane, acc);
+    contract<P, FM, PF>(g, lds + rbase * rowb, rowb, slab, lane, acc);
     const int colb = 64 * slab + lr;
     const int lo = (4 * lg * m_pad + colb) * 4;
     const int lou = (4 * lg * m + colb) * 4;
@@ -356,9 +358,9 @@ __global__ __launch_bounds__(PT, OCC) void fwd_persist(PersistArgs g) {
     for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
       for (int r4 = 0; r4 < 4; ++r4) {
-        const int rl = 16 * fm + 4 * lg + r4;
+        const int rl = rbase + 16 * fm + 4 * lg + r4;
         if (rl >= nrows) continue;
-        const int so = (16 * fm + r4) * rstride, sou = (16 * fm + r4) * ustride;
+        const int so = (rbase + 16 * fm + r4) * rstride, sou = (rbase + 16 * fm + r4) * ustride;
         const float w = seed ? (g.dF ? g.dF[row0 + rl] : g.dF_scalar) : 0.f;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
@@ -374,16 +376,18 @@ __global__ __launch_bounds__(PT, OCC) void fwd_persist(PersistArgs g) {
         }
       }
   }
-  if (want_f) finish_rows<FM>(fs, red, wave, lane, tid, row0, N, g.xsq, g.F, g.Fd);
+  if (want_f) finish_rows<FM, R>(fs, red, wave, rbase, lane, tid, row0, N, g.xsq, g.F, g.Fd);
 }
 
-template <int P, int R, int NP, int PF, int OCC>
-__global__ __launch_bounds__(PT, OCC) void bwd_persist(PersistArgs g) {
+template <int P, int R, int NP, int PF, int OCC, int WR>
+__global__ __launch_bounds__(PT * WR, OCC) void bwd_persist(PersistArgs g) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  constexpr int FM = R / 16;
+  constexpr int FM = R / (16 * WR);  // 16-row blocks per wave
   const int tid = threadIdx.x, lane = tid & 63;
   // wave-uniform, and known to be: descriptors built from it stay in SGPRs
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wave = wid & 3;                 // column wave: slab 4 p + wave of pass p
+  const int rbase = (wid >> 2) * 16 * FM;   // first tile row of this wave
   const int lr = lane & 15, lg = lane >> 4;
   const int row0 = blockIdx.x * R;
   const int m_pad = g.m_pad, N = g.N;
@@ -394,8 +398,8 @@ __global__ __launch_bounds__(PT, OCC) void bwd_persist(PersistArgs g) {
   double* dred = (double*)(lds + R * rowb);
 
   float vm[NP][FM][4][4];
-  load_master<FM, NP>(vm, g.Vio, row0, N, m_pad, npass, wave, lane);
-  master_to_lds<P, FM, NP>(vm, lds, rowb, npass, m_pad, wave, lane);
+  load_master<FM, NP>(vm, g.Vio, row0 + rbase, N, m_pad, npass, wave, lane);
+  master_to_lds<P, FM, NP>(vm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
   __syncthreads();
 
   for (int t = g.t_hi; t >= g.t_lo; --t) {
@@ -409,14 +413,14 @@ __global__ __launch_bounds__(PT, OCC) void bwd_persist(PersistArgs g) {
       const int slab = 4 * p + wave;
       if (!(p < npass && slab * 64 < m_pad)) continue;
       f32x4 acc[FM][4];
-      if (t >= 1) contract<P, FM, PF>(g, lds, rowb, slab, lane, acc);
+      if (t >= 1) contract<P, FM, PF>(g, lds + rbase * rowb, rowb, slab, lane, acc);
       const int lo = (4 * lg * m_pad + 64 * slab + lr) * 4;
 #pragma unroll
       for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
         for (int r4 = 0; r4 < 4; ++r4) {
-          if (16 * fm + 4 * lg + r4 >= nrows) continue;
-          const int so = (16 * fm + r4) * rstride;
+          if (rbase + 16 * fm + 4 * lg + r4 >= nrows) continue;
+          const int so = (rbase + 16 * fm + r4) * rstride;
 #pragma unroll
           for (int f = 0; f < 4; ++f) {
             const float v = vm[p][fm][f][r4];
@@ -429,10 +433,15 @@ __global__ __launch_bounds__(PT, OCC) void bwd_persist(PersistArgs g) {
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) dsum += __shfl_xor(dsum, o);
-    if (lane == 0) dred[wave] = dsum;
+    if (lane == 0) dred[wid] = dsum;
     __syncthreads();
-    if (tid == 0) g.dpart[(size_t)t * g.P_stride + blockIdx.x] = ((dred[0] + dred[1]) + dred[2]) + dred[3];
-    if (t >= 1 && t > g.t_lo) master_to_lds<P, FM, NP>(vm, lds, rowb, npass, m_pad, wave, lane);
+    if (tid == 0) {
+      double tot = 0.0;
+#pragma unroll
+      for (int w = 0; w < 4 * WR; ++w) tot += dred[w];
+      g.dpart[(size_t)t * g.P_stride + blockIdx.x] = tot;
+    }
+    if (t >= 1 && t > g.t_lo) master_to_lds<P, FM, NP>(vm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
     __syncthreads();
   }
   if (g.t_lo >= 1) {
@@ -446,9 +455,9 @@ __global__ __launch_bounds__(PT, OCC) void bwd_persist(PersistArgs g) {
       for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
         for (int r4 = 0; r4 < 4; ++r4) {
-          if (16 * fm + 4 * lg + r4 >= nrows) continue;
+          if (rbase + 16 * fm + 4 * lg + r4 >= nrows) continue;
 #pragma unroll
-          for (int f = 0; f < 4; ++f) bstore(vm[p][fm][f][r4], rv, lo + 64 * f, (16 * fm + r4) * rstride);
+          for (int f = 0; f < 4; ++f) bstore(vm[p][fm][f][r4], rv, lo + 64 * f, (rbase + 16 * fm + r4) * rstride);
         }
     }
   }
@@ -478,23 +487,23 @@ __global__ void k_swizzle(const float* __restrict__ G, int mp, uint16_t* __restr
   }
 }
 
-template <int P, int R, int NP, int PF, int OCC>
+template <int P, int R, int NP, int PF, int OCC, int WR = 1>
 hipError_t launch_pair(bool fwd, const PersistArgs& a, hipStream_t s) {
   const int tiles = (a.N + R - 1) / R;
   if (tiles == 0) return hipSuccess;
   const size_t lds = (size_t)R * (a.m_pad * Elem<P>::bytes + 16) + 4 * R * sizeof(float) + 64;
   const bool trace = fwd && (a.mode & kModeTrace);
-  const void* fn = !fwd ? (const void*)bwd_persist<P, R, NP, PF, OCC>
-                        : trace ? (const void*)fwd_persist<P, R, NP, true, PF, OCC>
-                                : (const void*)fwd_persist<P, R, NP, false, PF, OCC>;
+  const void* fn = !fwd ? (const void*)bwd_persist<P, R, NP, PF, OCC, WR>
+                        : trace ? (const void*)fwd_persist<P, R, NP, true, PF, OCC, WR>
+                                : (const void*)fwd_persist<P, R, NP, false, PF, OCC, WR>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   if (!fwd)
-    hipLaunchKernelGGL((bwd_persist<P, R, NP, PF, OCC>), dim3(tiles), dim3(PT), lds, s, a);
+    hipLaunchKernelGGL((bwd_persist<P, R, NP, PF, OCC, WR>), dim3(tiles), dim3(PT * WR), lds, s, a);
   else if (trace)
-    hipLaunchKernelGGL((fwd_persist<P, R, NP, true, PF, OCC>), dim3(tiles), dim3(PT), lds, s, a);
+    hipLaunchKernelGGL((fwd_persist<P, R, NP, true, PF, OCC, WR>), dim3(tiles), dim3(PT * WR), lds, s, a);
   else
-    hipLaunchKernelGGL((fwd_persist<P, R, NP, false, PF, OCC>), dim3(tiles), dim3(PT), lds, s, a);
+    hipLaunchKernelGGL((fwd_persist<P, R, NP, false, PF, OCC, WR>), dim3(tiles), dim3(PT * WR), lds, s, a);
   return hipGetLastError();
 }
 
@@ -509,9 +518,13 @@ int np_of(int m_pad) { return m_pad <= 256 ? 1 : m_pad <= 512 ? 2 : m_pad <= 102
 //              SIMD), G fragments 3 K steps ahead;
 //   variant 2: half the rows, two workgroups per CU (two waves per SIMD, so
 //              one tile's FP32 epilogue runs under the other tile's MFMAs),
-//              G fragments 1 K step ahead, at most 256 registers per lane.
+//              G fragments 1 K step ahead, at most 256 registers per lane;
+//   variant 3: the rows of variant 1 in one 8-wave workgroup per CU: two row
+//              halves x four column slabs, two waves per SIMD; the two waves
+//              of a column slab read the same G fragments (one L2 fetch,
+//              one L1 hit), G fragments 1 K step ahead.
 // m_pad in (1024, 2048] has variant 1 only.
-int persist_variants(int m_pad) { return np_of(m_pad) == 8 ? 1 : (np_of(m_pad) ? 2 : 0); }
+int persist_variants(int m_pad) { return np_of(m_pad) == 8 ? 1 : (np_of(m_pad) ? 3 : 0); }
 
 // Measured on the 256 x 1024, N = 65 536, T = 50 workload: variant 2 is 1.16x
 // (BF16) and 1.12x (FP32) faster than variant 1 for fwd+bwd.
@@ -528,27 +541,38 @@ int persist_rows(int prec, int m_pad, int variant) {
   if (prec == kBF16) return np == 8 ? 32 : (v2 ? 32 : 64);
   if (np == 8) return 16;
   if (np == 4) return v2 ? 16 : 32;
-  return v2 ? 32 : 64;
+  return v2 ? 32 : 64;  // variant 3 keeps the rows of variant 1
 }
 
 hipError_t launch_persist(bool fwd, int prec, const PersistArgs& a, hipStream_t s, int variant) {
   const int np = np_of(a.m_pad);
   if (variant <= 0 || variant > persist_variants(a.m_pad)) variant = default_variant(prec, a.m_pad);
-  const bool v2 = variant == 2;
   if (prec == kBF16) {
-    switch (np) {
-      case 1: return v2 ? launch_pair<kBF16, 32, 1, 2, 2>(fwd, a, s) : launch_pair<kBF16, 64, 1, 4, 1>(fwd, a, s);
-      case 2: return v2 ? launch_pair<kBF16, 32, 2, 2, 2>(fwd, a, s) : launch_pair<kBF16, 64, 2, 4, 1>(fwd, a, s);
-      case 4: return v2 ? launch_pair<kBF16, 32, 4, 2, 2>(fwd, a, s) : launch_pair<kBF16, 64, 4, 4, 1>(fwd, a, s);
-      case 8: return launch_pair<kBF16, 32, 8, 4, 1>(fwd, a, s);
+    switch (np * 4 + variant) {
+      case 1 * 4 + 1: return launch_pair<kBF16, 64, 1, 4, 1>(fwd, a, s);
+      case 1 * 4 + 2: return launch_pair<kBF16, 32, 1, 2, 2>(fwd, a, s);
+      case 1 * 4 + 3: return launch_pair<kBF16, 64, 1, 2, 1, 2>(fwd, a, s);
+      case 2 * 4 + 1: return launch_pair<kBF16, 64, 2, 4, 1>(fwd, a, s);
+      case 2 * 4 + 2: return launch_pair<kBF16, 32, 2, 2, 2>(fwd, a, s);
+      case 2 * 4 + 3: return launch_pair<kBF16, 64, 2, 2, 1, 2>(fwd, a, s);
+      case 4 * 4 + 1: return launch_pair<kBF16, 64, 4, 4, 1>(fwd, a, s);
+      case 4 * 4 + 2: return launch_pair<kBF16, 32, 4, 2, 2>(fwd, a, s);
+      case 4 * 4 + 3: return launch_pair<kBF16, 64, 4, 2, 1, 2>(fwd, a, s);
+      case 8 * 4 + 1: return launch_pair<kBF16, 32, 8, 4, 1>(fwd, a, s);
       default: return hipErrorInvalidValue;
     }
   }
-  switch (np) {
-    case 1: return v2 ? launch_pair<kF32, 32, 1, 2, 2>(fwd, a, s) : launch_pair<kF32, 64, 1, 4, 1>(fwd, a, s);
-    case 2: return v2 ? launch_pair<kF32, 32, 2, 2, 2>(fwd, a, s) : launch_pair<kF32, 64, 2, 4, 1>(fwd, a, s);
-    case 4: return v2 ? launch_pair<kF32, 16, 4, 2, 2>(fwd, a, s) : launch_pair<kF32, 32, 4, 4, 1>(fwd, a, s);
-    case 8: return launch_pair<kF32, 16, 8, 4, 1>(fwd, a, s);
+  switch (np * 4 + variant) {
+    case 1 * 4 + 1: return launch_pair<kF32, 64, 1, 4, 1>(fwd, a, s);
+    case 1 * 4 + 2: return launch_pair<kF32, 32, 1, 2, 2>(fwd, a, s);
+    case 1 * 4 + 3: return launch_pair<kF32, 64, 1, 2, 1, 2>(fwd, a, s);
+    case 2 * 4 + 1: return launch_pair<kF32, 64, 2, 4, 1>(fwd, a, s);
+    case 2 * 4 + 2: return launch_pair<kF32, 32, 2, 2, 2>(fwd, a, s);
+    case 2 * 4 + 3: return launch_pair<kF32, 64, 2, 2, 1, 2>(fwd, a, s);
+    case 4 * 4 + 1: return launch_pair<kF32, 32, 4, 4, 1>(fwd, a, s);
+    case 4 * 4 + 2: return launch_pair<kF32, 16, 4, 2, 2>(fwd, a, s);
+    case 4 * 4 + 3: return launch_pair<kF32, 32, 4, 2, 1, 2>(fwd, a, s);
+    case 8 * 4 + 1: return launch_pair<kF32, 16, 8, 4, 1>(fwd, a, s);
     default: return hipErrorInvalidValue;
   }
 }

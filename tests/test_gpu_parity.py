@@ -328,9 +328,9 @@ def test_full_size_256x1024(sl, full_prec_problem, prec):
 @pytest.mark.parametrize("shape", [(50, 200, 1037, 9), (64, 256, 3000, 12), (96, 1024, 700, 7), (40, 1100, 300, 5)])
 def test_kernel_families_agree(sl, prec, shape):
     """The persistent kernels (a workgroup carries a sample tile through all
-    layers) and the per-layer kernels use the same K order and epilogue
-    arithmetic: z^(T) and the kept iterates are bitwise identical; dalpha
-    differs only by the grouping of its FP64 partial sums."""
+    layers; three tile variants) and the per-layer kernels use the same K
+    order and epilogue arithmetic: z^(T) is bitwise identical; dalpha differs
+    only by the grouping of its FP64 partial sums."""
     n, m, N, T = shape
     pb = synth.make_problem(n, m, N, 0.08, 0.01, 0.1, seed=300 + m)
     alpha = synth.perturbed_steps(oracle.lipschitz(pb.D), T, seed=4)
@@ -338,14 +338,17 @@ def test_kernel_families_agree(sl, prec, shape):
     X, a = _gpu(pb.X), _gpu(alpha)
     res = {}
     try:
-        for fam in ("layer", "persistent"):
+        for fam, variants in (("layer", (0,)), ("persistent", (1, 2, 3))):
             sl.set_kernel_family(fam)
-            for k in (1, 3):
-                Z, F, loss, da, _ = sl.forward_backward(d, X, pb.lam, a, prec=prec, ckpt_every=k)
-                res[(fam, k)] = (Z.cpu().numpy(), F.cpu().numpy(), da.cpu().numpy())
+            for v in variants:
+                sl.set_tile_variant(v)
+                for k in (1, 3):
+                    Z, F, loss, da, _ = sl.forward_backward(d, X, pb.lam, a, prec=prec, ckpt_every=k)
+                    res[(fam, v, k)] = (Z.cpu().numpy(), F.cpu().numpy(), da.cpu().numpy())
     finally:
         sl.set_kernel_family("auto")
-    ref = res[("layer", 1)]
+        sl.set_tile_variant(0)
+    ref = res[("layer", 0, 1)]
     for key, (Z, F, da) in res.items():
         assert np.array_equal(Z, ref[0]), key
         np.testing.assert_allclose(da, ref[2], rtol=1e-6, atol=1e-12 * np.max(np.abs(ref[2])))
