@@ -181,6 +181,51 @@ SLISTA_API int slista_forward_backward(const slista_dict* dict, const float* X, 
                                        size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Uneven batches: many independent Lasso problems (each its own dictionary,
+ * n, m, N, lambda and steps; one common T) run forward + backward of their
+ * mean losses together. Problems are grouped by column-pass bucket (m_pad up
+ * to 256, 512, 1024, 2048); each bucket runs as one persistent launch per
+ * phase over a work list of (problem, tile) pairs ordered longest first.
+ *
+ * Usage: slista_batch_create -> slista_batch_workspace_size -> allocate ->
+ * slista_batch_bind (builds the device argument tables, synchronises) ->
+ * slista_batch_run (enqueue) or slista_batch_capture once and then
+ * slista_batch_replay (HIP graph) -> slista_batch_destroy.
+ * A batch owns small device tables (argument records and work lists) and
+ * the captured graph; the problems' buffers and the workspace stay the
+ * caller's and must outlive the batch's use of them.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const slista_dict* dict;   /* dictionary of this problem (m_pad <= 2048) */
+  const float* X;            /* device FP32 [N, n] */
+  int N;                     /* >= 1 */
+  float lambda;              /* finite, > 0 */
+  const float* alpha;        /* device FP32 [T] */
+  float* Z;                  /* device FP32 [N, m] out: z^(T) */
+  float* F;                  /* device FP32 [N] out: F(z^(T)), or NULL */
+  float* loss;               /* device FP32 [1] out: mean F, or NULL */
+  float* dalpha;             /* device FP32 [T] out: d(mean F)/d alpha */
+} slista_problem;
+
+typedef struct slista_batch slista_batch;
+
+/* Plan a batch of P >= 1 problems (the array is copied). ckpt_every >= 1. */
+SLISTA_API int slista_batch_create(const slista_problem* problems, int P, int T, int prec, int ckpt_every,
+                                   slista_batch** out);
+SLISTA_API int slista_batch_workspace_size(const slista_batch* batch, size_t* bytes);
+/* Attach a workspace (256-byte aligned, >= slista_batch_workspace_size) and
+ * upload the argument tables; synchronises `stream`. */
+SLISTA_API int slista_batch_bind(slista_batch* batch, void* ws, size_t ws_bytes, void* stream);
+/* Enqueue forward + backward of every problem on `stream`. */
+SLISTA_API int slista_batch_run(slista_batch* batch, void* stream);
+/* Record slista_batch_run into a HIP graph owned by the batch (stream
+ * capture on `stream`; nothing runs). Replaces a previous capture. */
+SLISTA_API int slista_batch_capture(slista_batch* batch, void* stream);
+/* Launch the captured graph on `stream`. */
+SLISTA_API int slista_batch_replay(slista_batch* batch, void* stream);
+SLISTA_API int slista_batch_destroy(slista_batch* batch);
+
+/* ---------------------------------------------------------------------------
  * Options (process-wide, not thread-safe; set before enqueuing work)
  *
  * SLISTA_OPT_KERNEL_FAMILY: which kernels run the layers.

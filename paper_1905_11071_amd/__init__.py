@@ -5,6 +5,7 @@ include/slista.h); this package is its thin PyTorch binding.
 """
 from .ops import (  # noqa: F401
     PRECISIONS,
+    Batch,
     Dictionary,
     SlistaError,
     backward,

@@ -40,11 +40,25 @@ SIGNATURES = {
     "slista_forward_backward": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _vp, _vp, _vp,
                                          _vp, _c_int, _vp, _size_t, _vp]),
     "slista_set_option": (_c_int, [_c_int, _c_int]),
+    "slista_batch_create": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_vp)]),
+    "slista_batch_workspace_size": (_c_int, [_vp, ctypes.POINTER(_size_t)]),
+    "slista_batch_bind": (_c_int, [_vp, _vp, _size_t, _vp]),
+    "slista_batch_run": (_c_int, [_vp, _vp]),
+    "slista_batch_capture": (_c_int, [_vp, _vp]),
+    "slista_batch_replay": (_c_int, [_vp, _vp]),
+    "slista_batch_destroy": (_c_int, [_vp]),
     "slista_profile_begin": (_c_int, []),
     "slista_profile_end": (_c_int, [ctypes.POINTER(_c_int), ctypes.POINTER(_c_double), ctypes.POINTER(_c_int)]),
 }
 
 PROFILE_KINDS = ["correlation", "forward_layer", "objective", "backward_seed", "backward_layer", "elementwise"]
+
+class Problem(ctypes.Structure):
+    """C layout of slista_problem."""
+    _fields_ = [("dict", ctypes.c_void_p), ("X", ctypes.c_void_p), ("N", ctypes.c_int), ("lam", ctypes.c_float),
+                ("alpha", ctypes.c_void_p), ("Z", ctypes.c_void_p), ("F", ctypes.c_void_p),
+                ("loss", ctypes.c_void_p), ("dalpha", ctypes.c_void_p)]
+
 
 STATUS = {0: "SLISTA_OK", -1: "SLISTA_EINVAL", -2: "SLISTA_ENOMEM", -3: "SLISTA_EHIP",
           -4: "SLISTA_ENOTSUP", -5: "SLISTA_ENOTCONV"}

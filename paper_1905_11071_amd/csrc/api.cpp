@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -30,6 +31,28 @@
 
 struct slista_dict {
   slista::Dict d;
+};
+
+struct slista_batch {
+  int P = 0, T = 0, prec = 0, k = 1, variant = 0;
+  std::vector<slista_problem> probs;
+  std::vector<size_t> offset;          // workspace offset of each problem
+  size_t total = 0;
+  // buckets of the persistent kernels
+  struct Bucket {
+    int np = 0, max_m_pad = 0, nwork = 0;
+    std::vector<int> problems;
+    size_t work_off = 0;                // index of the bucket's first work item
+  };
+  std::vector<Bucket> buckets;
+  std::vector<int> rows;                // tile rows per problem
+  // device tables (owned)
+  slista::PersistArgs* d_args = nullptr;
+  int2* d_work = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -686,6 +709,190 @@ int slista_forward_backward(const slista_dict* dict, const float* X, int N, floa
   }
   if ((st = run_forward(r, X, lambda, alpha, prec, Z, nullptr, 0, nullptr, false)) != SLISTA_OK) return st;
   return run_backward(r, lambda, alpha, prec, nullptr, nullptr, (float)(1.0 / N), dalpha, F || loss, F, loss);
+}
+
+static void batch_release_graph(slista_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+int slista_batch_create(const slista_problem* problems, int P, int T, int prec, int ckpt_every, slista_batch** out) {
+  if (!out) return fail(SLISTA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!problems || P < 1 || P > 1 << 20) return fail(SLISTA_EINVAL, "need 1 <= P problems");
+  if (T < 1 || T > kMaxT) return fail(SLISTA_EINVAL, "T=%d outside [1, %d]", T, kMaxT);
+  if (prec != SLISTA_FP32 && prec != SLISTA_BF16) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
+  if (ckpt_every < 1 || ckpt_every > kMaxT) return fail(SLISTA_EINVAL, "ckpt_every=%d must be >= 1", ckpt_every);
+  for (int p = 0; p < P; ++p) {
+    const slista_problem& q = problems[p];
+    if (!q.dict || !q.X || !q.alpha || !q.Z || !q.dalpha)
+      return fail(SLISTA_EINVAL, "problem %d: dict, X, alpha, Z or dalpha is NULL", p);
+    if (q.N < 1 || q.N > kMaxN) return fail(SLISTA_EINVAL, "problem %d: N=%d outside [1, %d]", p, q.N, kMaxN);
+    if (!(q.lambda > 0.f) || !std::isfinite(q.lambda)) return fail(SLISTA_EINVAL, "problem %d: bad lambda", p);
+    if (slista::persist_np(q.dict->d.m_pad) == 0)
+      return fail(SLISTA_ENOTSUP, "problem %d: m_pad=%d > 2048 is not batched", p, q.dict->d.m_pad);
+  }
+  slista_batch* b = new (std::nothrow) slista_batch;
+  if (!b) return fail(SLISTA_ENOMEM, "host allocation failed");
+  b->P = P;
+  b->T = T;
+  b->prec = prec;
+  b->k = ckpt_every;
+  b->variant = g_persist_variant;
+  b->probs.assign(problems, problems + P);
+  size_t off = 0;
+  for (int p = 0; p < P; ++p) {
+    b->offset.push_back(off);
+    off += align256(make_layout(problems[p].dict->d, problems[p].N, T, ckpt_every).total);
+    b->rows.push_back(slista::persist_rows(prec, problems[p].dict->d.m_pad, b->variant));
+  }
+  b->total = off;
+  for (int np : {8, 4, 2, 1}) {
+    slista_batch::Bucket bk;
+    bk.np = np;
+    for (int p = 0; p < P; ++p)
+      if (slista::persist_np(problems[p].dict->d.m_pad) == np) {
+        bk.problems.push_back(p);
+        bk.max_m_pad = std::max(bk.max_m_pad, problems[p].dict->d.m_pad);
+        bk.nwork += (problems[p].N + b->rows[p] - 1) / b->rows[p];
+      }
+    if (!bk.problems.empty()) b->buckets.push_back(bk);
+  }
+  *out = b;
+  return SLISTA_OK;
+}
+
+int slista_batch_workspace_size(const slista_batch* b, size_t* bytes) {
+  if (!b || !bytes) return fail(SLISTA_EINVAL, "batch or bytes is NULL");
+  *bytes = b->total;
+  return SLISTA_OK;
+}
+
+static Run batch_run_of(const slista_batch* b, int p, hipStream_t s) {
+  const slista_problem& q = b->probs[p];
+  return Run{&q.dict->d, make_layout(q.dict->d, q.N, b->T, b->k), b->ws + b->offset[p], q.N, b->T, s};
+}
+
+int slista_batch_bind(slista_batch* b, void* ws, size_t ws_bytes, void* stream) {
+  if (!b) return fail(SLISTA_EINVAL, "batch is NULL");
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < b->total)
+    return fail(SLISTA_EINVAL, "workspace must be 256-byte aligned with %zu bytes", b->total);
+  hipStream_t s = (hipStream_t)stream;
+  b->ws = (char*)ws;
+  b->ws_bytes = ws_bytes;
+  batch_release_graph(b);
+  std::vector<slista::PersistArgs> args(b->P);
+  for (int p = 0; p < b->P; ++p) {
+    const slista_problem& q = b->probs[p];
+    Run r = batch_run_of(b, p, s);
+    slista::PersistArgs a = persist_args(r, b->prec, q.alpha, q.lambda);
+    a.F = q.F;
+    a.Fd = r.Fd();
+    a.Zuser = q.Z;
+    a.Vout = r.vbuf(0);
+    a.Vio = r.vbuf(0);
+    a.dpart = r.dpart();
+    a.dF_scalar = (float)(1.0 / q.N);
+    a.mode_mask = slista::kModeF | slista::kModeSeed;
+    args[p] = a;
+  }
+  std::vector<int2> work;
+  for (auto& bk : b->buckets) {
+    bk.work_off = work.size();
+    // longest tiles first: larger m_pad, then problem order
+    std::vector<int> order = bk.problems;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return b->probs[x].dict->d.m_pad > b->probs[y].dict->d.m_pad;
+    });
+    for (int p : order) {
+      const int tiles = (b->probs[p].N + b->rows[p] - 1) / b->rows[p];
+      for (int t = 0; t < tiles; ++t) work.push_back(make_int2(p, t));
+    }
+  }
+  if (!b->d_args) {
+    HIP_TRY(hipMalloc(&b->d_args, sizeof(slista::PersistArgs) * b->P));
+    HIP_TRY(hipMalloc(&b->d_work, sizeof(int2) * work.size()));
+  }
+  HIP_TRY(hipMemcpyAsync(b->d_args, args.data(), sizeof(slista::PersistArgs) * b->P, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b->d_work, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return SLISTA_OK;
+}
+
+int slista_batch_run(slista_batch* b, void* stream) {
+  if (!b || !b->ws) return fail(SLISTA_EINVAL, "batch is NULL or not bound to a workspace");
+  hipStream_t s = (hipStream_t)stream;
+  const int T = b->T, k = b->k, prec = b->prec;
+  int st;
+  for (int p = 0; p < b->P; ++p)
+    if ((st = prep(batch_run_of(b, p, s), b->probs[p].X)) != SLISTA_OK) return st;
+  auto phase = [&](bool fwd, slista::PersistPhase ph) -> int {
+    for (const auto& bk : b->buckets)
+      LAUNCH(fwd ? kKFwd : kKBwd, s,
+             slista::launch_persist_batched(fwd, prec, bk.np, b->variant, b->d_args, b->d_work + bk.work_off,
+                                            bk.nwork, bk.max_m_pad, ph, s));
+    return SLISTA_OK;
+  };
+  if ((st = phase(true, slista::PersistPhase{0, T, slista::kModeF | slista::kModeSeed, 0, 0, 0})) != SLISTA_OK)
+    return st;
+  for (int p = 0; p < b->P; ++p)
+    if (b->probs[p].loss) {
+      Run r = batch_run_of(b, p, s);
+      LAUNCH(kKOther, s, slista::launch_reduce_loss(r.Fd(), r.N, b->probs[p].loss, s));
+    }
+  const int seg_len = k == 1 ? T : k;
+  const int nseg = (T + seg_len - 1) / seg_len;
+  for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+    const int a0 = sgi * seg_len;
+    const int e = (a0 + seg_len < T) ? a0 + seg_len : T;
+    if (k > 1 && sgi != nseg - 1 && e - 1 > a0)
+      if ((st = phase(true, slista::PersistPhase{a0, e - 1, 0, 1, 0, 0})) != SLISTA_OK) return st;
+    if ((st = phase(false, slista::PersistPhase{0, 0, 0, 0, e - 1, a0})) != SLISTA_OK) return st;
+  }
+  for (int p = 0; p < b->P; ++p) {
+    Run r = batch_run_of(b, p, s);
+    const int tiles = (r.N + b->rows[p] - 1) / b->rows[p];
+    LAUNCH(kKOther, s, slista::launch_reduce_dalpha(r.dpart(), T, r.L.P, tiles, tiles, b->probs[p].alpha,
+                                                    b->probs[p].dalpha, s));
+  }
+  return SLISTA_OK;
+}
+
+int slista_batch_capture(slista_batch* b, void* stream) {
+  if (!b || !b->ws) return fail(SLISTA_EINVAL, "batch is NULL or not bound to a workspace");
+  if (g_prof.on) return fail(SLISTA_EINVAL, "kernel timing must be off during capture");
+  hipStream_t s = (hipStream_t)stream;
+  batch_release_graph(b);
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  const int st = slista_batch_run(b, stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (st != SLISTA_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(SLISTA_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  b->graph = g;
+  HIP_TRY(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+  return SLISTA_OK;
+}
+
+int slista_batch_replay(slista_batch* b, void* stream) {
+  if (!b || !b->exec) return fail(SLISTA_EINVAL, "batch is NULL or has no captured graph");
+  HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
+  return SLISTA_OK;
+}
+
+int slista_batch_destroy(slista_batch* b) {
+  if (!b) return SLISTA_OK;
+  (void)hipDeviceSynchronize();
+  batch_release_graph(b);
+  hipFree(b->d_args);
+  hipFree(b->d_work);
+  delete b;
+  return SLISTA_OK;
 }
 
 }  // extern "C"

@@ -241,9 +241,8 @@ __device__ __forceinline__ void load_master(float (&zm)[NP][FM][4][4], const flo
 // Forward over layers [t_begin, t_end): z^(t+1) = ST(z^t - a_t (G z^t - c), lam a_t),
 // keeping the tape; with TRACE also F(z^t) for each t. Then, if asked, one
 // more contraction G z^(t_end) for F(z^(t_end)) and the backward seed.
-template <int P, int R, int NP, bool TRACE, int PF, int OCC, int WR>
-__global__ __launch_bounds__(PT * WR, OCC) void fwd_persist(PersistArgs g) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
+template <int P, int R, int NP, bool TRACE, int PF, int WR>
+__device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* lds) {
   constexpr int FM = R / (16 * WR);  // 16-row blocks per wave
   const int tid = threadIdx.x, lane = tid & 63;
   // wave-uniform, and known to be: descriptors built from it stay in SGPRs
@@ -251,7 +250,7 @@ __global__ __launch_bounds__(PT * WR, OCC) void fwd_persist(PersistArgs g) {
   const int wave = wid & 3;                 // column wave: slab 4 p + wave of pass p
   const int rbase = (wid >> 2) * 16 * FM;   // first tile row of this wave
   const int lr = lane & 15, lg = lane >> 4;
-  const int row0 = blockIdx.x * R;
+  const int row0 = tile * R;
   const int m_pad = g.m_pad, N = g.N, m = g.m;
   const int rowb = m_pad * Elem<P>::bytes + 16;
   const int npass = (m_pad + 255) / 256;
@@ -379,9 +378,8 @@ __global__ __launch_bounds__(PT * WR, OCC) void fwd_persist(PersistArgs g) {
   if (want_f) finish_rows<FM, R>(fs, red, wave, rbase, lane, tid, row0, N, g.xsq, g.F, g.Fd);
 }
 
-template <int P, int R, int NP, int PF, int OCC, int WR>
-__global__ __launch_bounds__(PT * WR, OCC) void bwd_persist(PersistArgs g) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
+template <int P, int R, int NP, int PF, int WR>
+__device__ __forceinline__ void bwd_body(const PersistArgs& g, int tile, char* lds) {
   constexpr int FM = R / (16 * WR);  // 16-row blocks per wave
   const int tid = threadIdx.x, lane = tid & 63;
   // wave-uniform, and known to be: descriptors built from it stay in SGPRs
@@ -389,7 +387,7 @@ __global__ __launch_bounds__(PT * WR, OCC) void bwd_persist(PersistArgs g) {
   const int wave = wid & 3;                 // column wave: slab 4 p + wave of pass p
   const int rbase = (wid >> 2) * 16 * FM;   // first tile row of this wave
   const int lr = lane & 15, lg = lane >> 4;
-  const int row0 = blockIdx.x * R;
+  const int row0 = tile * R;
   const int m_pad = g.m_pad, N = g.N;
   const int rowb = m_pad * Elem<P>::bytes + 16;
   const int npass = (m_pad + 255) / 256;
@@ -439,7 +437,7 @@ __global__ __launch_bounds__(PT * WR, OCC) void bwd_persist(PersistArgs g) {
       double tot = 0.0;
 #pragma unroll
       for (int w = 0; w < 4 * WR; ++w) tot += dred[w];
-      g.dpart[(size_t)t * g.P_stride + blockIdx.x] = tot;
+      g.dpart[(size_t)t * g.P_stride + tile] = tot;
     }
     if (t >= 1 && t > g.t_lo) master_to_lds<P, FM, NP>(vm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
     __syncthreads();
@@ -461,6 +459,55 @@ __global__ __launch_bounds__(PT * WR, OCC) void bwd_persist(PersistArgs g) {
         }
     }
   }
+}
+
+// Single problem: workgroup b carries tile b.
+template <int P, int R, int NP, bool TRACE, int PF, int OCC, int WR>
+__global__ __launch_bounds__(PT * WR, OCC) void fwd_persist(PersistArgs g) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  fwd_body<P, R, NP, TRACE, PF, WR>(g, blockIdx.x, lds);
+}
+
+template <int P, int R, int NP, int PF, int OCC, int WR>
+__global__ __launch_bounds__(PT * WR, OCC) void bwd_persist(PersistArgs g) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  bwd_body<P, R, NP, PF, WR>(g, blockIdx.x, lds);
+}
+
+// Several problems in one launch: workgroup b carries tile work[b].y of
+// problem work[b].x, whose arguments are tab[work[b].x] with the layer range
+// and mode of this launch (ph) filled in. The work list is ordered longest
+// tile first.
+__device__ __forceinline__ PersistArgs batched_args(const PersistArgs* tab, const int2* work, const PersistPhase& ph,
+                                                    int& tile) {
+  const int2 w = work[blockIdx.x];
+  PersistArgs g = tab[w.x];
+  g.t_begin = ph.t_begin;
+  g.t_end = ph.t_end;
+  g.mode = ph.mode & g.mode_mask;
+  g.store_all = ph.store_all;
+  g.t_hi = ph.t_hi;
+  g.t_lo = ph.t_lo;
+  tile = w.y;
+  return g;
+}
+
+template <int P, int R, int NP, int PF, int OCC, int WR>
+__global__ __launch_bounds__(PT * WR, OCC) void fwd_persist_batched(const PersistArgs* tab, const int2* work,
+                                                                     PersistPhase ph) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  int tile;
+  const PersistArgs g = batched_args(tab, work, ph, tile);
+  fwd_body<P, R, NP, false, PF, WR>(g, tile, lds);
+}
+
+template <int P, int R, int NP, int PF, int OCC, int WR>
+__global__ __launch_bounds__(PT * WR, OCC) void bwd_persist_batched(const PersistArgs* tab, const int2* work,
+                                                                     PersistPhase ph) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  int tile;
+  const PersistArgs g = batched_args(tab, work, ph, tile);
+  bwd_body<P, R, NP, PF, WR>(g, tile, lds);
 }
 
 // Fragment-ordered copies of G for the persistent kernels.
@@ -504,6 +551,22 @@ hipError_t launch_pair(bool fwd, const PersistArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((fwd_persist<P, R, NP, true, PF, OCC, WR>), dim3(tiles), dim3(PT * WR), lds, s, a);
   else
     hipLaunchKernelGGL((fwd_persist<P, R, NP, false, PF, OCC, WR>), dim3(tiles), dim3(PT * WR), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int P, int R, int NP, int PF, int OCC, int WR = 1>
+hipError_t launch_pair_batched(bool fwd, const PersistArgs* tab, const int2* work, int nwork, int max_m_pad,
+                               const PersistPhase& ph, hipStream_t s) {
+  if (nwork == 0) return hipSuccess;
+  const size_t lds = (size_t)R * (max_m_pad * Elem<P>::bytes + 16) + 4 * R * sizeof(float) + 64;
+  const void* fn = fwd ? (const void*)fwd_persist_batched<P, R, NP, PF, OCC, WR>
+                       : (const void*)bwd_persist_batched<P, R, NP, PF, OCC, WR>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (fwd)
+    hipLaunchKernelGGL((fwd_persist_batched<P, R, NP, PF, OCC, WR>), dim3(nwork), dim3(PT * WR), lds, s, tab, work, ph);
+  else
+    hipLaunchKernelGGL((bwd_persist_batched<P, R, NP, PF, OCC, WR>), dim3(nwork), dim3(PT * WR), lds, s, tab, work, ph);
   return hipGetLastError();
 }
 
@@ -575,6 +638,44 @@ hipError_t launch_persist(bool fwd, int prec, const PersistArgs& a, hipStream_t 
     case 8 * 4 + 1: return launch_pair<kF32, 16, 8, 4, 1>(fwd, a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+int persist_np(int m_pad) { return np_of(m_pad); }
+
+hipError_t launch_persist_batched(bool fwd, int prec, int np, int variant, const PersistArgs* tab, const int2* work,
+                                  int nwork, int max_m_pad, const PersistPhase& ph, hipStream_t s) {
+  const int probe_m_pad = np == 8 ? 2048 : np * 256;
+  if (variant <= 0 || variant > persist_variants(probe_m_pad)) variant = default_variant(prec, probe_m_pad);
+#define SLISTA_B(...) return launch_pair_batched<__VA_ARGS__>(fwd, tab, work, nwork, max_m_pad, ph, s)
+  if (prec == kBF16) {
+    switch (np * 4 + variant) {
+      case 1 * 4 + 1: SLISTA_B(kBF16, 64, 1, 4, 1);
+      case 1 * 4 + 2: SLISTA_B(kBF16, 32, 1, 2, 2);
+      case 1 * 4 + 3: SLISTA_B(kBF16, 64, 1, 2, 1, 2);
+      case 2 * 4 + 1: SLISTA_B(kBF16, 64, 2, 4, 1);
+      case 2 * 4 + 2: SLISTA_B(kBF16, 32, 2, 2, 2);
+      case 2 * 4 + 3: SLISTA_B(kBF16, 64, 2, 2, 1, 2);
+      case 4 * 4 + 1: SLISTA_B(kBF16, 64, 4, 4, 1);
+      case 4 * 4 + 2: SLISTA_B(kBF16, 32, 4, 2, 2);
+      case 4 * 4 + 3: SLISTA_B(kBF16, 64, 4, 2, 1, 2);
+      case 8 * 4 + 1: SLISTA_B(kBF16, 32, 8, 4, 1);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (np * 4 + variant) {
+    case 1 * 4 + 1: SLISTA_B(kF32, 64, 1, 4, 1);
+    case 1 * 4 + 2: SLISTA_B(kF32, 32, 1, 2, 2);
+    case 1 * 4 + 3: SLISTA_B(kF32, 64, 1, 2, 1, 2);
+    case 2 * 4 + 1: SLISTA_B(kF32, 64, 2, 4, 1);
+    case 2 * 4 + 2: SLISTA_B(kF32, 32, 2, 2, 2);
+    case 2 * 4 + 3: SLISTA_B(kF32, 64, 2, 2, 1, 2);
+    case 4 * 4 + 1: SLISTA_B(kF32, 32, 4, 4, 1);
+    case 4 * 4 + 2: SLISTA_B(kF32, 16, 4, 2, 2);
+    case 4 * 4 + 3: SLISTA_B(kF32, 32, 4, 2, 1, 2);
+    case 8 * 4 + 1: SLISTA_B(kF32, 16, 8, 4, 1);
+    default: return hipErrorInvalidValue;
+  }
+#undef SLISTA_B
 }
 
 hipError_t launch_swizzle(const float* G32, int mp, uint16_t* Gsb, float* Gsf, hipStream_t s) {

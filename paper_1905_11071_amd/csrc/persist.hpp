@@ -39,6 +39,12 @@ struct PersistArgs {
   float* Vio;
   double* dpart;
   int P_stride, t_hi, t_lo;
+  int mode_mask;      // batched launches: modes this problem takes part in
+};
+
+// Layer range and mode of one launch over several problems.
+struct PersistPhase {
+  int t_begin, t_end, mode, store_all, t_hi, t_lo;
 };
 
 // Tile variants available for m_pad (0 = not handled by the persistent kernels).
@@ -47,5 +53,11 @@ int persist_variants(int m_pad);
 int persist_rows(int prec, int m_pad, int variant);
 hipError_t launch_persist(bool fwd, int prec, const PersistArgs& a, hipStream_t s, int variant);
 hipError_t launch_swizzle(const float* G32, int m_pad, uint16_t* Gsb, float* Gsf, hipStream_t s);
+// Column-pass bucket of m_pad (1, 2, 4, 8; 0 = not handled).
+int persist_np(int m_pad);
+// One launch over the work list (problem, tile) of problems in bucket np; the
+// LDS is sized for max_m_pad.
+hipError_t launch_persist_batched(bool fwd, int prec, int np, int variant, const PersistArgs* tab, const int2* work,
+                                  int nwork, int max_m_pad, const PersistPhase& ph, hipStream_t s);
 
 }  // namespace slista

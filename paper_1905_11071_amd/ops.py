@@ -176,6 +176,74 @@ def forward_backward(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Te
     return Z, F, loss, dalpha, ws
 
 
+class Batch:
+    """Forward + backward of many independent Lasso problems (own dictionary,
+    n, m, N, lambda and steps; common T) in grouped persistent launches, with
+    an optional captured HIP graph.
+
+    problems: list of (Dictionary, X [N, n], lam, alpha [T]). Outputs per
+    problem after run()/replay(): Z[i], F[i], loss[i], dalpha[i]."""
+
+    def __init__(self, problems, prec="fp32", ckpt_every: int = 1):
+        from ._lib import Problem
+        if not problems:
+            raise ValueError("empty batch")
+        T = int(problems[0][3].shape[0])
+        self.device = problems[0][0].device
+        self._keep = []
+        self.Z, self.F, self.loss, self.dalpha = [], [], [], []
+        arr = (Problem * len(problems))()
+        for i, (d, X, lam, alpha) in enumerate(problems):
+            X, alpha = _check_inputs(d, X, alpha)
+            if int(alpha.shape[0]) != T:
+                raise ValueError("all problems of a batch share T")
+            N = int(X.shape[0])
+            Z = torch.empty(N, d.m, device=d.device, dtype=torch.float32)
+            F = torch.empty(N, device=d.device, dtype=torch.float32)
+            loss = torch.empty(1, device=d.device, dtype=torch.float32)
+            da = torch.empty(T, device=d.device, dtype=torch.float32)
+            self._keep += [d, X, alpha]
+            self.Z.append(Z)
+            self.F.append(F)
+            self.loss.append(loss)
+            self.dalpha.append(da)
+            arr[i] = Problem(d.handle.value, X.data_ptr(), N, float(lam), alpha.data_ptr(), Z.data_ptr(),
+                             F.data_ptr(), loss.data_ptr(), da.data_ptr())
+        h = ctypes.c_void_p()
+        check(lib().slista_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(problems), T, _prec(prec),
+                                        ckpt_every, ctypes.byref(h)))
+        self._h = h
+        nbytes = ctypes.c_size_t()
+        check(lib().slista_batch_workspace_size(self._h, ctypes.byref(nbytes)))
+        self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            check(lib().slista_batch_bind(self._h, self.ws.data_ptr(), self.ws.numel(), _stream(self.device)))
+
+    def run(self) -> None:
+        check(lib().slista_batch_run(self._h, _stream(self.device)))
+
+    def capture(self) -> None:
+        """Record run() into a HIP graph (on a side stream, as capture requires)."""
+        s = torch.cuda.Stream(self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        check(lib().slista_batch_capture(self._h, ctypes.c_void_p(s.cuda_stream)))
+        torch.cuda.current_stream(self.device).wait_stream(s)
+
+    def replay(self) -> None:
+        check(lib().slista_batch_replay(self._h, _stream(self.device)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().slista_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 KERNEL_FAMILIES = {"auto": 0, "layer": 1, "persistent": 2}
 
 
