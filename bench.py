@@ -126,6 +126,57 @@ def cpu_baseline(pb, alpha_np, n_sub: int) -> dict:
                                         f"({sec:.1f} s)"}
 
 
+def uneven_report(sl, torch, prec: str, T: int, ckpt: int, reps: int) -> dict:
+    """Uneven multi-problem batch: 64 independent Lasso problems (n in [32, 512],
+    m = 4n, N in [128, 8192]), per-problem perturbed 1/L steps, forward +
+    backward with checkpoints every `ckpt` layers, autotuned tiles, timed as
+    replays of one captured HIP graph."""
+    import synth
+    import numpy as np
+    specs = synth.uneven_problem_specs(P=synth.UNEVEN["P"], seed=synth.UNEVEN["seed"])
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    inputs, dicts = [], []
+    for i, sp in enumerate(specs):
+        pb = synth.make_problem(sp["n"], sp["m"], sp["N"], sp["p"], sp["sigma"], sp["lam_frac"], sp["seed"])
+        d = sl.Dictionary(torch.tensor(pb.D32(), device=dev))
+        L, _ = d.lipschitz(max_iter=20_000, rtol=1e-9)
+        alpha = torch.tensor(synth.perturbed_steps(L, T, seed=sp["seed"]), device=dev, dtype=torch.float32)
+        inputs.append((d, torch.tensor(pb.X32(), device=dev), pb.lam, alpha))
+        dicts.append(d)
+    print(f"[bench] uneven batch: {len(specs)} problems generated in {time.time() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    b = sl.Batch(inputs, prec=prec, ckpt_every=ckpt)
+    b.run()
+    torch.cuda.synchronize()
+    tuned = b.autotune()
+    b.capture()
+    b.replay()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        b.replay()
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    Ns = np.array([sp["N"] for sp in specs], np.float64)
+    ms_ = np.array([sp["m"] for sp in specs], np.float64)
+    # useful contractions per sample: T forward (T-1 layers + the final G z^T) and T-1 backward
+    flops = float(np.sum(2.0 * Ns * ms_ ** 2) * (2 * T - 1))
+    peak = 2.5e15 if prec == "bf16" else 157.3e12
+    out = {"workload": "uneven_64", "problems": len(specs), "T": T, "ckpt_every": ckpt, "prec": prec,
+           "total_samples": int(Ns.sum()), "ms_per_step": round(ms, 3),
+           "value": round(float(Ns.sum()) * T / (ms * 1e-3), 1), "unit": "sample-layers/s",
+           "mfma_tflops": round(flops / (ms * 1e-3) / 1e12, 2), "mfma_frac": round(flops / (ms * 1e-3) / peak, 4),
+           "tuned_variant_by_column_passes": tuned, "timing": "HIP graph replay"}
+    b.close()
+    for d in dicts:
+        d.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,10 +185,14 @@ def main() -> int:
     ap.add_argument("--workload", default="prec_256x1024")
     ap.add_argument("--precs", default="bf16,fp32")
     ap.add_argument("--ckpt-every", type=int, default=1)
-    ap.add_argument("--variant", type=int, default=0, help="tile variant of the persistent kernels (0 = default)")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="tile variant of the persistent kernels (0 = autotune on the workload)")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gap", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven 64-problem batch")
+    ap.add_argument("--uneven-precs", default="bf16,fp32")
+    ap.add_argument("--uneven-reps", type=int, default=3)
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -175,8 +230,14 @@ def main() -> int:
     alpha = torch.full((T,), float(np.float32(1.0 / L)), device=dev, dtype=torch.float32)
     print(f"[bench] L={L:.9f} ({iters} power iterations)", file=sys.stderr, flush=True)
 
+    tuned = {}
     res = {}
     for p in args.precs.split(","):
+        if args.variant == 0:
+            best, ms = sl.autotune(d, X, pb.lam, alpha, prec=p, ckpt_every=args.ckpt_every)
+            tuned[p] = {"variant": best, "ms_per_call_by_variant": [round(x, 3) for x in ms]}
+            print(f"[bench] autotune {p}: variant {best}, ms by variant {tuned[p]['ms_per_call_by_variant']}",
+                  file=sys.stderr, flush=True)
         r = time_precision(sl, torch, d, X, pb.lam, alpha, p, args.steps, args.warmup, args.ckpt_every)
         dk = r["dominant"]
         n_l, tot = r["kernels"][dk]
@@ -191,6 +252,14 @@ def main() -> int:
     if not args.no_gap:
         gap = gap_report(sl, torch, d, X, pb.lam, alpha, {p: r["Z"] for p, r in res.items()})
         print(f"[bench] gap {gap}", file=sys.stderr, flush=True)
+
+    uneven = None
+    if not args.no_uneven:
+        ucfg = synth.UNEVEN
+        uneven = {}
+        for p in args.uneven_precs.split(","):
+            uneven[p] = uneven_report(sl, torch, p, ucfg["T"], ucfg["ckpt_every"], args.uneven_reps)
+            print(f"[bench] uneven {p}: {uneven[p]}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -223,6 +292,8 @@ def main() -> int:
                               "loss": r["loss"]}
                           for p, r in res.items()},
         "objective_gap": gap,
+        "uneven_batch": uneven,
+        "autotune": tuned or {"forced_variant": args.variant},
     }
     print(json.dumps(line))
     d.close()

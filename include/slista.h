@@ -223,6 +223,13 @@ SLISTA_API int slista_batch_run(slista_batch* batch, void* stream);
 SLISTA_API int slista_batch_capture(slista_batch* batch, void* stream);
 /* Launch the captured graph on `stream`. */
 SLISTA_API int slista_batch_replay(slista_batch* batch, void* stream);
+/* Autotune a bound batch: for each column-pass bucket in turn, run the whole
+ * batch once per tile variant (after a warm-up run) and keep the fastest;
+ * records the choices in the table slista_autotune fills. Writes the variant
+ * of the buckets np = 1, 2, 4, 8 to variants[0..3] (0: no such bucket) if
+ * variants is not NULL. Overwrites the batch's outputs; releases a captured
+ * graph (capture again afterwards). Synchronises. */
+SLISTA_API int slista_batch_autotune(slista_batch* batch, void* stream, int* variants);
 SLISTA_API int slista_batch_destroy(slista_batch* batch);
 
 /* ---------------------------------------------------------------------------
@@ -247,6 +254,27 @@ SLISTA_API int slista_batch_destroy(slista_batch* batch);
 #define SLISTA_OPT_PERSIST_VARIANT 2
 
 SLISTA_API int slista_set_option(int option, int value);
+
+/* ---------------------------------------------------------------------------
+ * Autotuning of the persistent kernels' tile variant
+ *
+ * slista_autotune runs slista_forward_backward once per tile variant
+ * available for this dictionary (after one warm-up call each), times two
+ * calls of each with HIP events on `stream`, and records the fastest in a
+ * process-wide table keyed by (precision, column-pass bucket of m_pad,
+ * floor(log2 N)). While SLISTA_OPT_PERSIST_VARIANT is 0, later calls with a
+ * matching key use the recorded variant. Writes the chosen variant to *best
+ * and, if ms is not NULL, the mean milliseconds per call of variants 1..3 to
+ * ms[0..2] (0 for a variant that does not apply). Arguments as for
+ * slista_forward_backward (Z and dalpha are overwritten). Synchronises.
+ * slista_tune_save / slista_tune_load write / read the table as text, one
+ * "precision np log2N variant" record per line.
+ * ------------------------------------------------------------------------- */
+SLISTA_API int slista_autotune(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha,
+                               int T, int prec, int ckpt_every, float* Z, float* dalpha, void* ws, size_t ws_bytes,
+                               void* stream, int* best, double* ms);
+SLISTA_API int slista_tune_save(const char* path);
+SLISTA_API int slista_tune_load(const char* path);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing (diagnostics)

@@ -8,6 +8,9 @@ from .ops import (  # noqa: F401
     Batch,
     Dictionary,
     SlistaError,
+    autotune,
+    tune_load,
+    tune_save,
     backward,
     forward,
     forward_backward,

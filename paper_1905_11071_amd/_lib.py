@@ -40,6 +40,11 @@ SIGNATURES = {
     "slista_forward_backward": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _vp, _vp, _vp,
                                          _vp, _c_int, _vp, _size_t, _vp]),
     "slista_set_option": (_c_int, [_c_int, _c_int]),
+    "slista_autotune": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _c_int, _vp, _vp, _vp, _size_t, _vp,
+                                 ctypes.POINTER(_c_int), ctypes.POINTER(_c_double)]),
+    "slista_batch_autotune": (_c_int, [_vp, _vp, ctypes.POINTER(_c_int)]),
+    "slista_tune_save": (_c_int, [ctypes.c_char_p]),
+    "slista_tune_load": (_c_int, [ctypes.c_char_p]),
     "slista_batch_create": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_vp)]),
     "slista_batch_workspace_size": (_c_int, [_vp, ctypes.POINTER(_size_t)]),
     "slista_batch_bind": (_c_int, [_vp, _vp, _size_t, _vp]),

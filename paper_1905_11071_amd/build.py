@@ -36,9 +36,8 @@ SOURCES = ["kernels_gemm.hip", "kernels_misc.hip", "kernels_persist.hip", "api.c
 def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD_DIR, src + ".o")
-    cmd = [HIPCC] + COMMON
-    if src.endswith(".hip"):
-        cmd += [f"--offload-arch={ARCH}"] + DEVICE_FLAGS
+    # api.cpp holds host code only; the same target keeps hipcc's device pass on gfx950
+    cmd = [HIPCC] + COMMON + [f"--offload-arch={ARCH}"] + DEVICE_FLAGS
     cmd += ["-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -19,6 +19,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <cstring>
 #include <new>
 #include <string>
@@ -40,7 +42,7 @@ struct slista_batch {
   size_t total = 0;
   // buckets of the persistent kernels
   struct Bucket {
-    int np = 0, max_m_pad = 0, nwork = 0;
+    int np = 0, max_m_pad = 0, nwork = 0, variant = 0, rows_total = 0;
     std::vector<int> problems;
     size_t work_off = 0;                // index of the bucket's first work item
   };
@@ -49,6 +51,7 @@ struct slista_batch {
   // device tables (owned)
   slista::PersistArgs* d_args = nullptr;
   int2* d_work = nullptr;
+  size_t work_cap = 0;                  // entries d_work holds
   char* ws = nullptr;
   size_t ws_bytes = 0;
   hipGraph_t graph = nullptr;
@@ -126,6 +129,25 @@ struct ProfScope {
 int g_kernel_family = 0;
 // Tile variant of the persistent kernels (0 = default; see persist_rows).
 int g_persist_variant = 0;
+// Autotuned variants: (precision, column-pass bucket, floor(log2 N)) -> variant.
+std::map<std::tuple<int, int, int>, int> g_tuned;
+
+int log2_bucket(int N) {
+  int b = 0;
+  while (N > 1) {
+    N >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+// The tile variant a call uses: the forced one, else the tuned one, else 0
+// (the kernels' built-in default).
+int variant_for(int prec, int m_pad, int N) {
+  if (g_persist_variant != 0) return g_persist_variant;
+  const auto it = g_tuned.find(std::make_tuple(prec, slista::persist_np(m_pad), log2_bucket(N)));
+  return it == g_tuned.end() ? 0 : it->second;
+}
 
 constexpr int kMaxN = 1 << 26;
 constexpr int kMaxT = 100000;
@@ -222,7 +244,7 @@ const void* gram_for(const slista::Dict& d, int prec) {
 
 bool use_persist(const Run& r, int prec) {
   if (g_kernel_family == 1) return false;
-  return slista::persist_rows(prec, r.d->m_pad, g_persist_variant) > 0;
+  return slista::persist_rows(prec, r.d->m_pad, variant_for(prec, r.d->m_pad, r.N)) > 0;
 }
 
 slista::PersistArgs persist_args(const Run& r, int prec, const float* alpha, float lam) {
@@ -336,7 +358,7 @@ int run_forward(const Run& r, const float* X, float lam, const float* alpha, int
       a.dF_scalar = seed_dF;
       a.Vout = seed_vout;
     }
-    LAUNCH(kKFwd, r.s, slista::launch_persist(true, prec, a, r.s, g_persist_variant));
+    LAUNCH(kKFwd, r.s, slista::launch_persist(true, prec, a, r.s, variant_for(prec, r.d->m_pad, r.N)));
     if (loss && want_final) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
     return SLISTA_OK;
   }
@@ -384,7 +406,7 @@ int run_backward(const Run& r, float lam, const float* alpha, int prec, const fl
         a.F = F;
         a.Fd = r.Fd();
       }
-      LAUNCH(kKSeed, r.s, slista::launch_persist(true, prec, a, r.s, g_persist_variant));
+      LAUNCH(kKSeed, r.s, slista::launch_persist(true, prec, a, r.s, variant_for(prec, r.d->m_pad, r.N)));
       if (seed_fpart && loss) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
     }
     // With every iterate kept (k = 1) nothing is recomputed: one launch walks
@@ -399,16 +421,16 @@ int run_backward(const Run& r, float lam, const float* alpha, int prec, const fl
         f.t_begin = a0;
         f.t_end = b - 1;
         f.store_all = 1;
-        LAUNCH(kKFwd, r.s, slista::launch_persist(true, prec, f, r.s, g_persist_variant));
+        LAUNCH(kKFwd, r.s, slista::launch_persist(true, prec, f, r.s, variant_for(prec, r.d->m_pad, r.N)));
       }
       slista::PersistArgs bw = persist_args(r, prec, alpha, lam);
       bw.t_hi = b - 1;
       bw.t_lo = a0;
       bw.Vio = r.vbuf(0);
       bw.dpart = r.dpart();
-      LAUNCH(kKBwd, r.s, slista::launch_persist(false, prec, bw, r.s, g_persist_variant));
+      LAUNCH(kKBwd, r.s, slista::launch_persist(false, prec, bw, r.s, variant_for(prec, r.d->m_pad, r.N)));
     }
-    const int rows = slista::persist_rows(prec, r.d->m_pad, g_persist_variant);
+    const int rows = slista::persist_rows(prec, r.d->m_pad, variant_for(prec, r.d->m_pad, r.N));
     const int tiles = (N + rows - 1) / rows;
     LAUNCH(kKOther, r.s, slista::launch_reduce_dalpha(r.dpart(), T, r.L.P, tiles, tiles, alpha, dalpha, r.s));
     return SLISTA_OK;
@@ -562,12 +584,12 @@ int slista_dict_create(const float* D, int n, int m, void* stream, slista_dict**
             hipMalloc(&d.Gsb, mp * mp * sizeof(uint16_t)) == hipSuccess &&
             hipMalloc(&d.Gsf, mp * mp * sizeof(float)) == hipSuccess;
   if (!ok) {
-    hipFree(d.G32);
-    hipFree(d.Gb);
-    hipFree(d.Dt);
-    hipFree(d.pwork);
-    hipFree(d.Gsb);
-    hipFree(d.Gsf);
+    (void)hipFree(d.G32);
+    (void)hipFree(d.Gb);
+    (void)hipFree(d.Dt);
+    (void)hipFree(d.pwork);
+    (void)hipFree(d.Gsb);
+    (void)hipFree(d.Gsf);
     delete h;
     (void)hipGetLastError();
     return fail(SLISTA_ENOMEM, "hipMalloc of the Gram matrices (m_pad=%d) failed", d.m_pad);
@@ -586,12 +608,12 @@ int slista_dict_create(const float* D, int n, int m, void* stream, slista_dict**
 int slista_dict_destroy(slista_dict* dict) {
   if (!dict) return SLISTA_OK;
   (void)hipDeviceSynchronize();
-  hipFree(dict->d.G32);
-  hipFree(dict->d.Gb);
-  hipFree(dict->d.Dt);
-  hipFree(dict->d.pwork);
-  hipFree(dict->d.Gsb);
-  hipFree(dict->d.Gsf);
+  (void)hipFree(dict->d.G32);
+  (void)hipFree(dict->d.Gb);
+  (void)hipFree(dict->d.Dt);
+  (void)hipFree(dict->d.pwork);
+  (void)hipFree(dict->d.Gsb);
+  (void)hipFree(dict->d.Gsf);
   delete dict;
   return SLISTA_OK;
 }
@@ -711,11 +733,136 @@ int slista_forward_backward(const slista_dict* dict, const float* X, int N, floa
   return run_backward(r, lambda, alpha, prec, nullptr, nullptr, (float)(1.0 / N), dalpha, F || loss, F, loss);
 }
 
+int slista_autotune(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha, int T, int prec,
+                    int ckpt_every, float* Z, float* dalpha, void* ws, size_t ws_bytes, void* stream, int* best,
+                    double* ms) {
+  if (!best) return fail(SLISTA_EINVAL, "best is NULL");
+  if (!dict || N < 1 || T < 1 || ckpt_every < 1) return fail(SLISTA_EINVAL, "autotune needs N, T, ckpt_every >= 1");
+  if (g_prof.on) return fail(SLISTA_EINVAL, "kernel timing must be off while tuning");
+  const int nv = slista::persist_variants(dict->d.m_pad);
+  if (ms)
+    for (int v = 0; v < 3; ++v) ms[v] = 0.0;
+  if (nv == 0) {
+    *best = 0;
+    return SLISTA_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int saved_family = g_kernel_family, saved_variant = g_persist_variant;
+  g_kernel_family = 2;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int st = SLISTA_OK, bestv = 1;
+  double bestms = 1e300;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    st = fail(SLISTA_EHIP, "hipEventCreate failed");
+  }
+  for (int v = 1; v <= nv && st == SLISTA_OK; ++v) {
+    g_persist_variant = v;
+    st = slista_forward_backward(dict, X, N, lambda, alpha, T, prec, Z, nullptr, nullptr, dalpha, ckpt_every, ws,
+                                 ws_bytes, stream);
+    if (st != SLISTA_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { st = fail(SLISTA_EHIP, "hipEventRecord failed"); break; }
+    for (int rep = 0; rep < 2 && st == SLISTA_OK; ++rep)
+      st = slista_forward_backward(dict, X, N, lambda, alpha, T, prec, Z, nullptr, nullptr, dalpha, ckpt_every, ws,
+                                   ws_bytes, stream);
+    if (st != SLISTA_OK) break;
+    float t = 0.f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+      st = fail(SLISTA_EHIP, "event timing failed");
+      break;
+    }
+    const double m = t / 2.0;
+    if (ms) ms[v - 1] = m;
+    if (m < bestms) {
+      bestms = m;
+      bestv = v;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  g_kernel_family = saved_family;
+  g_persist_variant = saved_variant;
+  if (st != SLISTA_OK) return st;
+  g_tuned[std::make_tuple(prec, slista::persist_np(dict->d.m_pad), log2_bucket(N))] = bestv;
+  *best = bestv;
+  return SLISTA_OK;
+}
+
+int slista_tune_save(const char* path) {
+  if (!path) return fail(SLISTA_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(SLISTA_EINVAL, "cannot open %s for writing", path);
+  for (const auto& kv : g_tuned)
+    std::fprintf(f, "%d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), kv.second);
+  std::fclose(f);
+  return SLISTA_OK;
+}
+
+int slista_tune_load(const char* path) {
+  if (!path) return fail(SLISTA_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(SLISTA_EINVAL, "cannot open %s", path);
+  int prec, np, nb, v, n = 0;
+  while (std::fscanf(f, "%d %d %d %d", &prec, &np, &nb, &v) == 4) {
+    if ((prec == SLISTA_FP32 || prec == SLISTA_BF16) && (np == 1 || np == 2 || np == 4 || np == 8) && nb >= 0 &&
+        nb < 31 && v >= 1 && v <= 3) {
+      g_tuned[std::make_tuple(prec, np, nb)] = v;
+      ++n;
+    }
+  }
+  std::fclose(f);
+  (void)n;
+  return SLISTA_OK;
+}
+
 static void batch_release_graph(slista_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
+}
+
+// Tile rows and work count of bucket `bi` for tile variant v.
+static void batch_set_variant(slista_batch* b, size_t bi, int v) {
+  slista_batch::Bucket& bk = b->buckets[bi];
+  bk.variant = slista::persist_resolve_variant(b->prec, bk.max_m_pad, v);
+  bk.nwork = 0;
+  for (int p : bk.problems) {
+    b->rows[p] = slista::persist_rows(b->prec, b->probs[p].dict->d.m_pad, v);
+    bk.nwork += (b->probs[p].N + b->rows[p] - 1) / b->rows[p];
+  }
+}
+
+// (problem, tile) work lists of all buckets, uploaded to d_work; synchronises.
+static int batch_upload_work(slista_batch* b, hipStream_t s) {
+  std::vector<int2> work;
+  for (auto& bk : b->buckets) {
+    bk.work_off = work.size();
+    // longest tiles first: larger m_pad, then problem order
+    std::vector<int> order = bk.problems;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return b->probs[x].dict->d.m_pad > b->probs[y].dict->d.m_pad;
+    });
+    for (int p : order) {
+      const int tiles = (b->probs[p].N + b->rows[p] - 1) / b->rows[p];
+      for (int t = 0; t < tiles; ++t) work.push_back(make_int2(p, t));
+    }
+  }
+  if (work.size() > b->work_cap) {
+    // capacity for the smallest tile any variant uses (16 rows)
+    size_t cap = 0;
+    for (const auto& q : b->probs) cap += (q.N + 15) / 16;
+    cap = std::max(cap, work.size());
+    HIP_TRY(hipStreamSynchronize(s));
+    if (b->d_work) HIP_TRY(hipFree(b->d_work));
+    b->d_work = nullptr;
+    b->work_cap = 0;
+    HIP_TRY(hipMalloc(&b->d_work, sizeof(int2) * cap));
+    b->work_cap = cap;
+  }
+  HIP_TRY(hipMemcpyAsync(b->d_work, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return SLISTA_OK;
 }
 
 int slista_batch_create(const slista_problem* problems, int P, int T, int prec, int ckpt_every, slista_batch** out) {
@@ -746,19 +893,24 @@ int slista_batch_create(const slista_problem* problems, int P, int T, int prec, 
   for (int p = 0; p < P; ++p) {
     b->offset.push_back(off);
     off += align256(make_layout(problems[p].dict->d, problems[p].N, T, ckpt_every).total);
-    b->rows.push_back(slista::persist_rows(prec, problems[p].dict->d.m_pad, b->variant));
   }
   b->total = off;
+  b->rows.assign(P, 0);
   for (int np : {8, 4, 2, 1}) {
     slista_batch::Bucket bk;
     bk.np = np;
+    long long rows_total = 0;
     for (int p = 0; p < P; ++p)
       if (slista::persist_np(problems[p].dict->d.m_pad) == np) {
         bk.problems.push_back(p);
         bk.max_m_pad = std::max(bk.max_m_pad, problems[p].dict->d.m_pad);
-        bk.nwork += (problems[p].N + b->rows[p] - 1) / b->rows[p];
+        rows_total += problems[p].N;
       }
-    if (!bk.problems.empty()) b->buckets.push_back(bk);
+    if (bk.problems.empty()) continue;
+    bk.rows_total = (int)std::min<long long>(rows_total, kMaxN);
+    b->buckets.push_back(bk);
+    // one tile variant per bucket launch: forced, tuned for the bucket's rows, or default
+    batch_set_variant(b, b->buckets.size() - 1, variant_for(prec, bk.max_m_pad, bk.rows_total));
   }
   *out = b;
   return SLISTA_OK;
@@ -798,27 +950,9 @@ int slista_batch_bind(slista_batch* b, void* ws, size_t ws_bytes, void* stream) 
     a.mode_mask = slista::kModeF | slista::kModeSeed;
     args[p] = a;
   }
-  std::vector<int2> work;
-  for (auto& bk : b->buckets) {
-    bk.work_off = work.size();
-    // longest tiles first: larger m_pad, then problem order
-    std::vector<int> order = bk.problems;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-      return b->probs[x].dict->d.m_pad > b->probs[y].dict->d.m_pad;
-    });
-    for (int p : order) {
-      const int tiles = (b->probs[p].N + b->rows[p] - 1) / b->rows[p];
-      for (int t = 0; t < tiles; ++t) work.push_back(make_int2(p, t));
-    }
-  }
-  if (!b->d_args) {
-    HIP_TRY(hipMalloc(&b->d_args, sizeof(slista::PersistArgs) * b->P));
-    HIP_TRY(hipMalloc(&b->d_work, sizeof(int2) * work.size()));
-  }
+  if (!b->d_args) HIP_TRY(hipMalloc(&b->d_args, sizeof(slista::PersistArgs) * b->P));
   HIP_TRY(hipMemcpyAsync(b->d_args, args.data(), sizeof(slista::PersistArgs) * b->P, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(b->d_work, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  return SLISTA_OK;
+  return batch_upload_work(b, s);
 }
 
 int slista_batch_run(slista_batch* b, void* stream) {
@@ -831,7 +965,7 @@ int slista_batch_run(slista_batch* b, void* stream) {
   auto phase = [&](bool fwd, slista::PersistPhase ph) -> int {
     for (const auto& bk : b->buckets)
       LAUNCH(fwd ? kKFwd : kKBwd, s,
-             slista::launch_persist_batched(fwd, prec, bk.np, b->variant, b->d_args, b->d_work + bk.work_off,
+             slista::launch_persist_batched(fwd, prec, bk.np, bk.variant, b->d_args, b->d_work + bk.work_off,
                                             bk.nwork, bk.max_m_pad, ph, s));
     return SLISTA_OK;
   };
@@ -856,6 +990,58 @@ int slista_batch_run(slista_batch* b, void* stream) {
     const int tiles = (r.N + b->rows[p] - 1) / b->rows[p];
     LAUNCH(kKOther, s, slista::launch_reduce_dalpha(r.dpart(), T, r.L.P, tiles, tiles, b->probs[p].alpha,
                                                     b->probs[p].dalpha, s));
+  }
+  return SLISTA_OK;
+}
+
+int slista_batch_autotune(slista_batch* b, void* stream, int* variants) {
+  if (!b || !b->ws) return fail(SLISTA_EINVAL, "batch is NULL or not bound to a workspace");
+  if (g_prof.on) return fail(SLISTA_EINVAL, "kernel timing must be off while tuning");
+  hipStream_t s = (hipStream_t)stream;
+  batch_release_graph(b);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(SLISTA_EHIP, "hipEventCreate failed");
+  }
+  int st = SLISTA_OK;
+  // one bucket at a time, the others at their current variant
+  for (size_t bi = 0; bi < b->buckets.size() && st == SLISTA_OK; ++bi) {
+    const int nv = slista::persist_variants(b->buckets[bi].max_m_pad);
+    if (nv < 2) continue;
+    int bestv = b->buckets[bi].variant;
+    double bestms = 1e300;
+    for (int v = 1; v <= nv && st == SLISTA_OK; ++v) {
+      batch_set_variant(b, bi, v);
+      if ((st = batch_upload_work(b, s)) != SLISTA_OK) break;
+      if ((st = slista_batch_run(b, stream)) != SLISTA_OK) break;  // warm-up
+      if (hipEventRecord(e0, s) != hipSuccess) { st = fail(SLISTA_EHIP, "hipEventRecord failed"); break; }
+      if ((st = slista_batch_run(b, stream)) != SLISTA_OK) break;
+      float t = 0.f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+        st = fail(SLISTA_EHIP, "event timing failed");
+        break;
+      }
+      if (t < bestms) {
+        bestms = t;
+        bestv = v;
+      }
+    }
+    batch_set_variant(b, bi, bestv);
+    if (st == SLISTA_OK) {
+      const auto& bk = b->buckets[bi];
+      g_tuned[std::make_tuple(b->prec, bk.np, log2_bucket(bk.rows_total))] = bestv;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const int st2 = batch_upload_work(b, s);
+  if (st != SLISTA_OK) return st;
+  if (st2 != SLISTA_OK) return st2;
+  if (variants) {
+    for (int i = 0; i < 4; ++i) variants[i] = 0;
+    for (const auto& bk : b->buckets) variants[bk.np == 1 ? 0 : bk.np == 2 ? 1 : bk.np == 4 ? 2 : 3] = bk.variant;
   }
   return SLISTA_OK;
 }
@@ -889,8 +1075,8 @@ int slista_batch_destroy(slista_batch* b) {
   if (!b) return SLISTA_OK;
   (void)hipDeviceSynchronize();
   batch_release_graph(b);
-  hipFree(b->d_args);
-  hipFree(b->d_work);
+  (void)hipFree(b->d_args);
+  (void)hipFree(b->d_work);
   delete b;
   return SLISTA_OK;
 }

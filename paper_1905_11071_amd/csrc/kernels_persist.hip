@@ -596,6 +596,11 @@ int default_variant(int prec, int m_pad) {
   return np_of(m_pad) <= 4 ? 2 : 1;
 }
 
+int persist_resolve_variant(int prec, int m_pad, int variant) {
+  if (np_of(m_pad) == 0) return 0;
+  return (variant <= 0 || variant > persist_variants(m_pad)) ? default_variant(prec, m_pad) : variant;
+}
+
 int persist_rows(int prec, int m_pad, int variant) {
   const int np = np_of(m_pad);
   if (np == 0) return 0;

@@ -51,6 +51,8 @@ struct PersistPhase {
 int persist_variants(int m_pad);
 // Rows per tile for (prec, m_pad, variant); variant 0 = the default one.
 int persist_rows(int prec, int m_pad, int variant);
+// The variant a launch with this request runs (0 or out of range -> default).
+int persist_resolve_variant(int prec, int m_pad, int variant);
 hipError_t launch_persist(bool fwd, int prec, const PersistArgs& a, hipStream_t s, int variant);
 hipError_t launch_swizzle(const float* G32, int m_pad, uint16_t* Gsb, float* Gsf, hipStream_t s);
 // Column-pass bucket of m_pad (1, 2, 4, 8; 0 = not handled).

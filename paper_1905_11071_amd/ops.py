@@ -176,6 +176,32 @@ def forward_backward(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Te
     return Z, F, loss, dalpha, ws
 
 
+def autotune(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, prec="fp32", ckpt_every: int = 1):
+    """Time every tile variant of the persistent kernels on this problem and
+    make the fastest the default for its (precision, m, N) class. Returns
+    (best variant, [ms per call of variants 1..3])."""
+    X, alpha = _check_inputs(d, X, alpha)
+    N, T = int(X.shape[0]), int(alpha.shape[0])
+    p = _prec(prec)
+    ws = d.workspace(N, T, p, ckpt_every)
+    Z = torch.empty(N, d.m, device=d.device, dtype=torch.float32)
+    da = torch.empty(T, device=d.device, dtype=torch.float32)
+    best = ctypes.c_int()
+    ms = (ctypes.c_double * 3)()
+    check(lib().slista_autotune(d.handle, X.data_ptr(), N, float(lam), alpha.data_ptr(), T, p, ckpt_every,
+                                Z.data_ptr(), da.data_ptr(), ws.data_ptr(), ws.numel(), _stream(d.device),
+                                ctypes.byref(best), ms))
+    return best.value, list(ms)
+
+
+def tune_save(path: str) -> None:
+    check(lib().slista_tune_save(path.encode()))
+
+
+def tune_load(path: str) -> None:
+    check(lib().slista_tune_load(path.encode()))
+
+
 class Batch:
     """Forward + backward of many independent Lasso problems (own dictionary,
     n, m, N, lambda and steps; common T) in grouped persistent launches, with
@@ -231,6 +257,13 @@ class Batch:
 
     def replay(self) -> None:
         check(lib().slista_batch_replay(self._h, _stream(self.device)))
+
+    def autotune(self) -> dict:
+        """Pick each bucket's tile variant by timing whole-batch runs; returns
+        {column passes: variant}. Drops a captured graph."""
+        v = (ctypes.c_int * 4)()
+        check(lib().slista_batch_autotune(self._h, _stream(self.device), v))
+        return {np_: v[i] for i, np_ in enumerate((1, 2, 4, 8)) if v[i]}
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -35,6 +35,7 @@ __all__ = [
     "make_binf_problem",
     "perturbed_steps",
     "CONFIGS",
+    "UNEVEN",
     "uneven_problem_specs",
 ]
 
@@ -125,6 +126,9 @@ CONFIGS: Dict[str, dict] = {
     # Precision study, 256x1024, N=65536, T=50, forward+backward.
     "prec_256x1024": dict(n=256, m=1024, N=65_536, T=50, p=0.02, sigma=0.0, lam_frac=0.05, seed=1004),
 }
+
+# The uneven batch (sizes from uneven_problem_specs): common depth and checkpoint spacing.
+UNEVEN: dict = dict(P=64, T=100, ckpt_every=10, seed=1005)
 
 
 def uneven_problem_specs(P: int = 64, seed: int = 1005, n_lo: int = 32, n_hi: int = 512,

@@ -105,3 +105,33 @@ def test_batch_gradients_vs_oracle(sl):
         _say(f"problem {i} n={pb.n} m={pb.m} N={pb.N}: dalpha rel err {err:.2e}, loss rel err {lerr:.2e}")
         assert err <= 1e-5 and lerr <= 1e-5
     b.close()
+
+
+def test_batch_autotune_keeps_results(sl):
+    """Tuning a batch changes only its tile shapes: the outputs stay the same
+    bits, before and after graph capture."""
+    T = 5
+    probs = _problems(SPECS, T, 1000)
+    dicts = [sl.Dictionary(_gpu(pb.D)) for pb, _ in probs]
+    inputs = [(d, _gpu(pb.X), pb.lam, _gpu(a)) for d, (pb, a) in zip(dicts, probs)]
+    b = sl.Batch(inputs, prec="bf16", ckpt_every=2)
+    b.run()
+    torch.cuda.synchronize()
+    ref = [(z.cpu().numpy(), da.cpu().numpy()) for z, da in zip(b.Z, b.dalpha)]
+    chosen = b.autotune()
+    _say(f"tuned variants by column passes: {chosen}")
+    assert set(chosen) == {1, 2, 4, 8} and all(v in (1, 2, 3) for v in chosen.values())
+    b.run()
+    torch.cuda.synchronize()
+    for i, (zr, dr) in enumerate(ref):
+        assert np.array_equal(b.Z[i].cpu().numpy(), zr), i
+        assert np.array_equal(b.dalpha[i].cpu().numpy(), dr), i
+    b.capture()
+    for z in b.Z:
+        z.zero_()
+    b.replay()
+    torch.cuda.synchronize()
+    for i, (zr, dr) in enumerate(ref):
+        assert np.array_equal(b.Z[i].cpu().numpy(), zr), i
+        assert np.array_equal(b.dalpha[i].cpu().numpy(), dr), i
+    b.close()

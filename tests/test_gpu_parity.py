@@ -369,3 +369,32 @@ def test_objective_entry_point(sl):
         Fo = oracle.objective(pb.D, pb.X, Z, pb.lam)
         np.testing.assert_allclose(Fg, Fo, rtol=2e-5, atol=1e-6)
     d.close()
+
+
+def test_autotune_keeps_results(sl, tmp_path):
+    """The autotuner times every tile variant on the problem and makes the
+    fastest the default for its class; the variants compute the same bits,
+    so results before and after tuning agree exactly. The tuning table
+    survives a save / load round trip."""
+    pb = synth.make_problem(64, 256, 3000, 0.05, 0.01, 0.1, seed=23)
+    T = 6
+    alpha = _gpu(synth.perturbed_steps(oracle.lipschitz(pb.D), T, seed=4))
+    d = sl.Dictionary(_gpu(pb.D))
+    X = _gpu(pb.X)
+    for prec in ("bf16", "fp32"):
+        Z0, F0, l0, da0, _ = sl.forward_backward(d, X, pb.lam, alpha, prec=prec)
+        best, ms = sl.autotune(d, X, pb.lam, alpha, prec=prec)
+        _say(f"{prec}: best variant {best}, ms by variant {ms}")
+        assert best in (1, 2, 3)
+        timed = [x for x in ms if x > 0]
+        assert len(timed) >= 2 and ms[best - 1] == min(timed)
+        Z1, F1, l1, da1, _ = sl.forward_backward(d, X, pb.lam, alpha, prec=prec)
+        assert np.array_equal(Z0.cpu().numpy(), Z1.cpu().numpy())
+        assert np.array_equal(da0.cpu().numpy(), da1.cpu().numpy())
+        assert l0.item() == l1.item()
+    path = str(tmp_path / "tune.txt")
+    sl.tune_save(path)
+    recs = [list(map(int, ln.split())) for ln in open(path).read().splitlines() if ln.strip()]
+    assert any(r[0] == 1 and r[1] == 1 and r[2] == 11 for r in recs), recs  # bf16, one pass, log2(3000)
+    sl.tune_load(path)
+    d.close()
