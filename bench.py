@@ -30,19 +30,19 @@ PEAK = {"bf16_tflops": 2500.0, "fp32_tflops": 157.3, "hbm_gbs": 8000.0}
 def launch_work(kind: str, N: int, m: int, T: int):
     """Algorithmic flops and HBM bytes of one launch of a persistent kernel.
 
-    Units: one contraction of one sample costs 2 m^2 flops (P = Z G); one
-    layer of one sample moves 8 m bytes (forward: read c, write the kept
-    iterate; backward: read z^t and z^{t+1}).
+    Units: one contraction of one sample costs 2 m^2 flops (P = Z G). One
+    forward layer of one sample moves 8 m bytes (read c, write the kept
+    iterate); one backward layer reads the kept iterate z^t once (4 m bytes).
       forward launch (all T layers + the final contraction for F and the
         seed): T contractions (layer 0 has none since z^0 = 0, the final one
         is G z^T); bytes 4 m N (2T + 3): T reads of c and T iterate writes,
         plus the final c read, the copy of z^T and the seed v^{T-1}.
-      backward launch (all T layers): T - 1 contractions; bytes 4 m N * 2T:
-        z^{t+1} for every t, z^t for t >= 1, and the seed read."""
+      backward launch (all T layers): T - 1 contractions; bytes 4 m N (T + 1):
+        the seed, z^T, and z^t for 1 <= t < T."""
     if kind == "forward_layer":
         return 2.0 * N * m * m * T, 4.0 * m * N * (2 * T + 3)
     if kind == "backward_layer":
-        return 2.0 * N * m * m * (T - 1), 4.0 * m * N * 2 * T
+        return 2.0 * N * m * m * (T - 1), 4.0 * m * N * (T + 1)
     raise ValueError(kind)
 
 

@@ -249,8 +249,13 @@ SLISTA_API int slista_batch_destroy(slista_batch* batch);
  *   1 tiles of 64 samples (32 for FP32 with m_pad > 512, 16 above 1024),
  *     one workgroup per CU;
  *   2 tiles of half that many samples, two workgroups per CU (m_pad <= 1024);
- *   3 the tiles of variant 1 in one 8-wave workgroup (m_pad <= 1024).
- * Results are bitwise identical across variants. */
+ *   3 the tiles of variant 1 in one 8-wave workgroup, rows split in two
+ *     (m_pad <= 1024);
+ *   4 the tiles of variant 1 in one 8-wave workgroup, columns split in
+ *     eight 32-column slabs.
+ * Codes Z are bitwise identical across variants; F and dalpha differ only
+ * by the grouping of their partial sums. A variant that does not exist for
+ * the dictionary's m_pad falls back to the default. */
 #define SLISTA_OPT_PERSIST_VARIANT 2
 
 SLISTA_API int slista_set_option(int option, int value);
@@ -264,8 +269,8 @@ SLISTA_API int slista_set_option(int option, int value);
  * process-wide table keyed by (precision, column-pass bucket of m_pad,
  * floor(log2 N)). While SLISTA_OPT_PERSIST_VARIANT is 0, later calls with a
  * matching key use the recorded variant. Writes the chosen variant to *best
- * and, if ms is not NULL, the mean milliseconds per call of variants 1..3 to
- * ms[0..2] (0 for a variant that does not apply). Arguments as for
+ * and, if ms is not NULL, the mean milliseconds per call of variants 1..4 to
+ * ms[0..3] (0 for a variant that does not apply). Arguments as for
  * slista_forward_backward (Z and dalpha are overwritten). Synchronises.
  * slista_tune_save / slista_tune_load write / read the table as text, one
  * "precision np log2N variant" record per line.

@@ -30,7 +30,8 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-fvisibility=hidden", "-Wall", "-Wno-unused-result",
           f"-I{os.path.join(ROOT, 'include')}"]
 
-SOURCES = ["kernels_gemm.hip", "kernels_misc.hip", "kernels_persist.hip", "api.cpp"]
+SOURCES = ["kernels_persist_bf16.hip", "kernels_persist_f32.hip", "kernels_gemm.hip", "kernels_misc.hip",
+           "kernels_persist.hip", "api.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -503,7 +503,8 @@ int slista_set_option(int option, int value) {
     return SLISTA_OK;
   }
   if (option == SLISTA_OPT_PERSIST_VARIANT) {
-    if (value < 0 || value > 3) return fail(SLISTA_EINVAL, "tile variant %d outside [0, 3]", value);
+    if (value < 0 || value > slista::kPersistMaxVariant)
+      return fail(SLISTA_EINVAL, "tile variant %d outside [0, %d]", value, slista::kPersistMaxVariant);
     g_persist_variant = value;
     return SLISTA_OK;
   }
@@ -739,9 +740,10 @@ int slista_autotune(const slista_dict* dict, const float* X, int N, float lambda
   if (!best) return fail(SLISTA_EINVAL, "best is NULL");
   if (!dict || N < 1 || T < 1 || ckpt_every < 1) return fail(SLISTA_EINVAL, "autotune needs N, T, ckpt_every >= 1");
   if (g_prof.on) return fail(SLISTA_EINVAL, "kernel timing must be off while tuning");
-  const int nv = slista::persist_variants(dict->d.m_pad);
+  int nv = 0;
+  for (int v = 1; v <= slista::kPersistMaxVariant; ++v) nv += slista::persist_has_variant(dict->d.m_pad, v);
   if (ms)
-    for (int v = 0; v < 3; ++v) ms[v] = 0.0;
+    for (int v = 0; v < slista::kPersistMaxVariant; ++v) ms[v] = 0.0;
   if (nv == 0) {
     *best = 0;
     return SLISTA_OK;
@@ -755,7 +757,8 @@ int slista_autotune(const slista_dict* dict, const float* X, int N, float lambda
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     st = fail(SLISTA_EHIP, "hipEventCreate failed");
   }
-  for (int v = 1; v <= nv && st == SLISTA_OK; ++v) {
+  for (int v = 1; v <= slista::kPersistMaxVariant && st == SLISTA_OK; ++v) {
+    if (!slista::persist_has_variant(dict->d.m_pad, v)) continue;
     g_persist_variant = v;
     st = slista_forward_backward(dict, X, N, lambda, alpha, T, prec, Z, nullptr, nullptr, dalpha, ckpt_every, ws,
                                  ws_bytes, stream);
@@ -805,7 +808,7 @@ int slista_tune_load(const char* path) {
   int prec, np, nb, v, n = 0;
   while (std::fscanf(f, "%d %d %d %d", &prec, &np, &nb, &v) == 4) {
     if ((prec == SLISTA_FP32 || prec == SLISTA_BF16) && (np == 1 || np == 2 || np == 4 || np == 8) && nb >= 0 &&
-        nb < 31 && v >= 1 && v <= 3) {
+        nb < 31 && v >= 1 && v <= slista::kPersistMaxVariant) {
       g_tuned[std::make_tuple(prec, np, nb)] = v;
       ++n;
     }
@@ -1007,11 +1010,14 @@ int slista_batch_autotune(slista_batch* b, void* stream, int* variants) {
   int st = SLISTA_OK;
   // one bucket at a time, the others at their current variant
   for (size_t bi = 0; bi < b->buckets.size() && st == SLISTA_OK; ++bi) {
-    const int nv = slista::persist_variants(b->buckets[bi].max_m_pad);
+    const int mp = b->buckets[bi].max_m_pad;
+    int nv = 0;
+    for (int v = 1; v <= slista::kPersistMaxVariant; ++v) nv += slista::persist_has_variant(mp, v);
     if (nv < 2) continue;
     int bestv = b->buckets[bi].variant;
     double bestms = 1e300;
-    for (int v = 1; v <= nv && st == SLISTA_OK; ++v) {
+    for (int v = 1; v <= slista::kPersistMaxVariant && st == SLISTA_OK; ++v) {
+      if (!slista::persist_has_variant(mp, v)) continue;
       batch_set_variant(b, bi, v);
       if ((st = batch_upload_work(b, s)) != SLISTA_OK) break;
       if ((st = slista_batch_run(b, stream)) != SLISTA_OK) break;  // warm-up

@@ -1,514 +1,12 @@
-// Persistent Step-LISTA kernels: one workgroup carries a tile of R samples
-// through a whole range of layers (Section 4, Eq. (14)), forward or back.
-//
-// On-chip state of a tile (4 wave64s, 1 workgroup per CU for the large shapes):
-//   LDS        the tile's iterate in the contraction's precision (BF16 or
-//              FP32), [R][m_pad], the A operand of P = Z G for every layer;
-//   registers  the FP32 master iterate (forward: z; backward: the adjoint v)
-//              in the MFMA accumulator layout, so the step, the threshold and
-//              the objective never re-read z from memory.
-// G streams from L2 in a fragment-ordered copy built with the dictionary:
-// the 16 x 32 (BF16) or 16 x 16 (FP32) fragment a wave needs for one K step
-// is 1 KiB contiguous, one 16-byte load per lane, issued PF steps ahead.
-// Each wave owns 64-column slabs of the output (4 slabs = one pass of 256
-// columns); the tile's rows are shared by all waves through LDS.
-//
-// Per sample and layer the forward reads c = D^T x (4 m bytes) and writes
-// the kept iterate (4 m bytes); the backward reads z^t and z^{t+1}.
-//
-// The K order, the per-lane K assignment and every epilogue expression are
-// the same as in the per-layer kernel (kernels_gemm.hip), so both give
-// bitwise-identical iterates.
+// Persistent Step-LISTA kernels: tile policy, dispatch and the
+// fragment-ordered copies of G. The kernels themselves are in
+// persist_body.hpp, instantiated per precision in kernels_persist_bf16.hip
+// and kernels_persist_f32.hip.
 #include "common.hpp"
 #include "persist.hpp"
 
 namespace slista {
 namespace {
-
-constexpr int PT = 256;  // threads per workgroup
-
-template <int P> struct Elem;
-template <> struct Elem<kF32> { static constexpr int bytes = 4; };
-template <> struct Elem<kBF16> { static constexpr int bytes = 2; };
-
-__device__ __forceinline__ float soft_thresh(float u, float th) {
-  const float au = fabsf(u) - th;
-  return au > 0.f ? copysignf(au, u) : 0.f;
-}
-__device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
-
-// Raw buffer descriptors (CDNA): a uniform base and byte range in SGPRs, so
-// each access needs one per-lane VGPR offset; the row part of an offset goes
-// into the SGPR soffset and the column part into the instruction's immediate.
-constexpr int kRsrcWord3 = 0x00020000;
-typedef __amdgpu_buffer_rsrc_t Rsrc;
-__device__ __forceinline__ Rsrc make_rsrc(const void* base, size_t bytes) {
-  const int n = bytes > 0x7fffffffu ? 0x7fffffff : (int)bytes;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, kRsrcWord3);
-}
-// The b32 builtins move raw 32-bit patterns (unsigned int): bit-cast, never
-// convert. Stores of per-sample results (the tape, outputs) are streaming
-// (cache policy nt): the tape is read back only by the backward pass, long
-// after. Loads stay temporal: a tile re-reads its rows of c every layer and
-// the backward reads each kept iterate at two consecutive layers, and those
-// re-reads hit in the caches (non-temporal loads measured 1.5x slower).
-constexpr int kNT = 2;
-__device__ __forceinline__ float bload(Rsrc r, int voff, int soff) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-__device__ __forceinline__ void bstore(float v, Rsrc r, int voff, int soff) {
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, kNT);
-}
-
-__device__ __forceinline__ float* slot_ptr(const PersistArgs& g, int t) {
-  const int k = g.k;
-  if (t % k == 0 || t == g.T) return (float*)(g.ckpt + (size_t)((t + k - 1) / k - 1) * g.zbytes);
-  return (float*)(g.seg + (size_t)(t % k - 1) * g.zbytes);
-}
-
-template <int P>
-__device__ __forceinline__ void mfma_pair(f32x4& acc, const uint4& a, const uint4& b) {
-  if constexpr (P == kF32) {
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
-  } else {
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
-                                                   acc, 0, 0, 0);
-  }
-}
-
-// One K step: prefetch the G fragments of step kc + PF - 1 and the A
-// fragments of step kc + 1 (both clamped to the last step, so the loads never
-// need a branch), then the FM x 4 MFMAs of step kc.
-template <int P, int FM, int PF, int J>
-__device__ __forceinline__ void k_step(const Rsrc& rg, int lo, int KC, const char* arow, int rowb, int kc,
-                                       uint4 (&bq)[PF][4], uint4 (&av)[2][FM], f32x4 (&acc)[FM][4]) {
-  const int nk = min(kc + PF - 1, KC - 1);
-#pragma unroll
-  for (int f = 0; f < 4; ++f)
-    bq[(J + PF - 1) % PF][f] =
-        __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rg, lo, (f * KC + nk) * 1024, 0));
-  constexpr int JB = J % PF;  // slot holding step kc
-  const int na = min(kc + 1, KC - 1);
-#pragma unroll
-  for (int fm = 0; fm < FM; ++fm) av[(J & 1) ^ 1][fm] = *(const uint4*)(arow + fm * 16 * rowb + na * 64);
-  if constexpr (P == kF32) {
-    // 4 MFMAs per (fm, f) pair; the K sub-step e is the outer loop so that
-    // consecutive MFMAs update independent accumulators (same order per acc)
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-          const uint4& a = av[J & 1][fm];
-          const uint4& b = bq[JB][f];
-          const uint32_t ae = e == 0 ? a.x : e == 1 ? a.y : e == 2 ? a.z : a.w;
-          const uint32_t be = e == 0 ? b.x : e == 1 ? b.y : e == 2 ? b.z : b.w;
-          acc[fm][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(ae), __uint_as_float(be), acc[fm][f], 0, 0, 0);
-        }
-  } else {
-#pragma unroll
-    for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-      for (int f = 0; f < 4; ++f) mfma_pair<P>(acc[fm][f], av[J & 1][fm], bq[JB][f]);
-  }
-}
-
-// acc[fm][f] = sum_k A[16 fm + row][k] G[k][64 slab + 16 f + col] over the
-// whole K range, A from the LDS tile, G fragments from global memory issued
-// PF - 1 K steps ahead (PF = 2 or 4).
-template <int P, int FM, int PF>
-__device__ __forceinline__ void contract(const PersistArgs& g, const char* lds, int rowb, int slab, int lane,
-                                         f32x4 (&acc)[FM][4]) {
-  const int lr = lane & 15, lg = lane >> 4;
-  const int KC = g.KC;
-  // the 4 * KC fragments of this slab: 4 KC KiB starting at fragment (4 slab, 0)
-  const Rsrc rg = make_rsrc((const char*)g.Gsw + (size_t)(4 * slab) * KC * 1024, (size_t)4 * KC * 1024);
-  const int lo = lane * 16;
-#pragma unroll
-  for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-    for (int f = 0; f < 4; ++f) acc[fm][f] = f32x4{0.f, 0.f, 0.f, 0.f};
-  uint4 bq[PF][4];
-#pragma unroll
-  for (int i = 0; i < PF - 1; ++i)
-#pragma unroll
-    for (int f = 0; f < 4; ++f)
-      bq[i][f] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rg, lo, (f * KC + min(i, KC - 1)) * 1024, 0));
-  const char* arow = lds + lr * rowb + 16 * lg;
-  uint4 av[2][FM];
-#pragma unroll
-  for (int fm = 0; fm < FM; ++fm) av[0][fm] = *(const uint4*)(arow + fm * 16 * rowb);
-  // steady state, 4 steps per iteration (a multiple of PF and of 2, so step
-  // kc uses bq[kc % PF] = bq[J % PF] and av[kc & 1] = av[J & 1])
-  const int KF = KC - KC % 4;
-  for (int kc0 = 0; kc0 < KF; kc0 += 4) {
-    k_step<P, FM, PF, 0>(rg, lo, KC, arow, rowb, kc0 + 0, bq, av, acc);
-    k_step<P, FM, PF, 1>(rg, lo, KC, arow, rowb, kc0 + 1, bq, av, acc);
-    k_step<P, FM, PF, 2>(rg, lo, KC, arow, rowb, kc0 + 2, bq, av, acc);
-    k_step<P, FM, PF, 3>(rg, lo, KC, arow, rowb, kc0 + 3, bq, av, acc);
-  }
-  // tail (KC is even, so at most 2 steps; BF16 with m_pad = 64 mod 128)
-  if (KF < KC) {
-    k_step<P, FM, PF, 0>(rg, lo, KC, arow, rowb, KF + 0, bq, av, acc);
-    k_step<P, FM, PF, 1>(rg, lo, KC, arow, rowb, KF + 1, bq, av, acc);
-  }
-}
-
-// Master registers -> LDS tile (the next contraction's A operand).
-template <int P, int FM, int NP>
-__device__ __forceinline__ void master_to_lds(const float (&zm)[NP][FM][4][4], char* lds, int rowb, int npass,
-                                              int m_pad, int wave, int lane) {
-  const int lr = lane & 15, lg = lane >> 4;
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    const int slab = 4 * p + wave;
-    if (p < npass && slab * 64 < m_pad) {
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int f = 0; f < 4; ++f)
-#pragma unroll
-          for (int r4 = 0; r4 < 4; ++r4) {
-            const int row = 16 * fm + 4 * lg + r4, col = 64 * slab + 16 * f + lr;
-            char* dst = lds + row * rowb + col * Elem<P>::bytes;
-            if constexpr (P == kF32)
-              *(float*)dst = zm[p][fm][f][r4];
-            else
-              *(__bf16*)dst = (__bf16)zm[p][fm][f][r4];
-          }
-    }
-  }
-}
-
-// Per-row objective of the tile from per-lane partials: reduce over the 16
-// lanes of a row group, then over the 4 column waves (fixed order), add
-// 1/2 ||x||^2. Rows of this wave start at rbase within the R-row tile.
-template <int FM, int R>
-__device__ __forceinline__ void finish_rows(const float (&fs)[FM][4], float* red, int wc, int rbase, int lane,
-                                            int tid, int row0, int N, const double* xsq, float* Fout, double* Fd) {
-  const int lr = lane & 15, lg = lane >> 4;
-#pragma unroll
-  for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-    for (int r4 = 0; r4 < 4; ++r4) {
-      float v = fs[fm][r4];
-      v += __shfl_xor(v, 1);
-      v += __shfl_xor(v, 2);
-      v += __shfl_xor(v, 4);
-      v += __shfl_xor(v, 8);
-      if (lr == 0) red[wc * R + rbase + 16 * fm + 4 * lg + r4] = v;
-    }
-  __syncthreads();
-  if (tid < R && row0 + tid < N) {
-    const double s = 0.5 * xsq[row0 + tid] + (((double)red[tid] + red[R + tid]) + red[2 * R + tid]) + red[3 * R + tid];
-    if (Fout) Fout[row0 + tid] = (float)s;
-    if (Fd) Fd[row0 + tid] = s;
-  }
-  __syncthreads();
-}
-
-// Loads this wave's 16 FM rows (from row0) of `src` ([N][m_pad] FP32) into
-// the master registers; rows past N read as 0.
-template <int FM, int NP>
-__device__ __forceinline__ void load_master(float (&zm)[NP][FM][4][4], const float* src, int row0, int N,
-                                            int m_pad, int npass, int wave, int lane) {
-  const int lr = lane & 15, lg = lane >> 4;
-  constexpr int R = FM * 16;
-  const int nrows = (N - row0) < R ? (N - row0) : R;
-  const Rsrc rs = make_rsrc(src + (size_t)row0 * m_pad, (size_t)nrows * m_pad * 4);
-  const int rstride = m_pad * 4;
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    const int slab = 4 * p + wave;
-    const bool act = p < npass && slab * 64 < m_pad;
-    const int lo = (4 * lg * m_pad + 64 * slab + lr) * 4;
-#pragma unroll
-    for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) {
-        const bool ok = act && (16 * fm + 4 * lg + r4) < nrows;
-#pragma unroll
-        for (int f = 0; f < 4; ++f)
-          zm[p][fm][f][r4] = ok ? bload(rs, lo + 64 * f, (16 * fm + r4) * rstride) : 0.f;
-      }
-  }
-}
-
-// Forward over layers [t_begin, t_end): z^(t+1) = ST(z^t - a_t (G z^t - c), lam a_t),
-// keeping the tape; with TRACE also F(z^t) for each t. Then, if asked, one
-// more contraction G z^(t_end) for F(z^(t_end)) and the backward seed.
-template <int P, int R, int NP, bool TRACE, int PF, int WR>
-__device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* lds) {
-  constexpr int FM = R / (16 * WR);  // 16-row blocks per wave
-  const int tid = threadIdx.x, lane = tid & 63;
-  // wave-uniform, and known to be: descriptors built from it stay in SGPRs
-  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wave = wid & 3;                 // column wave: slab 4 p + wave of pass p
-  const int rbase = (wid >> 2) * 16 * FM;   // first tile row of this wave
-  const int lr = lane & 15, lg = lane >> 4;
-  const int row0 = tile * R;
-  const int m_pad = g.m_pad, N = g.N, m = g.m;
-  const int rowb = m_pad * Elem<P>::bytes + 16;
-  const int npass = (m_pad + 255) / 256;
-  const int nrows = (N - row0) < R ? (N - row0) : R;
-  const int rstride = m_pad * 4;      // bytes per row of the [N][m_pad] buffers
-  const int ustride = m * 4;          // bytes per row of the caller's [N][m] buffers
-  float* red = (float*)(lds + R * rowb);
-  const Rsrc rC = make_rsrc(g.C + (size_t)row0 * m_pad, (size_t)nrows * rstride);
-  const Rsrc rZu = make_rsrc(g.Zuser ? g.Zuser + (size_t)row0 * m : nullptr, g.Zuser ? (size_t)nrows * ustride : 0);
-
-  float zm[NP][FM][4][4];
-  if (g.t_begin == 0) {
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int f = 0; f < 4; ++f)
-#pragma unroll
-          for (int r4 = 0; r4 < 4; ++r4) zm[p][fm][f][r4] = 0.f;
-  } else {
-    load_master<FM, NP>(zm, slot_ptr(g, g.t_begin), row0 + rbase, N, m_pad, npass, wave, lane);
-  }
-  master_to_lds<P, FM, NP>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
-  __syncthreads();
-
-  for (int t = g.t_begin; t < g.t_end; ++t) {
-    const float a = g.alpha[t];
-    const float lam = g.lam, th = lam * a;
-    const bool store = g.k > 0 && (g.store_all || (t + 1) % g.k == 0 || t + 1 == g.T || t + 1 > g.a_last);
-    const Rsrc rD = make_rsrc(store ? slot_ptr(g, t + 1) + (size_t)row0 * m_pad : nullptr,
-                              store ? (size_t)nrows * rstride : 0);
-    const bool copy_out = (t + 1 == g.T) && g.Zuser;
-    float fs[FM][4];
-    if constexpr (TRACE) {
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) fs[fm][r4] = 0.f;
-    }
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const int slab = 4 * p + wave;
-      if (!(p < npass && slab * 64 < m_pad)) continue;
-      f32x4 acc[FM][4];
-      if (t > 0) {
-        contract<P, FM, PF>(g, lds + rbase * rowb, rowb, slab, lane, acc);
-      } else {
-#pragma unroll
-        for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-          for (int f = 0; f < 4; ++f) acc[fm][f] = f32x4{0.f, 0.f, 0.f, 0.f};
-      }
-      const int colb = 64 * slab + lr;                 // column of block f = 0
-      const int lo = (4 * lg * m_pad + colb) * 4;      // per-lane offset, [N][m_pad] buffers
-      const int lou = (4 * lg * m + colb) * 4;         // per-lane offset, [N][m] buffers
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          if (rbase + 16 * fm + 4 * lg + r4 >= nrows) continue;
-          const int so = (rbase + 16 * fm + r4) * rstride, sou = (rbase + 16 * fm + r4) * ustride;
-#pragma unroll
-          for (int f = 0; f < 4; ++f) {
-            const float z = zm[p][fm][f][r4];
-            const float c = bload(rC, lo + 64 * f, so);
-            const float pv = acc[fm][f][r4];
-            if constexpr (TRACE) fs[fm][r4] += 0.5f * z * pv - z * c + lam * fabsf(z);
-            const float zn = soft_thresh(z - a * (pv - c), th);
-            zm[p][fm][f][r4] = zn;
-            if (store) bstore(zn, rD, lo + 64 * f, so);
-            if (copy_out && colb + 16 * f < m) bstore(zn, rZu, lou + 64 * f, sou);
-          }
-        }
-    }
-    if constexpr (TRACE) finish_rows<FM, R>(fs, red, wave, rbase, lane, tid, row0, N, g.xsq, g.Ftrace + (size_t)t * N, nullptr);
-    __syncthreads();
-    master_to_lds<P, FM, NP>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
-    __syncthreads();
-  }
-
-  if (!(g.mode & (kModeF | kModeSeed))) return;
-  // final contraction: F(z^(t_end)) and / or the seed of the backward pass
-  const bool want_f = (g.mode & kModeF) != 0;
-  const bool seed = (g.mode & kModeSeed) != 0;
-  const float lam = g.lam;
-  const Rsrc rV = make_rsrc(g.Vout ? g.Vout + (size_t)row0 * m_pad : nullptr, g.Vout ? (size_t)nrows * rstride : 0);
-  const Rsrc rdZ = make_rsrc(g.dZ ? g.dZ + (size_t)row0 * m : nullptr, g.dZ ? (size_t)nrows * ustride : 0);
-  float fs[FM][4];
-#pragma unroll
-  for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-    for (int r4 = 0; r4 < 4; ++r4) fs[fm][r4] = 0.f;
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    const int slab = 4 * p + wave;
-    if (!(p < npass && slab * 64 < m_pad)) continue;
-    f32x4 acc[FM][4];
-    contract<P, FM, PF>(g, lds + rbase * rowb, rowb, slab, lane, acc);
-    const int colb = 64 * slab + lr;
-    const int lo = (4 * lg * m_pad + colb) * 4;
-    const int lou = (4 * lg * m + colb) * 4;
-#pragma unroll
-    for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) {
-        const int rl = rbase + 16 * fm + 4 * lg + r4;
-        if (rl >= nrows) continue;
-        const int so = (rbase + 16 * fm + r4) * rstride, sou = (rbase + 16 * fm + r4) * ustride;
-        const float w = seed ? (g.dF ? g.dF[row0 + rl] : g.dF_scalar) : 0.f;
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-          const float z = zm[p][fm][f][r4];
-          const float c = bload(rC, lo + 64 * f, so);
-          const float pv = acc[fm][f][r4];
-          if (want_f) fs[fm][r4] += 0.5f * z * pv - z * c + lam * fabsf(z);
-          if (seed) {
-            float gv = w * (pv - c + lam * sgnf(z));
-            if (g.dZ && colb + 16 * f < m) gv += bload(rdZ, lou + 64 * f, sou);
-            bstore((z != 0.f) ? gv : 0.f, rV, lo + 64 * f, so);
-          }
-        }
-      }
-  }
-  if (want_f) finish_rows<FM, R>(fs, red, wave, rbase, lane, tid, row0, N, g.xsq, g.F, g.Fd);
-}
-
-template <int P, int R, int NP, int PF, int WR>
-__device__ __forceinline__ void bwd_body(const PersistArgs& g, int tile, char* lds) {
-  constexpr int FM = R / (16 * WR);  // 16-row blocks per wave
-  const int tid = threadIdx.x, lane = tid & 63;
-  // wave-uniform, and known to be: descriptors built from it stay in SGPRs
-  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wave = wid & 3;                 // column wave: slab 4 p + wave of pass p
-  const int rbase = (wid >> 2) * 16 * FM;   // first tile row of this wave
-  const int lr = lane & 15, lg = lane >> 4;
-  const int row0 = tile * R;
-  const int m_pad = g.m_pad, N = g.N;
-  const int rowb = m_pad * Elem<P>::bytes + 16;
-  const int npass = (m_pad + 255) / 256;
-  const int nrows = (N - row0) < R ? (N - row0) : R;
-  const int rstride = m_pad * 4;
-  double* dred = (double*)(lds + R * rowb);
-
-  float vm[NP][FM][4][4];
-  load_master<FM, NP>(vm, g.Vio, row0 + rbase, N, m_pad, npass, wave, lane);
-  master_to_lds<P, FM, NP>(vm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
-  __syncthreads();
-
-  for (int t = g.t_hi; t >= g.t_lo; --t) {
-    const float a = g.alpha[t];
-    const Rsrc rz0 = make_rsrc(t >= 1 ? slot_ptr(g, t) + (size_t)row0 * m_pad : nullptr,
-                               t >= 1 ? (size_t)nrows * rstride : 0);
-    const Rsrc rz1 = make_rsrc(slot_ptr(g, t + 1) + (size_t)row0 * m_pad, (size_t)nrows * rstride);
-    double dsum = 0.0;
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const int slab = 4 * p + wave;
-      if (!(p < npass && slab * 64 < m_pad)) continue;
-      f32x4 acc[FM][4];
-      if (t >= 1) contract<P, FM, PF>(g, lds + rbase * rowb, rowb, slab, lane, acc);
-      const int lo = (4 * lg * m_pad + 64 * slab + lr) * 4;
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          if (rbase + 16 * fm + 4 * lg + r4 >= nrows) continue;
-          const int so = (rbase + 16 * fm + r4) * rstride;
-#pragma unroll
-          for (int f = 0; f < 4; ++f) {
-            const float v = vm[p][fm][f][r4];
-            const float z0 = t >= 1 ? bload(rz0, lo + 64 * f, so) : 0.f;
-            const float z1 = bload(rz1, lo + 64 * f, so);
-            dsum += (double)v * ((double)z0 - (double)z1);
-            if (t >= 1) vm[p][fm][f][r4] = (z0 != 0.f) ? v - a * acc[fm][f][r4] : 0.f;
-          }
-        }
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) dsum += __shfl_xor(dsum, o);
-    if (lane == 0) dred[wid] = dsum;
-    __syncthreads();
-    if (tid == 0) {
-      double tot = 0.0;
-#pragma unroll
-      for (int w = 0; w < 4 * WR; ++w) tot += dred[w];
-      g.dpart[(size_t)t * g.P_stride + tile] = tot;
-    }
-    if (t >= 1 && t > g.t_lo) master_to_lds<P, FM, NP>(vm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
-    __syncthreads();
-  }
-  if (g.t_lo >= 1) {
-    const Rsrc rv = make_rsrc(g.Vio + (size_t)row0 * m_pad, (size_t)nrows * rstride);
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const int slab = 4 * p + wave;
-      if (!(p < npass && slab * 64 < m_pad)) continue;
-      const int lo = (4 * lg * m_pad + 64 * slab + lr) * 4;
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          if (rbase + 16 * fm + 4 * lg + r4 >= nrows) continue;
-#pragma unroll
-          for (int f = 0; f < 4; ++f) bstore(vm[p][fm][f][r4], rv, lo + 64 * f, (rbase + 16 * fm + r4) * rstride);
-        }
-    }
-  }
-}
-
-// Single problem: workgroup b carries tile b.
-template <int P, int R, int NP, bool TRACE, int PF, int OCC, int WR>
-__global__ __launch_bounds__(PT * WR, OCC) void fwd_persist(PersistArgs g) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
-  fwd_body<P, R, NP, TRACE, PF, WR>(g, blockIdx.x, lds);
-}
-
-template <int P, int R, int NP, int PF, int OCC, int WR>
-__global__ __launch_bounds__(PT * WR, OCC) void bwd_persist(PersistArgs g) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
-  bwd_body<P, R, NP, PF, WR>(g, blockIdx.x, lds);
-}
-
-// Several problems in one launch: workgroup b carries tile work[b].y of
-// problem work[b].x, whose arguments are tab[work[b].x] with the layer range
-// and mode of this launch (ph) filled in. The work list is ordered longest
-// tile first.
-__device__ __forceinline__ PersistArgs batched_args(const PersistArgs* tab, const int2* work, const PersistPhase& ph,
-                                                    int& tile) {
-  const int2 w = work[blockIdx.x];
-  PersistArgs g = tab[w.x];
-  g.t_begin = ph.t_begin;
-  g.t_end = ph.t_end;
-  g.mode = ph.mode & g.mode_mask;
-  g.store_all = ph.store_all;
-  g.t_hi = ph.t_hi;
-  g.t_lo = ph.t_lo;
-  tile = w.y;
-  return g;
-}
-
-template <int P, int R, int NP, int PF, int OCC, int WR>
-__global__ __launch_bounds__(PT * WR, OCC) void fwd_persist_batched(const PersistArgs* tab, const int2* work,
-                                                                     PersistPhase ph) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
-  int tile;
-  const PersistArgs g = batched_args(tab, work, ph, tile);
-  fwd_body<P, R, NP, false, PF, WR>(g, tile, lds);
-}
-
-template <int P, int R, int NP, int PF, int OCC, int WR>
-__global__ __launch_bounds__(PT * WR, OCC) void bwd_persist_batched(const PersistArgs* tab, const int2* work,
-                                                                     PersistPhase ph) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
-  int tile;
-  const PersistArgs g = batched_args(tab, work, ph, tile);
-  bwd_body<P, R, NP, PF, WR>(g, tile, lds);
-}
 
 // Fragment-ordered copies of G for the persistent kernels.
 // BF16: fragment (cb, kc) = G[16 cb + l % 16][32 kc + 8 (l / 16) + e], e < 8.
@@ -534,42 +32,6 @@ __global__ void k_swizzle(const float* __restrict__ G, int mp, uint16_t* __restr
   }
 }
 
-template <int P, int R, int NP, int PF, int OCC, int WR = 1>
-hipError_t launch_pair(bool fwd, const PersistArgs& a, hipStream_t s) {
-  const int tiles = (a.N + R - 1) / R;
-  if (tiles == 0) return hipSuccess;
-  const size_t lds = (size_t)R * (a.m_pad * Elem<P>::bytes + 16) + 4 * R * sizeof(float) + 64;
-  const bool trace = fwd && (a.mode & kModeTrace);
-  const void* fn = !fwd ? (const void*)bwd_persist<P, R, NP, PF, OCC, WR>
-                        : trace ? (const void*)fwd_persist<P, R, NP, true, PF, OCC, WR>
-                                : (const void*)fwd_persist<P, R, NP, false, PF, OCC, WR>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  if (!fwd)
-    hipLaunchKernelGGL((bwd_persist<P, R, NP, PF, OCC, WR>), dim3(tiles), dim3(PT * WR), lds, s, a);
-  else if (trace)
-    hipLaunchKernelGGL((fwd_persist<P, R, NP, true, PF, OCC, WR>), dim3(tiles), dim3(PT * WR), lds, s, a);
-  else
-    hipLaunchKernelGGL((fwd_persist<P, R, NP, false, PF, OCC, WR>), dim3(tiles), dim3(PT * WR), lds, s, a);
-  return hipGetLastError();
-}
-
-template <int P, int R, int NP, int PF, int OCC, int WR = 1>
-hipError_t launch_pair_batched(bool fwd, const PersistArgs* tab, const int2* work, int nwork, int max_m_pad,
-                               const PersistPhase& ph, hipStream_t s) {
-  if (nwork == 0) return hipSuccess;
-  const size_t lds = (size_t)R * (max_m_pad * Elem<P>::bytes + 16) + 4 * R * sizeof(float) + 64;
-  const void* fn = fwd ? (const void*)fwd_persist_batched<P, R, NP, PF, OCC, WR>
-                       : (const void*)bwd_persist_batched<P, R, NP, PF, OCC, WR>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  if (fwd)
-    hipLaunchKernelGGL((fwd_persist_batched<P, R, NP, PF, OCC, WR>), dim3(nwork), dim3(PT * WR), lds, s, tab, work, ph);
-  else
-    hipLaunchKernelGGL((bwd_persist_batched<P, R, NP, PF, OCC, WR>), dim3(nwork), dim3(PT * WR), lds, s, tab, work, ph);
-  return hipGetLastError();
-}
-
 // Number of 256-column passes for m_pad (0: not handled by these kernels).
 int np_of(int m_pad) { return m_pad <= 256 ? 1 : m_pad <= 512 ? 2 : m_pad <= 1024 ? 4 : m_pad <= 2048 ? 8 : 0; }
 
@@ -585,64 +47,52 @@ int np_of(int m_pad) { return m_pad <= 256 ? 1 : m_pad <= 512 ? 2 : m_pad <= 102
 //   variant 3: the rows of variant 1 in one 8-wave workgroup per CU: two row
 //              halves x four column slabs, two waves per SIMD; the two waves
 //              of a column slab read the same G fragments (one L2 fetch,
-//              one L1 hit), G fragments 1 K step ahead.
-// m_pad in (1024, 2048] has variant 1 only.
-int persist_variants(int m_pad) { return np_of(m_pad) == 8 ? 1 : (np_of(m_pad) ? 3 : 0); }
+//              one L1 hit), G fragments 1 K step ahead;
+//   variant 4: the rows of variant 1 in one 8-wave workgroup per CU with
+//              eight 32-column slabs per pass: each G fragment is read once
+//              per tile, a K step needs half the G registers of variants
+//              1-3, and G fragments are issued 3 K steps ahead with two
+//              waves per SIMD.
+// m_pad in (1024, 2048] has variants 1 and 4.
+bool persist_has_variant(int m_pad, int v) {
+  const int np = np_of(m_pad);
+  if (np == 0) return false;
+  return np == 8 ? (v == 1 || v == 4) : (v >= 1 && v <= 4);
+}
 
-// Measured on the 256 x 1024, N = 65 536, T = 50 workload: variant 2 is 1.16x
-// (BF16) and 1.12x (FP32) faster than variant 1 for fwd+bwd.
+// Measured on the 256 x 1024, N = 65 536, T = 50 workload (fwd + bwd per
+// launch, BF16 / FP32 ms): variant 1 19.1+15.0 / 65.9+58.9, variant 2
+// 15.2+16.2 / 56.7+56.1, variant 3 15.9+16.2 / 56.5+57.6, variant 4
+// 12.0+15.4 / 54.3+54.5. The autotuner can still pick per problem class.
 int default_variant(int prec, int m_pad) {
   (void)prec;
-  return np_of(m_pad) <= 4 ? 2 : 1;
+  (void)m_pad;
+  return 4;
 }
 
 int persist_resolve_variant(int prec, int m_pad, int variant) {
   if (np_of(m_pad) == 0) return 0;
-  return (variant <= 0 || variant > persist_variants(m_pad)) ? default_variant(prec, m_pad) : variant;
+  return persist_has_variant(m_pad, variant) ? variant : default_variant(prec, m_pad);
 }
 
 int persist_rows(int prec, int m_pad, int variant) {
   const int np = np_of(m_pad);
   if (np == 0) return 0;
-  if (variant <= 0 || variant > persist_variants(m_pad)) variant = default_variant(prec, m_pad);
+  variant = persist_resolve_variant(prec, m_pad, variant);
   const bool v2 = variant == 2;
   if (prec == kBF16) return np == 8 ? 32 : (v2 ? 32 : 64);
   if (np == 8) return 16;
   if (np == 4) return v2 ? 16 : 32;
-  return v2 ? 32 : 64;  // variant 3 keeps the rows of variant 1
+  return v2 ? 32 : 64;  // variants 3 and 4 keep the rows of variant 1
 }
+
+// Template arguments per (precision, passes, variant): rows, passes, G
+// prefetch depth, waves per SIMD bound, row waves, column waves.
 
 hipError_t launch_persist(bool fwd, int prec, const PersistArgs& a, hipStream_t s, int variant) {
   const int np = np_of(a.m_pad);
-  if (variant <= 0 || variant > persist_variants(a.m_pad)) variant = default_variant(prec, a.m_pad);
-  if (prec == kBF16) {
-    switch (np * 4 + variant) {
-      case 1 * 4 + 1: return launch_pair<kBF16, 64, 1, 4, 1>(fwd, a, s);
-      case 1 * 4 + 2: return launch_pair<kBF16, 32, 1, 2, 2>(fwd, a, s);
-      case 1 * 4 + 3: return launch_pair<kBF16, 64, 1, 2, 1, 2>(fwd, a, s);
-      case 2 * 4 + 1: return launch_pair<kBF16, 64, 2, 4, 1>(fwd, a, s);
-      case 2 * 4 + 2: return launch_pair<kBF16, 32, 2, 2, 2>(fwd, a, s);
-      case 2 * 4 + 3: return launch_pair<kBF16, 64, 2, 2, 1, 2>(fwd, a, s);
-      case 4 * 4 + 1: return launch_pair<kBF16, 64, 4, 4, 1>(fwd, a, s);
-      case 4 * 4 + 2: return launch_pair<kBF16, 32, 4, 2, 2>(fwd, a, s);
-      case 4 * 4 + 3: return launch_pair<kBF16, 64, 4, 2, 1, 2>(fwd, a, s);
-      case 8 * 4 + 1: return launch_pair<kBF16, 32, 8, 4, 1>(fwd, a, s);
-      default: return hipErrorInvalidValue;
-    }
-  }
-  switch (np * 4 + variant) {
-    case 1 * 4 + 1: return launch_pair<kF32, 64, 1, 4, 1>(fwd, a, s);
-    case 1 * 4 + 2: return launch_pair<kF32, 32, 1, 2, 2>(fwd, a, s);
-    case 1 * 4 + 3: return launch_pair<kF32, 64, 1, 2, 1, 2>(fwd, a, s);
-    case 2 * 4 + 1: return launch_pair<kF32, 64, 2, 4, 1>(fwd, a, s);
-    case 2 * 4 + 2: return launch_pair<kF32, 32, 2, 2, 2>(fwd, a, s);
-    case 2 * 4 + 3: return launch_pair<kF32, 64, 2, 2, 1, 2>(fwd, a, s);
-    case 4 * 4 + 1: return launch_pair<kF32, 32, 4, 4, 1>(fwd, a, s);
-    case 4 * 4 + 2: return launch_pair<kF32, 16, 4, 2, 2>(fwd, a, s);
-    case 4 * 4 + 3: return launch_pair<kF32, 32, 4, 2, 1, 2>(fwd, a, s);
-    case 8 * 4 + 1: return launch_pair<kF32, 16, 8, 4, 1>(fwd, a, s);
-    default: return hipErrorInvalidValue;
-  }
+  variant = persist_resolve_variant(prec, a.m_pad, variant);
+  return prec == kBF16 ? launch_persist_bf16(fwd, np, variant, a, s) : launch_persist_f32(fwd, np, variant, a, s);
 }
 
 int persist_np(int m_pad) { return np_of(m_pad); }
@@ -650,37 +100,9 @@ int persist_np(int m_pad) { return np_of(m_pad); }
 hipError_t launch_persist_batched(bool fwd, int prec, int np, int variant, const PersistArgs* tab, const int2* work,
                                   int nwork, int max_m_pad, const PersistPhase& ph, hipStream_t s) {
   const int probe_m_pad = np == 8 ? 2048 : np * 256;
-  if (variant <= 0 || variant > persist_variants(probe_m_pad)) variant = default_variant(prec, probe_m_pad);
-#define SLISTA_B(...) return launch_pair_batched<__VA_ARGS__>(fwd, tab, work, nwork, max_m_pad, ph, s)
-  if (prec == kBF16) {
-    switch (np * 4 + variant) {
-      case 1 * 4 + 1: SLISTA_B(kBF16, 64, 1, 4, 1);
-      case 1 * 4 + 2: SLISTA_B(kBF16, 32, 1, 2, 2);
-      case 1 * 4 + 3: SLISTA_B(kBF16, 64, 1, 2, 1, 2);
-      case 2 * 4 + 1: SLISTA_B(kBF16, 64, 2, 4, 1);
-      case 2 * 4 + 2: SLISTA_B(kBF16, 32, 2, 2, 2);
-      case 2 * 4 + 3: SLISTA_B(kBF16, 64, 2, 2, 1, 2);
-      case 4 * 4 + 1: SLISTA_B(kBF16, 64, 4, 4, 1);
-      case 4 * 4 + 2: SLISTA_B(kBF16, 32, 4, 2, 2);
-      case 4 * 4 + 3: SLISTA_B(kBF16, 64, 4, 2, 1, 2);
-      case 8 * 4 + 1: SLISTA_B(kBF16, 32, 8, 4, 1);
-      default: return hipErrorInvalidValue;
-    }
-  }
-  switch (np * 4 + variant) {
-    case 1 * 4 + 1: SLISTA_B(kF32, 64, 1, 4, 1);
-    case 1 * 4 + 2: SLISTA_B(kF32, 32, 1, 2, 2);
-    case 1 * 4 + 3: SLISTA_B(kF32, 64, 1, 2, 1, 2);
-    case 2 * 4 + 1: SLISTA_B(kF32, 64, 2, 4, 1);
-    case 2 * 4 + 2: SLISTA_B(kF32, 32, 2, 2, 2);
-    case 2 * 4 + 3: SLISTA_B(kF32, 64, 2, 2, 1, 2);
-    case 4 * 4 + 1: SLISTA_B(kF32, 32, 4, 4, 1);
-    case 4 * 4 + 2: SLISTA_B(kF32, 16, 4, 2, 2);
-    case 4 * 4 + 3: SLISTA_B(kF32, 32, 4, 2, 1, 2);
-    case 8 * 4 + 1: SLISTA_B(kF32, 16, 8, 4, 1);
-    default: return hipErrorInvalidValue;
-  }
-#undef SLISTA_B
+  variant = persist_resolve_variant(prec, probe_m_pad, variant);
+  return prec == kBF16 ? launch_persist_batched_bf16(fwd, np, variant, tab, work, nwork, max_m_pad, ph, s)
+                       : launch_persist_batched_f32(fwd, np, variant, tab, work, nwork, max_m_pad, ph, s);
 }
 
 hipError_t launch_swizzle(const float* G32, int mp, uint16_t* Gsb, float* Gsf, hipStream_t s) {

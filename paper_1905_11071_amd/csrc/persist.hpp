@@ -47,13 +47,22 @@ struct PersistPhase {
   int t_begin, t_end, mode, store_all, t_hi, t_lo;
 };
 
-// Tile variants available for m_pad (0 = not handled by the persistent kernels).
-int persist_variants(int m_pad);
+// Highest tile variant number; persist_has_variant tells which exist for m_pad
+// (none when m_pad is not handled by the persistent kernels).
+constexpr int kPersistMaxVariant = 4;
+bool persist_has_variant(int m_pad, int v);
 // Rows per tile for (prec, m_pad, variant); variant 0 = the default one.
 int persist_rows(int prec, int m_pad, int variant);
 // The variant a launch with this request runs (0 or out of range -> default).
 int persist_resolve_variant(int prec, int m_pad, int variant);
 hipError_t launch_persist(bool fwd, int prec, const PersistArgs& a, hipStream_t s, int variant);
+// Per-precision tile tables (variant already resolved).
+hipError_t launch_persist_bf16(bool fwd, int np, int variant, const PersistArgs& a, hipStream_t s);
+hipError_t launch_persist_f32(bool fwd, int np, int variant, const PersistArgs& a, hipStream_t s);
+hipError_t launch_persist_batched_bf16(bool fwd, int np, int variant, const PersistArgs* tab, const int2* work,
+                                       int nwork, int max_m_pad, const PersistPhase& ph, hipStream_t s);
+hipError_t launch_persist_batched_f32(bool fwd, int np, int variant, const PersistArgs* tab, const int2* work,
+                                      int nwork, int max_m_pad, const PersistPhase& ph, hipStream_t s);
 hipError_t launch_swizzle(const float* G32, int m_pad, uint16_t* Gsb, float* Gsf, hipStream_t s);
 // Column-pass bucket of m_pad (1, 2, 4, 8; 0 = not handled).
 int persist_np(int m_pad);

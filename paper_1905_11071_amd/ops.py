@@ -179,7 +179,7 @@ def forward_backward(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Te
 def autotune(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, prec="fp32", ckpt_every: int = 1):
     """Time every tile variant of the persistent kernels on this problem and
     make the fastest the default for its (precision, m, N) class. Returns
-    (best variant, [ms per call of variants 1..3])."""
+    (best variant, [ms per call of variants 1..4; 0 where a variant does not apply])."""
     X, alpha = _check_inputs(d, X, alpha)
     N, T = int(X.shape[0]), int(alpha.shape[0])
     p = _prec(prec)
@@ -187,7 +187,7 @@ def autotune(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, pr
     Z = torch.empty(N, d.m, device=d.device, dtype=torch.float32)
     da = torch.empty(T, device=d.device, dtype=torch.float32)
     best = ctypes.c_int()
-    ms = (ctypes.c_double * 3)()
+    ms = (ctypes.c_double * 4)()
     check(lib().slista_autotune(d.handle, X.data_ptr(), N, float(lam), alpha.data_ptr(), T, p, ckpt_every,
                                 Z.data_ptr(), da.data_ptr(), ws.data_ptr(), ws.numel(), _stream(d.device),
                                 ctypes.byref(best), ms))
@@ -287,7 +287,7 @@ def set_kernel_family(name: str) -> None:
 
 
 def set_tile_variant(v: int) -> None:
-    """Tile configuration of the persistent kernels (0 = library default, 1, 2)."""
+    """Tile configuration of the persistent kernels (0 = library default, 1..4)."""
     check(lib().slista_set_option(2, int(v)))
 
 
