@@ -33,6 +33,13 @@ template <int P> struct Elem;
 template <> struct Elem<kF32> { static constexpr int bytes = 4; };
 template <> struct Elem<kBF16> { static constexpr int bytes = 2; };
 
+// Bytes per row of a tile's LDS copy: m_pad elements plus 32 bytes. Rows
+// then start 32 mod 64 bytes apart, which keeps the 16-byte fragment reads of
+// 16 rows x 4 lanes (and the 2-byte writes of the accumulator layout) free of
+// bank conflicts; a 16-byte pad measured 2-way conflicts on every read.
+template <int P>
+__host__ __device__ constexpr int tile_rowb(int m_pad) { return m_pad * Elem<P>::bytes + 32; }
+
 __device__ __forceinline__ float soft_thresh(float u, float th) {
   const float au = fabsf(u) - th;
   return au > 0.f ? copysignf(au, u) : 0.f;
@@ -117,6 +124,9 @@ __device__ __forceinline__ void k_step(const Rsrc& rg, int lo, int KC, const cha
 #pragma unroll
       for (int f = 0; f < FB; ++f) mfma_pair<P>(acc[fm][f], av[J & 1][fm], bq[JB][f]);
   }
+  // keep the step boundary: the scheduler would otherwise sink the prefetches
+  // of later steps next to their uses when registers run short
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // Unrolled K steps J .. U-1 from step kc0 (run), or only those below KC (tail).
@@ -276,7 +286,7 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
   const int lr = lane & 15, lg = lane >> 4;
   const int row0 = tile * R;
   const int m_pad = g.m_pad, N = g.N, m = g.m;
-  const int rowb = m_pad * Elem<P>::bytes + 16;
+  const int rowb = tile_rowb<P>(m_pad);
   const int npass = (m_pad + 255) / 256;
   const int nrows = (N - row0) < R ? (N - row0) : R;
   const int rstride = m_pad * 4;      // bytes per row of the [N][m_pad] buffers
@@ -415,7 +425,7 @@ __device__ __forceinline__ void bwd_body(const PersistArgs& g, int tile, char* l
   const int lr = lane & 15, lg = lane >> 4;
   const int row0 = tile * R;
   const int m_pad = g.m_pad, N = g.N;
-  const int rowb = m_pad * Elem<P>::bytes + 16;
+  const int rowb = tile_rowb<P>(m_pad);
   const int npass = (m_pad + 255) / 256;
   const int nrows = (N - row0) < R ? (N - row0) : R;
   const int rstride = m_pad * 4;
@@ -567,7 +577,7 @@ __global__ __launch_bounds__(64 * WC * WR, OCC) void bwd_persist_batched(const P
 // LDS of a tile: the A operand rows plus the per-wave row partials.
 template <int P, int R, int WC>
 size_t tile_lds(int m_pad) {
-  return (size_t)R * (m_pad * Elem<P>::bytes + 16) + (size_t)WC * R * sizeof(float) + 64;
+  return (size_t)R * tile_rowb<P>(m_pad) + (size_t)WC * R * sizeof(float) + 64;
 }
 
 template <int P, int R, int NP, int PF, int OCC, int WR = 1, int WC = 4>
