@@ -46,7 +46,43 @@ def launch_work(kind: str, N: int, m: int, T: int):
     raise ValueError(kind)
 
 
-def roofline(kind: str, avg_ms: float, N: int, m: int, T: int, prec: str) -> dict:
+# HBM traffic per launch on prec_256x1024 (ckpt_every = 1, tile variant 4) from
+# rocprofv3 counters: FETCH_SIZE x 2 + WRITE_SIZE x 1 (KiB per dispatch; the
+# factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
+# for the kernel sources they were taken on (sha256 below) and that variant.
+MEASURED_TRAFFIC = {
+    "sources_sha256": "337d0b12c80ed762cea41b2475d7520eec4d696c117947ca022d8fd52637a956",
+    "workload": "prec_256x1024",
+    "variant": 4,
+    "bytes": {
+        ("bf16", "forward_layer"): (7914068 * 2 + 19870303) * 1024,
+        ("bf16", "backward_layer"): (8266064 * 2 + 622413) * 1024,
+        ("fp32", "forward_layer"): (13725548 * 2 + 19874653) * 1024,
+        ("fp32", "backward_layer"): (13967900 * 2 + 3680) * 1024,
+    },
+}
+KERNEL_SOURCES = ["common.hpp", "persist.hpp", "persist_body.hpp", "kernels_persist.hip",
+                  "kernels_persist_bf16.hip", "kernels_persist_f32.hip"]
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1905_11071_amd", "csrc")
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, ckpt: int, variant: int, prec: str, kind: str):
+    if (workload != MEASURED_TRAFFIC["workload"] or ckpt != 1 or variant != MEASURED_TRAFFIC["variant"]
+            or kernel_sources_sha256() != MEASURED_TRAFFIC["sources_sha256"]):
+        return None
+    return MEASURED_TRAFFIC["bytes"].get((prec, kind))
+
+
+def roofline(kind: str, avg_ms: float, N: int, m: int, T: int, prec: str, traffic=None) -> dict:
     flops, bytes_ = launch_work(kind, N, m, T)
     peak_f = PEAK["bf16_tflops"] if prec == "bf16" else PEAK["fp32_tflops"]
     ridge = peak_f * 1e12 / (PEAK["hbm_gbs"] * 1e9)
@@ -54,7 +90,9 @@ def roofline(kind: str, avg_ms: float, N: int, m: int, T: int, prec: str) -> dic
     tflops = flops / sec / 1e12
     gbs = bytes_ / sec / 1e9
     out = {"kernel": kind, "avg_ms": round(avg_ms, 4), "flops_per_launch": flops, "bytes_per_launch": bytes_,
-           "mfma_frac": round(tflops / peak_f, 4), "hbm_frac": round(gbs / PEAK["hbm_gbs"], 4), "traffic": None}
+           "mfma_frac": round(tflops / peak_f, 4), "hbm_frac": round(gbs / PEAK["hbm_gbs"], 4), "traffic": traffic}
+    if traffic is not None:
+        out["traffic_gbs"] = round(traffic / sec / 1e9, 1)
     if flops / bytes_ < ridge:
         out.update({"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
                     "frac": round(gbs / PEAK["hbm_gbs"], 4)})
@@ -126,26 +164,33 @@ def cpu_baseline(pb, alpha_np, n_sub: int) -> dict:
                                         f"({sec:.1f} s)"}
 
 
-def uneven_report(sl, torch, prec: str, T: int, ckpt: int, reps: int) -> dict:
-    """Uneven multi-problem batch: 64 independent Lasso problems (n in [32, 512],
-    m = 4n, N in [128, 8192]), per-problem perturbed 1/L steps, forward +
-    backward with checkpoints every `ckpt` layers, autotuned tiles, timed as
-    replays of one captured HIP graph."""
+def uneven_inputs(sl, torch, T: int):
+    """The 64 problems of the uneven batch on the device: (dictionary, X, lambda,
+    alpha) with alpha_t = (1/L)(1 + 0.3 U[0,1)), L from the library's power
+    iteration (setup, not timed)."""
     import synth
-    import numpy as np
     specs = synth.uneven_problem_specs(P=synth.UNEVEN["P"], seed=synth.UNEVEN["seed"])
     dev = torch.device("cuda:0")
     t0 = time.time()
-    inputs, dicts = [], []
-    for i, sp in enumerate(specs):
+    inputs = []
+    for sp in specs:
         pb = synth.make_problem(sp["n"], sp["m"], sp["N"], sp["p"], sp["sigma"], sp["lam_frac"], sp["seed"])
         d = sl.Dictionary(torch.tensor(pb.D32(), device=dev))
-        L, _ = d.lipschitz(max_iter=20_000, rtol=1e-9)
+        L, _ = d.lipschitz(max_iter=20_000, rtol=1e-7)
         alpha = torch.tensor(synth.perturbed_steps(L, T, seed=sp["seed"]), device=dev, dtype=torch.float32)
         inputs.append((d, torch.tensor(pb.X32(), device=dev), pb.lam, alpha))
-        dicts.append(d)
-    print(f"[bench] uneven batch: {len(specs)} problems generated in {time.time() - t0:.1f} s",
+    print(f"[bench] uneven batch: {len(specs)} problems set up in {time.time() - t0:.1f} s",
           file=sys.stderr, flush=True)
+    return specs, inputs
+
+
+def uneven_report(sl, torch, specs, inputs, prec: str, T: int, ckpt: int, reps: int) -> dict:
+    """Uneven multi-problem batch: 64 independent Lasso problems (n in [32, 512],
+    m = 4n, N in [128, 8192]), forward + backward with checkpoints every `ckpt`
+    layers, tiles autotuned per column-pass bucket, timed as replays of one
+    captured HIP graph."""
+    import numpy as np
+    dev = torch.device("cuda:0")
     b = sl.Batch(inputs, prec=prec, ckpt_every=ckpt)
     b.run()
     torch.cuda.synchronize()
@@ -172,8 +217,6 @@ def uneven_report(sl, torch, prec: str, T: int, ckpt: int, reps: int) -> dict:
            "mfma_tflops": round(flops / (ms * 1e-3) / 1e12, 2), "mfma_frac": round(flops / (ms * 1e-3) / peak, 4),
            "tuned_variant_by_column_passes": tuned, "timing": "HIP graph replay"}
     b.close()
-    for d in dicts:
-        d.close()
     return out
 
 
@@ -241,7 +284,10 @@ def main() -> int:
         r = time_precision(sl, torch, d, X, pb.lam, alpha, p, args.steps, args.warmup, args.ckpt_every)
         dk = r["dominant"]
         n_l, tot = r["kernels"][dk]
-        r["roofline"] = roofline(dk, tot / n_l, pb.N, pb.m, T, p)
+        variant = tuned[p]["variant"] if args.variant == 0 else args.variant
+        r["variant"] = variant
+        r["roofline"] = roofline(dk, tot / n_l, pb.N, pb.m, T, p,
+                                 measured_traffic(args.workload, args.ckpt_every, variant, p, dk))
         r["value"] = pb.N * T / (r["ms_per_step"] * 1e-3)
         res[p] = r
         print(f"[bench] {p}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4g} sample-layers/s, "
@@ -257,9 +303,13 @@ def main() -> int:
     if not args.no_uneven:
         ucfg = synth.UNEVEN
         uneven = {}
+        specs, inputs = uneven_inputs(sl, torch, ucfg["T"])
         for p in args.uneven_precs.split(","):
-            uneven[p] = uneven_report(sl, torch, p, ucfg["T"], ucfg["ckpt_every"], args.uneven_reps)
+            uneven[p] = uneven_report(sl, torch, specs, inputs, p, ucfg["T"], ucfg["ckpt_every"], args.uneven_reps)
             print(f"[bench] uneven {p}: {uneven[p]}", file=sys.stderr, flush=True)
+        for dd, _, _, _ in inputs:
+            dd.close()
+        del inputs
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -287,7 +337,7 @@ def main() -> int:
         "roofline": h["roofline"],
         "cpu_baseline": cpu,
         "per_precision": {p: {"value": round(r["value"], 1), "ms_per_step": round(r["ms_per_step"], 4),
-                              "roofline": r["roofline"],
+                              "roofline": r["roofline"], "tile_variant": r["variant"],
                               "kernels_ms": {k: [v[0], round(v[1] / args.steps, 4)] for k, v in r["kernels"].items()},
                               "loss": r["loss"]}
                           for p, r in res.items()},
