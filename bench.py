@@ -51,14 +51,14 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "337d0b12c80ed762cea41b2475d7520eec4d696c117947ca022d8fd52637a956",
+    "sources_sha256": "67143d8645f72e2f7ae85503cbc20aa210136c4eb8721bea487473c9910bf0c3",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {
-        ("bf16", "forward_layer"): (7914068 * 2 + 19870303) * 1024,
-        ("bf16", "backward_layer"): (8266064 * 2 + 622413) * 1024,
-        ("fp32", "forward_layer"): (13725548 * 2 + 19874653) * 1024,
-        ("fp32", "backward_layer"): (13967900 * 2 + 3680) * 1024,
+        ("bf16", "forward_layer"): (9872745 * 2 + 13751376) * 1024,
+        ("bf16", "backward_layer"): (8114900 * 2 + 622442) * 1024,
+        ("fp32", "forward_layer"): (17608741 * 2 + 13654236) * 1024,
+        ("fp32", "backward_layer"): (14002478 * 2 + 3675) * 1024,
     },
 }
 KERNEL_SOURCES = ["common.hpp", "persist.hpp", "persist_body.hpp", "kernels_persist.hip",

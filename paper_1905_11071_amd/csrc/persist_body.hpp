@@ -56,17 +56,18 @@ __device__ __forceinline__ Rsrc make_rsrc(const void* base, size_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, kRsrcWord3);
 }
 // The b32 builtins move raw 32-bit patterns (unsigned int): bit-cast, never
-// convert. Stores of per-sample results (the tape, outputs) are streaming
-// (cache policy nt): the tape is read back only by the backward pass, long
-// after. Loads stay temporal: a tile re-reads its rows of c every layer and
-// the backward reads each kept iterate at two consecutive layers, and those
-// re-reads hit in the caches (non-temporal loads measured 1.5x slower).
-constexpr int kNT = 2;
+// convert. All accesses use the default (temporal) cache policy: a tile
+// re-reads its rows of c every layer and the backward reads each kept
+// iterate once, and those re-reads hit in the caches (non-temporal loads
+// measured 1.5x slower); non-temporal stores of the tape measured the same
+// speed but 1.46x the HBM write bytes (each 64-byte half line went out on
+// its own), temporal stores write exactly the stored iterates.
+constexpr int kCachePolicy = 0;
 __device__ __forceinline__ float bload(Rsrc r, int voff, int soff) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, kCachePolicy));
 }
 __device__ __forceinline__ void bstore(float v, Rsrc r, int voff, int soff) {
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, kNT);
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, kCachePolicy);
 }
 
 __device__ __forceinline__ float* slot_ptr(const PersistArgs& g, int t) {
