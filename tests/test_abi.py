@@ -72,3 +72,39 @@ def test_binding_refuses_cpu_tensors():
     import paper_1905_11071_amd as sl
     with pytest.raises(ValueError):
         sl.Dictionary(torch.zeros(4, 8))
+
+
+def test_options_are_checked_on_the_host(lib):
+    assert lib.slista_set_option(1, 3) == -1          # kernel family outside [0, 2]
+    assert lib.slista_set_option(2, 5) == -1          # tile variant outside [0, 4]
+    assert lib.slista_set_option(99, 0) == -1         # unknown option
+    assert lib.slista_set_option(2, 4) == 0
+    assert lib.slista_set_option(2, 0) == 0
+    assert lib.slista_set_option(1, 0) == 0
+
+
+def test_tuning_table_round_trip(lib, tmp_path):
+    """slista_tune_load keeps only well-formed records (precision, column
+    passes, log2 N, variant); slista_tune_save writes them back. Host only."""
+    src = tmp_path / "in.txt"
+    src.write_text("1 4 16 4\n0 8 12 1\n1 3 10 2\n0 2 9 7\n1 1 30 2\n")
+    assert lib.slista_tune_load(str(src).encode()) == 0
+    out = tmp_path / "out.txt"
+    assert lib.slista_tune_save(str(out).encode()) == 0
+    recs = {tuple(map(int, ln.split())) for ln in out.read_text().splitlines() if ln.strip()}
+    assert {(1, 4, 16, 4), (0, 8, 12, 1), (1, 1, 30, 2)} <= recs
+    assert (1, 3, 10, 2) not in recs and (0, 2, 9, 7) not in recs   # bad passes / variant dropped
+    assert lib.slista_tune_load(str(tmp_path / "missing.txt").encode()) == -1
+    assert lib.slista_tune_save(None) == -1
+
+
+def test_batch_and_autotune_reject_null_arguments(lib):
+    best = ctypes.c_int()
+    assert lib.slista_autotune(None, None, 1, ctypes.c_float(0.1), None, 1, 0, 1, None, None, None, 0, None,
+                               ctypes.byref(best), None) == -1
+    assert lib.slista_batch_autotune(None, None, None) == -1
+    out = ctypes.c_void_p()
+    assert lib.slista_batch_create(None, 1, 5, 0, 1, ctypes.byref(out)) == -1
+    assert lib.slista_batch_run(None, None) == -1
+    assert lib.slista_batch_replay(None, None) == -1
+    assert lib.slista_batch_destroy(None) == 0
