@@ -581,7 +581,7 @@ int slista_dict_create(const float* D, int n, int m, void* stream, slista_dict**
   bool ok = hipMalloc(&d.G32, mp * mp * sizeof(float)) == hipSuccess &&
             hipMalloc(&d.Gb, mp * mp * sizeof(uint16_t)) == hipSuccess &&
             hipMalloc(&d.Dt, mp * (size_t)n * sizeof(float)) == hipSuccess &&
-            hipMalloc(&d.pwork, (2 * mp + 4) * sizeof(double)) == hipSuccess &&
+            hipMalloc(&d.pwork, (2 * mp + 8) * sizeof(double)) == hipSuccess &&
             hipMalloc(&d.Gsb, mp * mp * sizeof(uint16_t)) == hipSuccess &&
             hipMalloc(&d.Gsf, mp * mp * sizeof(float)) == hipSuccess;
   if (!ok) {
@@ -642,10 +642,17 @@ int slista_dict_lipschitz(slista_dict* dict, int max_iter, double rtol, double* 
   if (!(rtol >= 0.0) || !std::isfinite(rtol)) return fail(SLISTA_EINVAL, "rtol must be finite and >= 0");
   slista::Dict& d = dict->d;
   hipStream_t s = (hipStream_t)stream;
-  LAUNCH(kKOther, s, slista::launch_power(d.G32, d.m, d.m_pad, max_iter, rtol, d.pwork, s));
-  double res[3];
-  HIP_TRY(hipMemcpyAsync(res, d.pwork + 2 * (size_t)d.m_pad, sizeof res, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  LAUNCH(kKOther, s, slista::launch_power_init(d.m, d.m_pad, d.pwork, s));
+  // state: L, iterations, converged, previous quotient, zero vector
+  double res[5] = {0, 0, 0, 0, 0};
+  for (;;) {
+    // a batch of iterations; launches after a stop condition return at once
+    for (int b = 0; b < 32; ++b)
+      LAUNCH(kKOther, s, slista::launch_power_step(d.G32, d.m, d.m_pad, max_iter, rtol, d.pwork, s));
+    HIP_TRY(hipMemcpyAsync(res, d.pwork + 2 * (size_t)d.m_pad, sizeof res, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (res[2] != 0.0 || res[4] != 0.0 || res[1] >= (double)max_iter) break;
+  }
   *L_out = res[0];
   if (iters) *iters = (int)res[1];
   if (res[2] == 0.0) return fail(SLISTA_ENOTCONV, "power iteration: %d iterations without rtol=%g", (int)res[1], rtol);

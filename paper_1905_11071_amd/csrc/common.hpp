@@ -71,8 +71,11 @@ void gemm_grid(int rows, int ncols, GemmArgs& a);  // fills the tile counts
 // Launchers (kernels_misc.hip)
 hipError_t launch_gram(const float* D, int n, int m, int m_pad, float* G32, uint16_t* Gb, float* Dt,
                        hipStream_t s);
-hipError_t launch_power(const float* G32, int m, int m_pad, int max_iter, double rtol, double* work,
-                        hipStream_t s);
+// FP64 power iteration for L: state in work (2 m_pad + 8 doubles); one step
+// = one matrix-vector product over all CUs and one normalisation.
+hipError_t launch_power_init(int m, int mp, double* work, hipStream_t s);
+hipError_t launch_power_step(const float* G32, int m, int mp, int max_iter, double rtol, double* work,
+                             hipStream_t s);
 hipError_t launch_xsq(const float* X, int N, int n, double* xsq, hipStream_t s);
 hipError_t launch_layer0(const float* C, int N, int ldz, const float* alpha, float lam, float* Z1,
                          hipStream_t s);

@@ -59,54 +59,74 @@ __device__ double start_value(int j) {
 }
 
 // Power iteration for the top eigenvalue of G (FP64 arithmetic on the FP32
-// entries), one workgroup of 1024 threads. v and w live in `work`:
-// work[0 .. mp) = v, work[mp .. 2mp) = w, work[2mp] = L, work[2mp+1] = iters,
-// work[2mp+2] = converged flag. Stops when successive Rayleigh quotients
-// agree to rtol.
-__global__ __launch_bounds__(1024) void k_power(const float* __restrict__ G, int m, int mp,
-                                                int max_iter, double rtol, double* work) {
+// entries), one iteration = k_power_mv (all CUs: one wave per row of G) then
+// k_power_norm (one workgroup: Rayleigh quotient, normalisation, stopping
+// test). State in `work`: [0, mp) = v, [mp, 2mp) = w, then L, iterations,
+// converged flag, previous quotient, zero-vector flag. Once a stop condition
+// holds the later launches return at once, so the host can enqueue batches of
+// iterations and test the flags between batches. Stops when successive
+// Rayleigh quotients agree to rtol.
+constexpr int kPowL = 0, kPowIt = 1, kPowConv = 2, kPowPrev = 3, kPowZero = 4;
+
+__device__ __forceinline__ bool power_done(const double* st, int max_iter) {
+  return st[kPowConv] != 0.0 || st[kPowZero] != 0.0 || st[kPowIt] >= (double)max_iter;
+}
+
+__global__ __launch_bounds__(1024) void k_power_init(int m, int mp, double* work) {
   __shared__ double sh[1024];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
-  double* v = work;
-  double* w = work + mp;
+  const int tid = threadIdx.x;
   double nrm = 0.0;
   for (int j = tid; j < m; j += blockDim.x) nrm += start_value(j) * start_value(j);
   nrm = sqrt(block_sum(nrm, sh));
-  for (int j = tid; j < mp; j += blockDim.x) v[j] = j < m ? start_value(j) / nrm : 0.0;
-  __syncthreads();
-  double prev = 0.0, rq = 0.0;
-  int it = 0, conv = 0;
-  while (it < max_iter) {
-    ++it;
-    for (int i = wave; i < m; i += nwaves) {
-      double s = 0.0;
-      for (int j = lane; j < m; j += 64) s += (double)G[(size_t)i * mp + j] * v[j];
-      for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-      if (lane == 0) w[i] = s;
-    }
-    __threadfence_block();
-    __syncthreads();
-    double pr = 0.0, pw = 0.0;
-    for (int j = tid; j < m; j += blockDim.x) {
-      pr += v[j] * w[j];
-      pw += w[j] * w[j];
-    }
-    rq = block_sum(pr, sh);
-    const double nw = sqrt(block_sum(pw, sh));
-    if (nw == 0.0) break;
-    for (int j = tid; j < m; j += blockDim.x) v[j] = w[j] / nw;
-    __threadfence_block();
-    __syncthreads();
-    if (it > 1 && fabs(rq - prev) <= rtol * fabs(rq)) {
-      conv = 1;
-      break;
-    }
-    prev = rq;
+  for (int j = tid; j < mp; j += blockDim.x) work[j] = j < m ? start_value(j) / nrm : 0.0;
+  if (tid < 8) work[2 * mp + tid] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_power_mv(const float* __restrict__ G, int m, int mp, int max_iter,
+                                                  double* __restrict__ work) {
+  const double* st = work + 2 * mp;
+  if (power_done(st, max_iter)) return;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= m) return;
+  const double* v = work;
+  double s = 0.0;
+  for (int j = lane; j < m; j += 64) s += (double)G[(size_t)i * mp + j] * v[j];
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) work[mp + i] = s;
+}
+
+__global__ __launch_bounds__(1024) void k_power_norm(int m, int mp, int max_iter, double rtol, double* work) {
+  __shared__ double sh[1024];
+  double* st = work + 2 * mp;
+  if (power_done(st, max_iter)) return;
+  const int tid = threadIdx.x;
+  double* v = work;
+  const double* w = work + mp;
+  double pr = 0.0, pw = 0.0;
+  for (int j = tid; j < m; j += blockDim.x) {
+    pr += v[j] * w[j];
+    pw += w[j] * w[j];
   }
+  const double rq = block_sum(pr, sh);
+  const double nw = sqrt(block_sum(pw, sh));
+  const double it = st[kPowIt] + 1.0;
+  const double prev = st[kPowPrev];
+  __syncthreads();  // every thread has read the state before thread 0 updates it
+  if (nw == 0.0) {
+    if (tid == 0) {
+      st[kPowIt] = it;
+      st[kPowL] = rq;
+      st[kPowZero] = 1.0;
+    }
+    return;
+  }
+  for (int j = tid; j < m; j += blockDim.x) v[j] = w[j] / nw;
   if (tid == 0) {
-    work[2 * mp] = rq;
-    work[2 * mp + 1] = (double)it;
-    work[2 * mp + 2] = (double)conv;
+    st[kPowIt] = it;
+    st[kPowL] = rq;
+    st[kPowPrev] = rq;
+    if (it > 1.0 && fabs(rq - prev) <= rtol * fabs(rq)) st[kPowConv] = 1.0;
   }
 }
 
@@ -258,9 +278,15 @@ hipError_t launch_gram(const float* D, int n, int m, int mp, float* G32, uint16_
   return hipGetLastError();
 }
 
-hipError_t launch_power(const float* G32, int m, int mp, int max_iter, double rtol, double* work,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_power, dim3(1), dim3(1024), 0, s, G32, m, mp, max_iter, rtol, work);
+hipError_t launch_power_init(int m, int mp, double* work, hipStream_t s) {
+  hipLaunchKernelGGL(k_power_init, dim3(1), dim3(1024), 0, s, m, mp, work);
+  return hipGetLastError();
+}
+
+hipError_t launch_power_step(const float* G32, int m, int mp, int max_iter, double rtol, double* work,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_power_mv, dim3((m + 3) / 4), dim3(256), 0, s, G32, m, mp, max_iter, work);
+  hipLaunchKernelGGL(k_power_norm, dim3(1), dim3(1024), 0, s, m, mp, max_iter, rtol, work);
   return hipGetLastError();
 }
 
