@@ -47,3 +47,24 @@ def mean_gap_rel_error(D, X, lam, Z_gpu, Z_orc, Zstar):
     g_gpu = float(np.mean(oracle.objective(D, X, Z_gpu, lam) - Fs))
     g_orc = float(np.mean(oracle.objective(D, X, Z_orc, lam) - Fs))
     return abs(g_gpu - g_orc) / g_orc, g_gpu, g_orc
+
+
+def round_to_bf16(a):
+    """Round to the nearest bfloat16 (ties to even), returned as float64."""
+    f = np.ascontiguousarray(a, np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def gap_tolerance(prec: str, T: int, gap_orc: float, gap_rounded: float) -> float:
+    """Tolerance on the relative error of the mean gap.
+
+    The nominal figure (GAP_TOL) assumes the gap is resolvable in the working
+    precision. Near convergence it is not: rounding the oracle's exact z^T to
+    the precision of the device iterate (FP32) or of its contraction operand
+    (BF16) already moves the mean gap by rho = |gap(rounded) - gap| / gap, and
+    each of the T layers rounds once more, so the tolerance is
+    max(GAP_TOL, T * rho)."""
+    rho = abs(gap_rounded - gap_orc) / gap_orc
+    return max(GAP_TOL[prec], T * rho)

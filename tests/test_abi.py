@@ -108,3 +108,16 @@ def test_batch_and_autotune_reject_null_arguments(lib):
     assert lib.slista_batch_run(None, None) == -1
     assert lib.slista_batch_replay(None, None) == -1
     assert lib.slista_batch_destroy(None) == 0
+
+
+def test_bf16_rounding_helper_matches_torch():
+    """The tests' BF16 rounding (used for the gap resolution floor) is
+    round-to-nearest-even, as torch's float32 -> bfloat16 conversion."""
+    import numpy as np
+    import torch
+    from tests.gpu_common import round_to_bf16
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-20, 20, 10000),
+                        [0.0, -0.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8]]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).double().numpy()
+    assert np.array_equal(round_to_bf16(x), ref)
