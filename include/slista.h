@@ -261,6 +261,33 @@ SLISTA_API int slista_batch_destroy(slista_batch* batch);
 SLISTA_API int slista_set_option(int option, int value);
 
 /* ---------------------------------------------------------------------------
+ * Learning the step sizes (Appendix D, "Training the networks"): full-batch
+ * sub-gradient descent on the mean loss of Eq. (15) with a backtracking
+ * learning rate. From steps alpha with loss J and gradient g, each iteration
+ * tries alpha' = max(alpha - eta g, 0) (FP64 arithmetic, rounded to FP32):
+ * if J(alpha') < J it is accepted and eta doubles, otherwise eta halves and
+ * the next candidate is tried, at most max_halvings times; an iteration with
+ * no decrease ends the loop. J is the FP64 mean of the per-sample objectives.
+ *
+ * alpha   device [T], in: the starting steps, out: the learned steps.
+ * Z       device [N, m], out: the codes of the last evaluated candidate.
+ * losses  host [iters + 1] or NULL: J at the start and after each accepted
+ *         iteration; *accepted (host, may be NULL) = accepted iterations;
+ *         *lr_out (host, may be NULL) = the final learning rate.
+ * ws      device workspace of slista_train_workspace_size bytes, 256-byte
+ *         aligned (the forward/backward workspace with the full tape plus
+ *         the gradient, the candidate and the loss weights).
+ * Synchronises `stream` once per candidate (the accept test is on the host).
+ * Errors: SLISTA_EINVAL for NULL pointers, N or T < 1, iters < 0, lr not
+ * finite and positive, max_halvings outside [0, 1000], a short or misaligned
+ * workspace, or kernel timing switched on.
+ * ------------------------------------------------------------------------- */
+SLISTA_API int slista_train_workspace_size(const slista_dict* dict, int N, int T, int prec, size_t* bytes);
+SLISTA_API int slista_train(const slista_dict* dict, const float* X, int N, float lambda, float* alpha, int T,
+                            int prec, int iters, double lr, int max_halvings, float* Z, double* losses,
+                            int* accepted, double* lr_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Autotuning of the persistent kernels' tile variant
  *
  * slista_autotune runs slista_forward_backward once per tile variant

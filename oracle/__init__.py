@@ -14,4 +14,6 @@ from .slista import (  # noqa: F401
     kkt_residual,
     lasso_solution,
     brute_force_lasso,
+    train_steps,
+    support_lipschitz,
 )

@@ -32,6 +32,8 @@ __all__ = [
     "kkt_residual",
     "lasso_solution",
     "brute_force_lasso",
+    "train_steps",
+    "support_lipschitz",
 ]
 
 
@@ -275,3 +277,54 @@ def brute_force_lasso(D, x, lam) -> np.ndarray:
         if f < best_f:
             best, best_f = z, f
     return best
+
+
+def train_steps(D, X, lam, alpha0, iters: int, lr: float, max_halvings: int = 30):
+    """Full-batch sub-gradient descent on the step sizes with a backtracking
+    learning rate (Appendix D, "Training the networks"), on the mean loss of
+    Eq. (15). The paper does not spell the backtracking rule out; the reading
+    taken: from the current steps alpha with loss J and gradient g, try
+    alpha' = max(alpha - eta g, 0); if J(alpha') < J accept it and double eta,
+    otherwise halve eta and try again, at most max_halvings times per
+    iteration (no decrease found: stop).
+
+    Returns (alpha [T], losses [accepted + 1], eta). Pinned by: the loss
+    sequence decreases strictly; the first accepted step equals
+    max(alpha0 - eta g, 0) with g from forward_backward; the learned steps of
+    the paper's 10 x 20, lambda = 0.2 setting exceed 1/L in the late layers
+    and stay below the largest 1/L_S of the supports reached (Section 4.1).
+    """
+    D, X = _f64(D), _f64(X)
+    alpha = _f64(alpha0).reshape(-1).copy()
+    N = X.shape[0]
+    dF = np.full(N, 1.0 / N)
+    _, F, g = forward_backward(D, X, lam, alpha, dF=dF)
+    J = float(np.mean(F[-1]))
+    losses = [J]
+    eta = float(lr)
+    for _ in range(iters):
+        accepted = False
+        for _ in range(max_halvings + 1):
+            cand = np.maximum(alpha - eta * g, 0.0)
+            Jc = float(np.mean(forward(D, X, lam, cand)[1][-1]))
+            if Jc < J:
+                alpha, J = cand, Jc
+                _, _, g = forward_backward(D, X, lam, alpha, dF=dF)
+                eta *= 2.0
+                accepted = True
+                break
+            eta *= 0.5
+        if not accepted:
+            break
+        losses.append(J)
+    return alpha, np.array(losses), eta
+
+
+def support_lipschitz(D, z) -> float:
+    """L_S = greatest eigenvalue of D_S^T D_S for the support S of z (Section
+    3, Oracle-ISTA); 0 for an empty support."""
+    D = _f64(D)
+    S = np.flatnonzero(_f64(z) != 0.0)
+    if S.size == 0:
+        return 0.0
+    return float(scipy.linalg.eigvalsh(D[:, S].T @ D[:, S])[-1])

@@ -11,6 +11,7 @@ from .ops import (  # noqa: F401
     autotune,
     tune_load,
     tune_save,
+    train,
     backward,
     forward,
     forward_backward,

@@ -43,6 +43,10 @@ SIGNATURES = {
     "slista_autotune": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _c_int, _vp, _vp, _vp, _size_t, _vp,
                                  ctypes.POINTER(_c_int), ctypes.POINTER(_c_double)]),
     "slista_batch_autotune": (_c_int, [_vp, _vp, ctypes.POINTER(_c_int)]),
+    "slista_train_workspace_size": (_c_int, [_vp, _c_int, _c_int, _c_int, ctypes.POINTER(_size_t)]),
+    "slista_train": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _c_int, _c_double, _c_int, _vp,
+                              ctypes.POINTER(_c_double), ctypes.POINTER(_c_int), ctypes.POINTER(_c_double), _vp,
+                              _size_t, _vp]),
     "slista_tune_save": (_c_int, [ctypes.c_char_p]),
     "slista_tune_load": (_c_int, [ctypes.c_char_p]),
     "slista_batch_create": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_vp)]),

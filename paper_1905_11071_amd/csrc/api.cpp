@@ -741,6 +741,104 @@ int slista_forward_backward(const slista_dict* dict, const float* X, int N, floa
   return run_backward(r, lambda, alpha, prec, nullptr, nullptr, (float)(1.0 / N), dalpha, F || loss, F, loss);
 }
 
+// ------------------------------------------------------------- training
+// Workspace of slista_train: the forward/backward workspace with the full
+// tape, then the gradient [T], the candidate steps [T], the FP64 loss and
+// the loss weights dF = 1/N [N], each 256-byte aligned.
+static size_t train_extra_offsets(const slista::Dict& d, int N, int T, size_t off[4]) {
+  size_t o = align256(make_layout(d, N, T, 1).total);
+  off[0] = o;
+  o += align256((size_t)T * sizeof(float));
+  off[1] = o;
+  o += align256((size_t)T * sizeof(float));
+  off[2] = o;
+  o += align256(sizeof(double));
+  off[3] = o;
+  o += align256((size_t)N * sizeof(float));
+  return o;
+}
+
+int slista_train_workspace_size(const slista_dict* dict, int N, int T, int prec, size_t* bytes) {
+  if (!dict || !bytes) return fail(SLISTA_EINVAL, "dict or bytes is NULL");
+  if (N < 1 || N > kMaxN || T < 1 || T > kMaxT) return fail(SLISTA_EINVAL, "training needs 1 <= N, 1 <= T");
+  if (prec != SLISTA_FP32 && prec != SLISTA_BF16) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
+  size_t off[4];
+  *bytes = train_extra_offsets(dict->d, N, T, off);
+  return SLISTA_OK;
+}
+
+int slista_train(const slista_dict* dict, const float* X, int N, float lambda, float* alpha, int T, int prec,
+                 int iters, double lr, int max_halvings, float* Z, double* losses, int* accepted, double* lr_out,
+                 void* ws, size_t ws_bytes, void* stream) {
+  if (!dict || !X || !alpha || !Z || !ws) return fail(SLISTA_EINVAL, "dict, X, alpha, Z or ws is NULL");
+  if (N < 1 || N > kMaxN || T < 1 || T > kMaxT) return fail(SLISTA_EINVAL, "training needs 1 <= N, 1 <= T");
+  if (iters < 0 || max_halvings < 0 || max_halvings > 1000)
+    return fail(SLISTA_EINVAL, "iters >= 0 and 0 <= max_halvings <= 1000 required");
+  if (!(lr > 0.0) || !std::isfinite(lr)) return fail(SLISTA_EINVAL, "lr must be finite and > 0");
+  if (g_prof.on) return fail(SLISTA_EINVAL, "kernel timing must be off while training");
+  size_t off[4];
+  const size_t need = train_extra_offsets(dict->d, N, T, off);
+  if (((uintptr_t)ws & 255) || ws_bytes < need)
+    return fail(SLISTA_EINVAL, "workspace must be 256-byte aligned with %zu bytes", need);
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  const size_t main_bytes = off[0];
+  float* g = (float*)(w + off[0]);
+  float* cand = (float*)(w + off[1]);
+  double* Jd = (double*)(w + off[2]);
+  float* dF = (float*)(w + off[3]);
+  const Run r{&dict->d, make_layout(dict->d, N, T, 1), w, N, T, s};
+  int st;
+  LAUNCH(kKOther, s, slista::launch_fill(dF, (size_t)N, (float)(1.0 / N), s));
+  // loss and gradient at the starting steps
+  if ((st = slista_forward_backward(dict, X, N, lambda, alpha, T, prec, Z, nullptr, (float*)Jd, g, 1, ws,
+                                    main_bytes, stream)) != SLISTA_OK)
+    return st;
+  auto loss_now = [&](double* out) -> int {
+    LAUNCH(kKOther, s, slista::launch_mean_d(r.Fd(), N, Jd, s));
+    HIP_TRY(hipMemcpyAsync(out, Jd, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SLISTA_OK;
+  };
+  double J = 0.0;
+  if ((st = loss_now(&J)) != SLISTA_OK) return st;
+  if (losses) losses[0] = J;
+  double eta = lr;
+  int acc = 0;
+  for (int it = 0; it < iters; ++it) {
+    bool ok = false;
+    for (int h = 0; h <= max_halvings; ++h) {
+      LAUNCH(kKOther, s, slista::launch_alpha_step(alpha, g, eta, T, cand, s));
+      // forward at the candidate, keeping the tape for the gradient if accepted
+      // (the FP32 loss output lands in the FP64 slot, which loss_now overwrites)
+      if ((st = slista_forward(dict, X, N, lambda, cand, T, prec, Z, nullptr, 0, (float*)Jd, 1, ws, main_bytes,
+                               stream)) != SLISTA_OK)
+        return st;
+      double Jc = 0.0;
+      if ((st = loss_now(&Jc)) != SLISTA_OK) return st;
+      if (!(Jc < J)) {
+        eta *= 0.5;
+        continue;
+      }
+      HIP_TRY(hipMemcpyAsync(alpha, cand, (size_t)T * sizeof(float), hipMemcpyDeviceToDevice, s));
+      J = Jc;
+      if ((st = slista_backward(dict, X, N, lambda, alpha, T, prec, nullptr, dF, g, 1, ws, main_bytes, stream)) !=
+          SLISTA_OK)
+        return st;
+      eta *= 2.0;
+      ok = true;
+      break;
+    }
+    if (!ok) break;
+    ++acc;
+    if (losses) losses[acc] = J;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (accepted) *accepted = acc;
+  if (lr_out) *lr_out = eta;
+  return SLISTA_OK;
+}
+
 int slista_autotune(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha, int T, int prec,
                     int ckpt_every, float* Z, float* dalpha, void* ws, size_t ws_bytes, void* stream, int* best,
                     double* ms) {

@@ -84,6 +84,9 @@ hipError_t launch_fill(float* p, size_t count, float v, hipStream_t s);
 hipError_t launch_reduce_f(const double* xsq, const double* fpart, int col_tiles, int N, float* F,
                            double* Fd, hipStream_t s);
 hipError_t launch_reduce_loss(const double* Fd, int N, float* loss, hipStream_t s);
+// Training loop helpers: FP64 mean of Fd; candidate steps max(alpha - eta g, 0).
+hipError_t launch_mean_d(const double* Fd, int N, double* out, hipStream_t s);
+hipError_t launch_alpha_step(const float* alpha, const float* g, double eta, int T, float* cand, hipStream_t s);
 hipError_t launch_bwd0(const float* V0, const float* Z1, int N, int ldz, double* dpart, int nblocks,
                        hipStream_t s);
 hipError_t launch_reduce_dalpha(const double* dpart, int T, int P, int count0, int count, const float* alpha,

@@ -198,6 +198,25 @@ __global__ void k_reduce_loss(const double* __restrict__ Fd, int N, float* __res
   if (threadIdx.x == 0) *loss = N > 0 ? (float)(s / N) : 0.f;
 }
 
+// Mean of the per-sample objectives in FP64 (the training loop's loss).
+__global__ void k_mean_d(const double* __restrict__ Fd, int N, double* __restrict__ out) {
+  __shared__ double sh[kRedThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) s += Fd[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) *out = N > 0 ? s / N : 0.0;
+}
+
+// Candidate steps of one training iteration: max(alpha - eta g, 0) (FP64
+// arithmetic, rounded once to FP32).
+__global__ void k_alpha_step(const float* __restrict__ alpha, const float* __restrict__ g, double eta, int T,
+                             float* __restrict__ cand) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const double a = (double)alpha[t] - eta * (double)g[t];
+  cand[t] = (float)(a > 0.0 ? a : 0.0);
+}
+
 // Layer 0 of the adjoint: z^(0) = 0, so the partial is sum v^0 (0 - z^(1)).
 __global__ void k_bwd0(const float* __restrict__ V0, const float* __restrict__ Z1, size_t total,
                        double* __restrict__ dpart) {
@@ -327,6 +346,17 @@ hipError_t launch_reduce_f(const double* xsq, const double* fpart, int col_tiles
 
 hipError_t launch_reduce_loss(const double* Fd, int N, float* loss, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(kRedThreads), 0, s, Fd, N, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_mean_d(const double* Fd, int N, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mean_d, dim3(1), dim3(kRedThreads), 0, s, Fd, N, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_alpha_step(const float* alpha, const float* g, double eta, int T, float* cand, hipStream_t s) {
+  if (T == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_alpha_step, dim3((T + 255) / 256), dim3(256), 0, s, alpha, g, eta, T, cand);
   return hipGetLastError();
 }
 

@@ -194,6 +194,30 @@ def autotune(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, pr
     return best.value, list(ms)
 
 
+def train(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, iters: int, lr: float,
+          prec="fp32", max_halvings: int = 30):
+    """Learn the step sizes in place (alpha, a device float32 [T] tensor) by
+    full-batch sub-gradient descent with a backtracking learning rate on the
+    mean loss. Returns (losses [accepted + 1] as a list, final learning rate)."""
+    target = alpha
+    X, alpha = _check_inputs(d, X, alpha)
+    N, T = int(X.shape[0]), int(alpha.shape[0])
+    p = _prec(prec)
+    nbytes = ctypes.c_size_t()
+    check(lib().slista_train_workspace_size(d.handle, N, T, p, ctypes.byref(nbytes)))
+    ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=d.device)
+    Z = torch.empty(N, d.m, device=d.device, dtype=torch.float32)
+    losses = (ctypes.c_double * (iters + 1))()
+    acc = ctypes.c_int()
+    lr_out = ctypes.c_double()
+    check(lib().slista_train(d.handle, X.data_ptr(), N, float(lam), alpha.data_ptr(), T, p, int(iters), float(lr),
+                             int(max_halvings), Z.data_ptr(), losses, ctypes.byref(acc), ctypes.byref(lr_out),
+                             ws.data_ptr(), ws.numel(), _stream(d.device)))
+    if alpha.data_ptr() != target.data_ptr():
+        target.copy_(alpha)
+    return [losses[i] for i in range(acc.value + 1)], lr_out.value
+
+
 def tune_save(path: str) -> None:
     check(lib().slista_tune_save(path.encode()))
 

@@ -174,3 +174,47 @@ def test_adjoint_is_linear_in_seeds():
     _, _, g2 = oracle.forward_backward(pb.D, pb.X, pb.lam, alpha, dF=dF)
     _, _, g3 = oracle.forward_backward(pb.D, pb.X, pb.lam, alpha, dZ=dZ, dF=dF)
     np.testing.assert_allclose(g3, g1 + g2, rtol=1e-12, atol=1e-14)
+
+
+# --- step-size training (Appendix D) and per-support Lipschitz constants ------
+
+def test_support_lipschitz_special_cases():
+    pb = synth.make_problem(10, 20, 4, 0.1, 0.0, 0.1, seed=31)
+    z = np.zeros(20)
+    assert oracle.support_lipschitz(pb.D, z) == 0.0
+    z[3] = 1.0                                    # one atom: L_S = ||D_j||^2 (1 up to the FP32 rounding of D)
+    assert abs(oracle.support_lipschitz(pb.D, z) - float(pb.D[:, 3] @ pb.D[:, 3])) < 1e-14
+    assert abs(oracle.support_lipschitz(pb.D, np.ones(20)) - oracle.lipschitz(pb.D)) < 1e-10
+    Q, _ = np.linalg.qr(np.random.default_rng(0).standard_normal((6, 6)))
+    assert abs(oracle.support_lipschitz(Q, np.ones(6)) - 1.0) < 1e-12   # orthogonal D
+
+
+def test_train_steps_update_rule_and_monotone_loss():
+    """Each accepted iterate is max(alpha - eta g, 0) with g the oracle's
+    gradient at the previous iterate, and the loss decreases strictly."""
+    pb = synth.make_binf_problem(10, 20, 300, 0.2, seed=1101)
+    L = oracle.lipschitz(pb.D)
+    a0 = np.full(12, 1.0 / L)
+    a1, l1, eta1 = oracle.train_steps(pb.D, pb.X, pb.lam, a0, 1, lr=1.0 / L)
+    assert len(l1) == 2 and l1[1] < l1[0]
+    _, _, g0 = oracle.forward_backward(pb.D, pb.X, pb.lam, a0, dF=np.full(pb.N, 1.0 / pb.N))
+    assert np.allclose(a1, np.maximum(a0 - (eta1 / 2.0) * g0, 0.0), rtol=0, atol=1e-15)
+    _, l20, _ = oracle.train_steps(pb.D, pb.X, pb.lam, a0, 20, lr=1.0 / L)
+    assert np.all(np.diff(l20) < 0)
+
+
+def test_learned_steps_exceed_one_over_L_within_support_range():
+    """Section 4.1 / Fig. 4 setting (10 x 20 dictionary, lambda = 0.2, 1000
+    samples on B_inf, 20 layers): the learned steps of the late layers are
+    larger than 1/L and no larger than the largest 1/L_S of the supports the
+    layer's outputs reach."""
+    pb = synth.make_binf_problem(10, 20, 1000, 0.2, seed=1101)
+    L = oracle.lipschitz(pb.D)
+    T = 20
+    alpha, losses, _ = oracle.train_steps(pb.D, pb.X, pb.lam, np.full(T, 1.0 / L), 200, lr=1.0 / L)
+    assert losses[-1] < losses[0]
+    _, _, its = oracle.forward(pb.D, pb.X, pb.lam, alpha, return_iterates=True)
+    for t in range(T // 2, T):
+        assert alpha[t] > 1.0 / L
+        inv_ls = [1.0 / oracle.support_lipschitz(pb.D, z) for z in its[t + 1] if np.any(z)]
+        assert alpha[t] <= max(inv_ls)
