@@ -220,6 +220,34 @@ def uneven_report(sl, torch, specs, inputs, prec: str, T: int, ckpt: int, reps: 
     return out
 
 
+def training_report(sl, torch, iters: int) -> dict:
+    """Step-size training (full-batch sub-gradient descent with backtracking)
+    on the 64 x 256 learned-step workload (N = 4096, T = 20), FP32 and BF16:
+    accepted iterations, final loss and wall time per accepted iteration."""
+    import numpy as np
+    import synth
+    c = synth.CONFIGS["grad_64x256"]
+    pb = synth.make_problem(c["n"], c["m"], c["N"], c["p"], c["sigma"], c["lam_frac"], c["seed"])
+    dev = torch.device("cuda:0")
+    d = sl.Dictionary(torch.tensor(pb.D32(), device=dev))
+    X = torch.tensor(pb.X32(), device=dev)
+    L, _ = d.lipschitz(max_iter=100_000, rtol=1e-12)
+    out = {"workload": "grad_64x256", "n": pb.n, "m": pb.m, "N": pb.N, "T": c["T"], "iterations": iters}
+    for p in ("fp32", "bf16"):
+        alpha = torch.full((c["T"],), float(np.float32(1.0 / L)), device=dev, dtype=torch.float32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses, eta = sl.train(d, X, pb.lam, alpha, iters, 1.0 / L, prec=p)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        acc = len(losses) - 1
+        out[p] = {"accepted": acc, "loss_start": losses[0], "loss_end": losses[-1],
+                  "ms_per_accepted_iteration": round(dt * 1e3 / max(acc, 1), 3),
+                  "alpha_L_first_last": [round(float(alpha[0]) * L, 3), round(float(alpha[-1]) * L, 3)]}
+    d.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,6 +262,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gap", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven 64-problem batch")
+    ap.add_argument("--no-train", action="store_true", help="skip the step-size training report")
+    ap.add_argument("--train-iters", type=int, default=30)
     ap.add_argument("--uneven-precs", default="bf16,fp32")
     ap.add_argument("--uneven-reps", type=int, default=3)
     ap.add_argument("--copy-calib", action="store_true",
@@ -311,6 +341,11 @@ def main() -> int:
             dd.close()
         del inputs
 
+    train = None
+    if not args.no_train:
+        train = training_report(sl, torch, args.train_iters)
+        print(f"[bench] training {train}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pb, np.asarray(alpha.cpu().numpy(), np.float64), min(args.cpu_sample, pb.N))
@@ -343,6 +378,7 @@ def main() -> int:
                           for p, r in res.items()},
         "objective_gap": gap,
         "uneven_batch": uneven,
+        "training": train,
         "autotune": tuned or {"forced_variant": args.variant},
     }
     print(json.dumps(line))
