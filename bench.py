@@ -51,7 +51,7 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "a22f2bc9f1b700b6946fe9549b930d04d22536905975f08ea4ac96fb3292e582",
+    "sources_sha256": "ee9fbb146613b8f638d926065d8a0cf3d9a266a012e50c11186ed871b530ab9d",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {

@@ -258,6 +258,11 @@ SLISTA_API int slista_batch_destroy(slista_batch* batch);
  * the dictionary's m_pad falls back to the default. */
 #define SLISTA_OPT_PERSIST_VARIANT 2
 
+/* Options are process-wide: set them before other threads call the library.
+ * The autotuners use per-thread overrides while timing, and the tuning table
+ * they fill is shared and guarded, so tuning in one thread leaves the
+ * options other threads see unchanged. Calls on one stream are ordered by it;
+ * calls that share a workspace must not overlap. */
 SLISTA_API int slista_set_option(int option, int value);
 
 /* ---------------------------------------------------------------------------

@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <cstring>
 #include <new>
@@ -129,8 +130,16 @@ struct ProfScope {
 int g_kernel_family = 0;
 // Tile variant of the persistent kernels (0 = default; see persist_rows).
 int g_persist_variant = 0;
-// Autotuned variants: (precision, column-pass bucket, floor(log2 N)) -> variant.
+// Autotuned variants: (precision, column-pass bucket, floor(log2 N)) -> variant,
+// shared by all threads (g_tuned_mu guards it).
 std::map<std::tuple<int, int, int>, int> g_tuned;
+std::mutex g_tuned_mu;
+// The autotuners run their timing calls with these per-thread overrides of
+// the family and the variant, so other threads keep their settings.
+thread_local int t_family_override = -1;
+thread_local int t_variant_override = -1;
+
+int kernel_family() { return t_family_override >= 0 ? t_family_override : g_kernel_family; }
 
 int log2_bucket(int N) {
   int b = 0;
@@ -144,9 +153,16 @@ int log2_bucket(int N) {
 // The tile variant a call uses: the forced one, else the tuned one, else 0
 // (the kernels' built-in default).
 int variant_for(int prec, int m_pad, int N) {
+  if (t_variant_override >= 0) return t_variant_override;
   if (g_persist_variant != 0) return g_persist_variant;
+  std::lock_guard<std::mutex> lock(g_tuned_mu);
   const auto it = g_tuned.find(std::make_tuple(prec, slista::persist_np(m_pad), log2_bucket(N)));
   return it == g_tuned.end() ? 0 : it->second;
+}
+
+void record_tuned(int prec, int np, int nbucket, int variant) {
+  std::lock_guard<std::mutex> lock(g_tuned_mu);
+  g_tuned[std::make_tuple(prec, np, nbucket)] = variant;
 }
 
 constexpr int kMaxN = 1 << 26;
@@ -243,7 +259,7 @@ const void* gram_for(const slista::Dict& d, int prec) {
 }
 
 bool use_persist(const Run& r, int prec) {
-  if (g_kernel_family == 1) return false;
+  if (kernel_family() == 1) return false;
   return slista::persist_rows(prec, r.d->m_pad, variant_for(prec, r.d->m_pad, r.N)) > 0;
 }
 
@@ -854,8 +870,7 @@ int slista_autotune(const slista_dict* dict, const float* X, int N, float lambda
     return SLISTA_OK;
   }
   hipStream_t s = (hipStream_t)stream;
-  const int saved_family = g_kernel_family, saved_variant = g_persist_variant;
-  g_kernel_family = 2;
+  t_family_override = 2;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int st = SLISTA_OK, bestv = 1;
   double bestms = 1e300;
@@ -864,7 +879,7 @@ int slista_autotune(const slista_dict* dict, const float* X, int N, float lambda
   }
   for (int v = 1; v <= slista::kPersistMaxVariant && st == SLISTA_OK; ++v) {
     if (!slista::persist_has_variant(dict->d.m_pad, v)) continue;
-    g_persist_variant = v;
+    t_variant_override = v;
     st = slista_forward_backward(dict, X, N, lambda, alpha, T, prec, Z, nullptr, nullptr, dalpha, ckpt_every, ws,
                                  ws_bytes, stream);
     if (st != SLISTA_OK) break;
@@ -888,10 +903,10 @@ int slista_autotune(const slista_dict* dict, const float* X, int N, float lambda
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  g_kernel_family = saved_family;
-  g_persist_variant = saved_variant;
+  t_family_override = -1;
+  t_variant_override = -1;
   if (st != SLISTA_OK) return st;
-  g_tuned[std::make_tuple(prec, slista::persist_np(dict->d.m_pad), log2_bucket(N))] = bestv;
+  record_tuned(prec, slista::persist_np(dict->d.m_pad), log2_bucket(N), bestv);
   *best = bestv;
   return SLISTA_OK;
 }
@@ -900,6 +915,7 @@ int slista_tune_save(const char* path) {
   if (!path) return fail(SLISTA_EINVAL, "path is NULL");
   FILE* f = std::fopen(path, "w");
   if (!f) return fail(SLISTA_EINVAL, "cannot open %s for writing", path);
+  std::lock_guard<std::mutex> lock(g_tuned_mu);
   for (const auto& kv : g_tuned)
     std::fprintf(f, "%d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), kv.second);
   std::fclose(f);
@@ -914,7 +930,7 @@ int slista_tune_load(const char* path) {
   while (std::fscanf(f, "%d %d %d %d", &prec, &np, &nb, &v) == 4) {
     if ((prec == SLISTA_FP32 || prec == SLISTA_BF16) && (np == 1 || np == 2 || np == 4 || np == 8) && nb >= 0 &&
         nb < 31 && v >= 1 && v <= slista::kPersistMaxVariant) {
-      g_tuned[std::make_tuple(prec, np, nb)] = v;
+      record_tuned(prec, np, nb, v);
       ++n;
     }
   }
@@ -1142,7 +1158,7 @@ int slista_batch_autotune(slista_batch* b, void* stream, int* variants) {
     batch_set_variant(b, bi, bestv);
     if (st == SLISTA_OK) {
       const auto& bk = b->buckets[bi];
-      g_tuned[std::make_tuple(b->prec, bk.np, log2_bucket(bk.rows_total))] = bestv;
+      record_tuned(b->prec, bk.np, log2_bucket(bk.rows_total), bestv);
     }
   }
   (void)hipEventDestroy(e0);
