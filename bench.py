@@ -51,7 +51,7 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "ee9fbb146613b8f638d926065d8a0cf3d9a266a012e50c11186ed871b530ab9d",
+    "sources_sha256": "07800a5274fc89da6709b0a2ddedb8b928448352046bab006cc68ecfc787290f",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {

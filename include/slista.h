@@ -266,6 +266,23 @@ SLISTA_API int slista_batch_destroy(slista_batch* batch);
 SLISTA_API int slista_set_option(int option, int value);
 
 /* ---------------------------------------------------------------------------
+ * FISTA (Beck & Teboulle), the accelerated baseline of the paper's Figures 2
+ * and D.2: from z^0 = y^0 = 0, for t = 0 .. T-1
+ *   z^{t+1} = ST(y^t - alpha_t (G y^t - c), lam alpha_t),
+ *   y^{t+1} = z^{t+1} + beta_t (z^{t+1} - z^t),
+ * beta_t = (tau_t - 1) / tau_{t+1}, tau_0 = 1, tau_{t+1} = (1 + sqrt(1 +
+ * 4 tau_t^2)) / 2 (computed on the device). Forward only, per-layer kernels
+ * (G y^t on MFMA in the given precision, the update fused). Z [N, m] out;
+ * F [N] (F(z^T)) and loss (mean F) out if not NULL. Workspace of
+ * slista_fista_workspace_size bytes, 256-byte aligned. Errors as for
+ * slista_forward.
+ * ------------------------------------------------------------------------- */
+SLISTA_API int slista_fista_workspace_size(const slista_dict* dict, int N, int T, int prec, size_t* bytes);
+SLISTA_API int slista_fista(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha,
+                            int T, int prec, float* Z, float* F, float* loss, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* ---------------------------------------------------------------------------
  * Learning the step sizes (Appendix D, "Training the networks"): full-batch
  * sub-gradient descent on the mean loss of Eq. (15) with a backtracking
  * learning rate. From steps alpha with loss J and gradient g, each iteration

@@ -16,4 +16,6 @@ from .slista import (  # noqa: F401
     brute_force_lasso,
     train_steps,
     support_lipschitz,
+    fista_momentum,
+    fista,
 )

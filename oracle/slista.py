@@ -34,6 +34,8 @@ __all__ = [
     "brute_force_lasso",
     "train_steps",
     "support_lipschitz",
+    "fista_momentum",
+    "fista",
 ]
 
 
@@ -328,3 +330,47 @@ def support_lipschitz(D, z) -> float:
     if S.size == 0:
         return 0.0
     return float(scipy.linalg.eigvalsh(D[:, S].T @ D[:, S])[-1])
+
+
+def fista_momentum(T: int) -> np.ndarray:
+    """Momentum weights of FISTA (Beck & Teboulle 2009), the accelerated
+    baseline of the paper's Figures 2 and D.2: tau_0 = 1,
+    tau_{t+1} = (1 + sqrt(1 + 4 tau_t^2)) / 2, beta_t = (tau_t - 1) / tau_{t+1}
+    (so beta_0 = 0)."""
+    beta = np.zeros(T)
+    tau = 1.0
+    for t in range(T):
+        tau_next = (1.0 + np.sqrt(1.0 + 4.0 * tau * tau)) / 2.0
+        beta[t] = (tau - 1.0) / tau_next
+        tau = tau_next
+    return beta
+
+
+def fista(D, X, lam, alpha, return_iterates: bool = False):
+    """T layers of FISTA from z^(0) = y^(0) = 0, in the factored form:
+        z^(t+1) = ST(y^(t) - alpha_t D^T (D y^(t) - x), lam alpha_t)
+        y^(t+1) = z^(t+1) + beta_t (z^(t+1) - z^(t))
+    with beta_t from fista_momentum. Returns (Z [N, m], F [T+1, N] of the z^(t),
+    and the iterates z^(t) if asked). Pinned by: its first two layers equal
+    ISTA's (beta_0 = 0), and with alpha = 1/L it meets the O(1/t^2) bound
+    F(z^(t)) - F* <= 2 L ||z*||^2 / (t+1)^2."""
+    D, X = _f64(D), _f64(X)
+    alpha = _f64(alpha).reshape(-1)
+    T = alpha.shape[0]
+    beta = fista_momentum(T)
+    N, m = X.shape[0], D.shape[1]
+    z = np.zeros((N, m))
+    y = np.zeros((N, m))
+    F = np.empty((T + 1, N))
+    F[0] = objective(D, X, z, lam)
+    its = [z.copy()]
+    for t in range(T):
+        a = alpha[t]
+        grad = (y @ D.T - X) @ D            # D^T (D y^(t) - x)
+        z_next = soft_threshold(y - a * grad, lam * a)
+        y = z_next + beta[t] * (z_next - z)
+        z = z_next
+        F[t + 1] = objective(D, X, z, lam)
+        if return_iterates:
+            its.append(z.copy())
+    return (z, F, its) if return_iterates else (z, F)

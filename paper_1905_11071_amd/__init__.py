@@ -12,6 +12,7 @@ from .ops import (  # noqa: F401
     tune_load,
     tune_save,
     train,
+    fista,
     backward,
     forward,
     forward_backward,

@@ -757,6 +757,80 @@ int slista_forward_backward(const slista_dict* dict, const float* X, int N, floa
   return run_backward(r, lambda, alpha, prec, nullptr, nullptr, (float)(1.0 / N), dalpha, F || loss, F, loss);
 }
 
+// ------------------------------------------------------------- FISTA
+// Workspace of slista_fista: the forward workspace without a tape (C, norms,
+// objective partials, two z buffers), two y buffers and the momentum weights.
+static size_t fista_offsets(const slista::Dict& d, int N, int T, size_t off[2]) {
+  const Layout L = make_layout(d, N, T, 0);
+  size_t o = align256(L.total);
+  off[0] = o;  // y buffers
+  o += 2 * align256(L.zbytes);
+  off[1] = o;  // beta [T]
+  o += align256((size_t)(T > 0 ? T : 1) * sizeof(float));
+  return o;
+}
+
+int slista_fista_workspace_size(const slista_dict* dict, int N, int T, int prec, size_t* bytes) {
+  if (!dict || !bytes) return fail(SLISTA_EINVAL, "dict or bytes is NULL");
+  if (N < 0 || N > kMaxN || T < 0 || T > kMaxT) return fail(SLISTA_EINVAL, "sizes out of range");
+  if (prec != SLISTA_FP32 && prec != SLISTA_BF16) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
+  size_t off[2];
+  *bytes = fista_offsets(dict->d, N, T, off);
+  return SLISTA_OK;
+}
+
+int slista_fista(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha, int T, int prec,
+                 float* Z, float* F, float* loss, void* ws, size_t ws_bytes, void* stream) {
+  size_t need_fwd = 0;
+  int st = check_common(dict, X, N, lambda, alpha, T, prec, 0, ws, ws_bytes, &need_fwd);
+  if (st != SLISTA_OK) return st;
+  size_t off[2];
+  const size_t need = fista_offsets(dict->d, N, T, off);
+  if (ws_bytes < need) return fail(SLISTA_EINVAL, "workspace must hold %zu bytes", need);
+  if (N > 0 && !Z) return fail(SLISTA_EINVAL, "Z is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if (N == 0) {
+    if (loss) LAUNCH(kKOther, s, slista::launch_fill(loss, 1, 0.f, s));
+    return SLISTA_OK;
+  }
+  const Run r{&dict->d, make_layout(dict->d, N, T, 0), (char*)ws, N, T, s};
+  const int mp = dict->d.m_pad;
+  if (T == 0) return run_forward(r, X, lambda, alpha, prec, Z, F, 0, loss, true);  // Z = 0, F = |x|^2 / 2
+  if ((st = prep(r, X)) != SLISTA_OK) return st;
+  float* ybuf[2] = {(float*)((char*)ws + off[0]), (float*)((char*)ws + off[0] + align256(r.L.zbytes))};
+  float* beta = (float*)((char*)ws + off[1]);
+  LAUNCH(kKOther, s, slista::launch_fista_beta(T, beta, s));
+  // layer 0: y^0 = z^0 = 0, so z^1 = ST(alpha_0 c, lam alpha_0) and y^1 = z^1 (beta_0 = 0)
+  LAUNCH(kKOther, s, slista::launch_layer0(r.C(), N, mp, alpha, lambda, r.slot(1), s));
+  const float* y = r.slot(1);
+  for (int t = 1; t < T; ++t) {
+    slista::GemmArgs g = base_args(r, alpha, lambda);
+    g.A = y;
+    g.Bt = gram_for(*r.d, prec);
+    g.t = t;
+    g.Zt = y;
+    g.Zt1 = r.slot(t);
+    g.Out = r.slot(t + 1);
+    g.Out2 = ybuf[(t + 1) & 1];
+    g.beta = beta;
+    LAUNCH(kKFwd, s, slista::launch_gemm(prec, slista::kEpiFista, false, g, s));
+    y = g.Out2;
+  }
+  LAUNCH(kKOther, s, slista::launch_copy_out(r.slot(T), N, mp, dict->d.m, Z, s));
+  if (F || loss) {
+    slista::GemmArgs g = base_args(r, alpha, lambda);
+    g.A = r.slot(T);
+    g.Bt = gram_for(*r.d, prec);
+    g.t = T - 1;
+    g.Zt = r.slot(T);
+    g.fpart = r.fpart();
+    LAUNCH(kKFinal, s, slista::launch_gemm(prec, slista::kEpiFinal, false, g, s));
+    LAUNCH(kKOther, s, slista::launch_reduce_f(r.xsq(), r.fpart(), r.L.col_tiles, N, F, r.Fd(), s));
+    if (loss) LAUNCH(kKOther, s, slista::launch_reduce_loss(r.Fd(), N, loss, s));
+  }
+  return SLISTA_OK;
+}
+
 // ------------------------------------------------------------- training
 // Workspace of slista_train: the forward/backward workspace with the full
 // tape, then the gradient [T], the candidate steps [T], the FP64 loss and

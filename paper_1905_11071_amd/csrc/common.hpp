@@ -23,7 +23,8 @@ enum Epi : int {
   kEpiFwd = 1,    // z^{t+1} = ST(z^t - a (P - c), lam a); F(z^t) partial  (one layer)
   kEpiFinal = 2,  // F(z^T) partial only                                 (objective)
   kEpiSeed = 3,   // v^{T-1} = [z^T != 0] (dF (P - c + lam sign z^T) + dZ)  (backward seed)
-  kEpiBwd = 4     // dalpha_t partial; v^{t-1} = [z^t != 0] (v^t - a P)  (one layer back)
+  kEpiBwd = 4,    // dalpha_t partial; v^{t-1} = [z^t != 0] (v^t - a P)  (one layer back)
+  kEpiFista = 5   // z^{t+1} = ST(y^t - a (P - c), lam a), y^{t+1} = z^{t+1} + b (z^{t+1} - z^t)  (FISTA)
 };
 
 struct Dict {
@@ -62,6 +63,8 @@ struct GemmArgs {
   float dF_scalar;
   const float* dZ;    // [rows][m] upstream gradient of z^T, or null
   int m;
+  const float* beta;  // [T] momentum weights (kEpiFista)
+  float* Out2;        // [rows][ldz] second output: y^{t+1} (kEpiFista)
 };
 
 // Launchers (kernels_gemm.hip)
@@ -87,6 +90,8 @@ hipError_t launch_reduce_loss(const double* Fd, int N, float* loss, hipStream_t 
 // Training loop helpers: FP64 mean of Fd; candidate steps max(alpha - eta g, 0).
 hipError_t launch_mean_d(const double* Fd, int N, double* out, hipStream_t s);
 hipError_t launch_alpha_step(const float* alpha, const float* g, double eta, int T, float* cand, hipStream_t s);
+// FISTA momentum weights beta[0..T) (FP64 recurrence, one thread).
+hipError_t launch_fista_beta(int T, float* beta, hipStream_t s);
 hipError_t launch_bwd0(const float* V0, const float* Z1, int N, int ldz, double* dpart, int nblocks,
                        hipStream_t s);
 hipError_t launch_reduce_dalpha(const double* dpart, int T, int P, int count0, int count, const float* alpha,

@@ -198,6 +198,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
   const float a = (EPI == kEpiCorr) ? 0.f : g.alpha ? g.alpha[g.t] : 0.f;
   const float lam = g.lam;
   const float th = lam * a;
+  const float bt = (EPI == kEpiFista) ? g.beta[g.t] : 0.f;
   double fs[4][4];
   double dsum = 0.0;
 #pragma unroll
@@ -234,6 +235,12 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
           if (g.dZ && col < g.m) gv += g.dZ[(size_t)row * g.m + col];
           g.Out[idx] = (z != 0.f) ? gv : 0.f;
           if (g.fpart) fs[fm][r4] += (double)(0.5f * z * p - z * c + lam * fabsf(z));
+        } else if constexpr (EPI == kEpiFista) {
+          // A = y^t (Zt: its FP32 copy), Zt1 = z^t
+          const float y = g.Zt[idx], zo = g.Zt1[idx], c = g.C[idx];
+          const float zn = soft_thresh(y - a * (p - c), th);
+          g.Out[idx] = zn;
+          g.Out2[idx] = zn + bt * (zn - zo);
         } else {  // kEpiBwd
           const float v = g.Vin[idx], zt = g.Zt[idx], zt1 = g.Zt1[idx];
           dsum += (double)v * ((double)zt - (double)zt1);
@@ -303,6 +310,7 @@ hipError_t launch_gemm(int prec, int epi, bool safe, const GemmArgs& a, hipStrea
       case kEpiFinal: return launch_one<kF32, kEpiFinal, false>(a, s);
       case kEpiSeed: return launch_one<kF32, kEpiSeed, false>(a, s);
       case kEpiBwd: return launch_one<kF32, kEpiBwd, false>(a, s);
+      case kEpiFista: return launch_one<kF32, kEpiFista, false>(a, s);
       default: return hipErrorInvalidValue;
     }
   }
@@ -311,6 +319,7 @@ hipError_t launch_gemm(int prec, int epi, bool safe, const GemmArgs& a, hipStrea
     case kEpiFinal: return launch_one<kBF16, kEpiFinal, false>(a, s);
     case kEpiSeed: return launch_one<kBF16, kEpiSeed, false>(a, s);
     case kEpiBwd: return launch_one<kBF16, kEpiBwd, false>(a, s);
+    case kEpiFista: return launch_one<kBF16, kEpiFista, false>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

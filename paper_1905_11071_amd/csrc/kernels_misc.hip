@@ -217,6 +217,18 @@ __global__ void k_alpha_step(const float* __restrict__ alpha, const float* __res
   cand[t] = (float)(a > 0.0 ? a : 0.0);
 }
 
+// FISTA momentum (Beck & Teboulle): tau_0 = 1, tau_{t+1} = (1 + sqrt(1 + 4
+// tau_t^2)) / 2, beta_t = (tau_t - 1) / tau_{t+1}; a sequential recurrence.
+__global__ void k_fista_beta(int T, float* __restrict__ beta) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double tau = 1.0;
+  for (int t = 0; t < T; ++t) {
+    const double tn = (1.0 + sqrt(1.0 + 4.0 * tau * tau)) / 2.0;
+    beta[t] = (float)((tau - 1.0) / tn);
+    tau = tn;
+  }
+}
+
 // Layer 0 of the adjoint: z^(0) = 0, so the partial is sum v^0 (0 - z^(1)).
 __global__ void k_bwd0(const float* __restrict__ V0, const float* __restrict__ Z1, size_t total,
                        double* __restrict__ dpart) {
@@ -357,6 +369,12 @@ hipError_t launch_mean_d(const double* Fd, int N, double* out, hipStream_t s) {
 hipError_t launch_alpha_step(const float* alpha, const float* g, double eta, int T, float* cand, hipStream_t s) {
   if (T == 0) return hipSuccess;
   hipLaunchKernelGGL(k_alpha_step, dim3((T + 255) / 256), dim3(256), 0, s, alpha, g, eta, T, cand);
+  return hipGetLastError();
+}
+
+hipError_t launch_fista_beta(int T, float* beta, hipStream_t s) {
+  if (T == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fista_beta, dim3(1), dim3(64), 0, s, T, beta);
   return hipGetLastError();
 }
 

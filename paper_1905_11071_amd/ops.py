@@ -194,6 +194,22 @@ def autotune(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, pr
     return best.value, list(ms)
 
 
+def fista(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, prec="fp32"):
+    """T layers of FISTA (forward only). Returns (Z, F of z^T, mean loss)."""
+    X, alpha = _check_inputs(d, X, alpha)
+    N, T = int(X.shape[0]), int(alpha.shape[0])
+    p = _prec(prec)
+    nbytes = ctypes.c_size_t()
+    check(lib().slista_fista_workspace_size(d.handle, N, T, p, ctypes.byref(nbytes)))
+    ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=d.device)
+    Z = torch.empty(N, d.m, device=d.device, dtype=torch.float32)
+    F = torch.empty(N, device=d.device, dtype=torch.float32)
+    loss = torch.empty(1, device=d.device, dtype=torch.float32)
+    check(lib().slista_fista(d.handle, X.data_ptr(), N, float(lam), alpha.data_ptr(), T, p, Z.data_ptr(),
+                             F.data_ptr(), loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream(d.device)))
+    return Z, F, loss
+
+
 def train(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, iters: int, lr: float,
           prec="fp32", max_halvings: int = 30):
     """Learn the step sizes in place (alpha, a device float32 [T] tensor) by

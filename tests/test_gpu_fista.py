@@ -1,0 +1,89 @@
+"""FISTA (slista_fista, per-layer kernels) against the FP64 oracle's FISTA.
+The momentum makes the iteration non-contractive, so the codes are compared
+through the objective: the relative error of the mean gap (with the
+rounding-floor reading of tests.gpu_common.gap_tolerance) and per-sample
+objective values."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_common import gap_tolerance, round_to_bf16
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sl():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_1905_11071_amd as sl
+    return sl
+
+
+def _gpu(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device=DEV)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("shape", [(50, 200, 1037, 15), (64, 256, 2000, 30), (96, 1024, 300, 12)])
+def test_fista_vs_oracle(sl, prec, shape):
+    n, m, N, T = shape
+    pb = synth.make_problem(n, m, N, 0.05, 0.01, 0.1, seed=600 + m)
+    alpha = np.full(T, np.float32(1.0 / oracle.lipschitz(pb.D)), dtype=np.float64)
+    d = sl.Dictionary(_gpu(pb.D))
+    Z, F, loss = sl.fista(d, _gpu(pb.X), pb.lam, _gpu(alpha), prec=prec)
+    torch.cuda.synchronize()
+    Zg = Z.cpu().numpy().astype(np.float64)
+    Zo, Fo = oracle.fista(pb.D, pb.X, pb.lam, alpha)
+    zs = oracle.lasso_solution(pb.D, pb.X, pb.lam)
+    Fs = oracle.objective(pb.D, pb.X, zs, pb.lam)
+    g_gpu = float(np.mean(oracle.objective(pb.D, pb.X, Zg, pb.lam) - Fs))
+    g_orc = float(np.mean(Fo[-1] - Fs))
+    rnd = (lambda z: z.astype(np.float32).astype(np.float64)) if prec == "fp32" else round_to_bf16
+    g_rnd = float(np.mean(oracle.objective(pb.D, pb.X, rnd(Zo), pb.lam) - Fs))
+    rel = abs(g_gpu - g_orc) / g_orc
+    tol = gap_tolerance(prec, T, g_orc, g_rnd)
+    _say(f"[{prec}] {shape}: FISTA mean-gap rel err {rel:.2e} (tolerance {tol:.2e}), gap/F* {g_orc / np.mean(Fs):.2e}")
+    assert rel <= tol
+    np.testing.assert_allclose(F.cpu().numpy(), Fo[-1], rtol=1e-4 if prec == "fp32" else 2e-2)
+    assert abs(loss.item() - Fo[-1].mean()) <= (1e-5 if prec == "fp32" else 2e-2) * Fo[-1].mean()
+    d.close()
+
+
+def test_fista_beats_ista_at_equal_depth(sl):
+    """The accelerated baseline: at the same number of layers and step 1/L,
+    FISTA's mean objective is below ISTA's (Figures 2 and D.2)."""
+    c = synth.CONFIGS["fwd_64x256"]
+    pb = synth.make_problem(c["n"], c["m"], 4000, c["p"], c["sigma"], c["lam_frac"], c["seed"])
+    T = 40
+    a = _gpu(np.full(T, np.float32(1.0 / oracle.lipschitz(pb.D))))
+    d = sl.Dictionary(_gpu(pb.D))
+    X = _gpu(pb.X)
+    _, _, lf = sl.fista(d, X, pb.lam, a)
+    _, _, li, _ = sl.forward(d, X, pb.lam, a)
+    _say(f"T={T}: FISTA loss {lf.item():.6g}, ISTA loss {li.item():.6g}")
+    assert lf.item() < li.item()
+    d.close()
+
+
+def test_fista_edge_cases(sl):
+    pb = synth.make_problem(16, 64, 33, 0.1, 0.0, 0.1, seed=77)
+    d = sl.Dictionary(_gpu(pb.D))
+    Z, F, loss = sl.fista(d, _gpu(pb.X), pb.lam, _gpu(np.zeros(0)))   # T = 0: Z = 0, F = |x|^2 / 2
+    assert float(Z.abs().max()) == 0.0
+    np.testing.assert_allclose(F.cpu().numpy(), 0.5 * np.sum(pb.X ** 2, axis=1), rtol=1e-6)
+    a = np.full(2, np.float32(1.0 / oracle.lipschitz(pb.D)), dtype=np.float64)
+    Zf, _, _ = sl.fista(d, _gpu(pb.X), pb.lam, _gpu(a))              # two layers: FISTA = ISTA
+    Zi, _, _, _ = sl.forward(d, _gpu(pb.X), pb.lam, _gpu(a))
+    assert np.array_equal(Zf.cpu().numpy(), Zi.cpu().numpy())
+    d.close()

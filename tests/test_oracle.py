@@ -218,3 +218,36 @@ def test_learned_steps_exceed_one_over_L_within_support_range():
         assert alpha[t] > 1.0 / L
         inv_ls = [1.0 / oracle.support_lipschitz(pb.D, z) for z in its[t + 1] if np.any(z)]
         assert alpha[t] <= max(inv_ls)
+
+
+# --- FISTA (the accelerated baseline of Figs. 2 and D.2) ------------------------
+
+def test_fista_momentum_closed_values():
+    beta = oracle.fista_momentum(4)
+    tau1 = (1 + 5 ** 0.5) / 2
+    tau2 = (1 + (1 + 4 * tau1 ** 2) ** 0.5) / 2
+    assert beta[0] == 0.0
+    assert abs(beta[1] - (tau1 - 1) / tau2) < 1e-15
+    assert np.all(np.diff(beta) > 0) and np.all(beta < 1)
+
+
+def test_fista_first_two_layers_are_ista():
+    pb = synth.make_problem(16, 40, 50, 0.1, 0.01, 0.1, seed=41)
+    a = np.full(2, 1.0 / oracle.lipschitz(pb.D))
+    Zf, Ff = oracle.fista(pb.D, pb.X, pb.lam, a)
+    Zi, Fi = oracle.forward(pb.D, pb.X, pb.lam, a)[:2]
+    assert np.array_equal(Zf, Zi)
+    assert np.allclose(Ff, Fi, rtol=0, atol=0)
+
+
+def test_fista_meets_its_rate_bound():
+    """Beck & Teboulle (2009), Thm 4.4, from z^(0) = 0 with step 1/L."""
+    pb = synth.make_problem(20, 50, 40, 0.1, 0.0, 0.1, seed=43)
+    L = oracle.lipschitz(pb.D)
+    T = 60
+    _, F = oracle.fista(pb.D, pb.X, pb.lam, np.full(T, 1.0 / L))
+    zs = oracle.lasso_solution(pb.D, pb.X, pb.lam)
+    Fs = oracle.objective(pb.D, pb.X, zs, pb.lam)
+    bound = 2.0 * L * np.sum(zs * zs, axis=1)
+    for t in range(1, T + 1):
+        assert np.all(F[t] - Fs <= bound / (t + 1) ** 2 + 1e-12)
