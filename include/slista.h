@@ -114,6 +114,13 @@ SLISTA_API int slista_dict_gram(const slista_dict* dict, float* G_out, void* str
 SLISTA_API int slista_dict_lipschitz(slista_dict* dict, int max_iter, double rtol, double* L_out,
                                      int* iters, void* stream);
 
+/* Layer checkpointing for a memory budget: the smallest ckpt_every (fewest
+ * recomputed layers) whose forward/backward workspace for (N, T, prec) fits
+ * in `budget` bytes; *bytes (may be NULL) gets that workspace size.
+ * SLISTA_ENOMEM if even the smallest workspace does not fit. Host only. */
+SLISTA_API int slista_ckpt_for_budget(const slista_dict* dict, int N, int T, int prec, size_t budget,
+                                      int* ckpt_every, size_t* bytes);
+
 /* ---------------------------------------------------------------------------
  * Forward and backward through T layers
  *

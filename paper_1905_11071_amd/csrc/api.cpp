@@ -684,6 +684,27 @@ int slista_workspace_size(const slista_dict* dict, int N, int T, int prec, int c
   return SLISTA_OK;
 }
 
+int slista_ckpt_for_budget(const slista_dict* dict, int N, int T, int prec, size_t budget, int* ckpt_every,
+                           size_t* bytes) {
+  if (!dict || !ckpt_every) return fail(SLISTA_EINVAL, "dict or ckpt_every is NULL");
+  if (N < 0 || N > kMaxN || T < 1 || T > kMaxT) return fail(SLISTA_EINVAL, "sizes out of range");
+  if (prec != SLISTA_FP32 && prec != SLISTA_BF16) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
+  // the workspace shrinks with k until the segment buffers outgrow the
+  // checkpoints (around sqrt(T)); the smallest fitting k recomputes least
+  size_t best_bytes = (size_t)-1;
+  for (int k = 1; k <= T; ++k) {
+    const size_t b = make_layout(dict->d, N, T, k).total;
+    if (b <= budget) {
+      *ckpt_every = k;
+      if (bytes) *bytes = b;
+      return SLISTA_OK;
+    }
+    if (b < best_bytes) best_bytes = b;
+  }
+  return fail(SLISTA_ENOMEM, "no checkpoint spacing fits %zu bytes (smallest workspace %zu bytes)", budget,
+              best_bytes);
+}
+
 int slista_forward(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha, int T,
                    int prec, float* Z, float* F, int f_trace, float* loss, int ckpt_every, void* ws,
                    size_t ws_bytes, void* stream) {

@@ -86,6 +86,16 @@ class Dictionary:
         nbytes = self.workspace_bytes(N, T, prec, ckpt_every)
         return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
 
+    def ckpt_for_budget(self, N: int, T: int, prec="fp32", budget: Optional[int] = None) -> int:
+        """The smallest checkpoint spacing whose workspace fits `budget` bytes
+        (default: 90 % of the device's free memory)."""
+        if budget is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            budget = int(0.9 * free)
+        k = ctypes.c_int()
+        check(lib().slista_ckpt_for_budget(self._h, N, T, _prec(prec), int(budget), ctypes.byref(k), None))
+        return k.value
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().slista_dict_destroy(self._h)
@@ -358,6 +368,8 @@ class SlistaFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, alpha, d: Dictionary, X, lam, prec="fp32", ckpt_every=1):
+        if ckpt_every == "auto":  # keep every layer if it fits, else checkpoint
+            ckpt_every = d.ckpt_for_budget(int(X.shape[0]), int(alpha.shape[0]), prec)
         Z, F, _, ws = forward(d, X, lam, alpha, prec=prec, want_loss=False, ckpt_every=ckpt_every)
         ctx.save_for_backward(alpha, X)
         ctx.d, ctx.lam, ctx.prec, ctx.ckpt, ctx.ws = d, lam, prec, ckpt_every, ws
@@ -371,6 +383,8 @@ class SlistaFunction(torch.autograd.Function):
         return dalpha, None, None, None, None, None
 
 
-def slista(alpha: torch.Tensor, d: Dictionary, X: torch.Tensor, lam: float, prec="fp32", ckpt_every: int = 1):
-    """Differentiable Step-LISTA network: returns (Z, F) with gradients to alpha."""
+def slista(alpha: torch.Tensor, d: Dictionary, X: torch.Tensor, lam: float, prec="fp32", ckpt_every=1):
+    """Differentiable Step-LISTA network: returns (Z, F) with gradients to alpha.
+    ckpt_every: checkpoint spacing of the tape (1 = keep every layer), or
+    "auto" for the smallest spacing whose workspace fits the free memory."""
     return SlistaFunction.apply(alpha, d, X, lam, prec, ckpt_every)

@@ -399,3 +399,28 @@ def test_autotune_keeps_results(sl, tmp_path):
     assert any(r[0] == 1 and r[1] == 1 and r[2] == 11 for r in recs), recs  # bf16, one pass, log2(3000)
     sl.tune_load(path)
     d.close()
+
+
+def test_checkpoint_spacing_for_a_memory_budget(sl):
+    """slista_ckpt_for_budget picks the smallest spacing whose workspace fits;
+    the autograd node's "auto" mode uses it and gives the same gradient as
+    keeping every layer (checkpointing is bitwise neutral on the codes)."""
+    pb = synth.make_problem(32, 128, 700, 0.08, 0.01, 0.1, seed=14)
+    T = 24
+    alpha = synth.perturbed_steps(oracle.lipschitz(pb.D), T, seed=3)
+    d = sl.Dictionary(_gpu(pb.D))
+    full = d.workspace_bytes(pb.N, T, "fp32", 1)
+    assert d.ckpt_for_budget(pb.N, T, "fp32", budget=full) == 1
+    sizes = {k: d.workspace_bytes(pb.N, T, "fp32", k) for k in range(1, T + 1)}
+    budget = (full + min(sizes.values())) // 2
+    k = d.ckpt_for_budget(pb.N, T, "fp32", budget=budget)
+    assert sizes[k] <= budget and all(sizes[j] > budget for j in range(1, k))
+    with pytest.raises(sl.SlistaError):
+        d.ckpt_for_budget(pb.N, T, "fp32", budget=min(sizes.values()) - 1)
+    X = _gpu(pb.X)
+    a = _gpu(alpha).requires_grad_(True)
+    Z, F = sl.slista(a, d, X, pb.lam, "fp32", "auto")
+    F.mean().backward()
+    _, _, _, da, _ = sl.forward_backward(d, X, pb.lam, a.detach(), prec="fp32", ckpt_every=1)
+    np.testing.assert_allclose(a.grad.cpu().numpy(), da.cpu().numpy(), rtol=1e-6, atol=1e-9)
+    d.close()
