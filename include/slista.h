@@ -290,6 +290,24 @@ SLISTA_API int slista_fista(const slista_dict* dict, const float* X, int N, floa
                             void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Oracle-ISTA (Section 3, Algorithm 1): per sample and layer, S = supp(z^t),
+ * L_S = greatest eigenvalue of G restricted to S (FP64 power iteration,
+ * warm-started from the previous layer, stopped when successive Rayleigh
+ * quotients agree to power_rtol or after max_power_iter steps; L_S = L for
+ * an empty support); the step 1/L_S is taken when the support condition (*)
+ * holds and 1/L otherwise. For z_j = 0 the condition fails exactly when
+ * |(G z^t - c)_j| > lam, whatever the step, so one contraction per layer
+ * decides it. L: the dictionary's Lipschitz constant (slista_dict_lipschitz).
+ * Z [N, m] out; F [N] (F(z^T)) and loss out if not NULL; steps: device
+ * [T, N] (the step each sample took at each layer) or NULL. Per-layer
+ * kernels; m <= 2048. Workspace of slista_oista_workspace_size bytes.
+ * ------------------------------------------------------------------------- */
+SLISTA_API int slista_oista_workspace_size(const slista_dict* dict, int N, int T, int prec, size_t* bytes);
+SLISTA_API int slista_oista(const slista_dict* dict, const float* X, int N, float lambda, double L, int T, int prec,
+                            int max_power_iter, double power_rtol, float* Z, float* F, float* loss, float* steps,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Learning the step sizes (Appendix D, "Training the networks"): full-batch
  * sub-gradient descent on the mean loss of Eq. (15) with a backtracking
  * learning rate. From steps alpha with loss J and gradient g, each iteration

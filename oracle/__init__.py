@@ -18,4 +18,5 @@ from .slista import (  # noqa: F401
     support_lipschitz,
     fista_momentum,
     fista,
+    oista,
 )

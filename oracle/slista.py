@@ -36,6 +36,7 @@ __all__ = [
     "support_lipschitz",
     "fista_momentum",
     "fista",
+    "oista",
 ]
 
 
@@ -374,3 +375,35 @@ def fista(D, X, lam, alpha, return_iterates: bool = False):
         if return_iterates:
             its.append(z.copy())
     return (z, F, its) if return_iterates else (z, F)
+
+
+def oista(D, X, lam, T: int, return_steps: bool = False):
+    """Oracle-ISTA (Section 3, Algorithm 1), per sample, from z^(0) = 0:
+        S = supp(z^(t)), L_S = greatest eigenvalue of D_S^T D_S (L_empty = L),
+        y = psi_{1/L_S}(z^(t), x) = ST(z - (1/L_S) D^T (D z - x), lam / L_S);
+        z^(t+1) = y if supp(y) is inside S (condition (*)),
+                  else psi_{1/L}(z^(t), x).
+    Returns (Z [N, m], F [T+1, N]) and, if asked, the step used by every
+    sample at every layer [T, N]. Pinned by: its first layer equals ISTA's
+    (S is empty at z^(0) = 0); F decreases at every layer (majorization by
+    the tighter surrogate, Eq. (7)); on a long run it reaches z*."""
+    D, X = _f64(D), _f64(X)
+    N, m = X.shape[0], D.shape[1]
+    L = lipschitz(D)
+    Z = np.zeros((N, m))
+    F = np.empty((T + 1, N))
+    F[0] = objective(D, X, Z, lam)
+    steps = np.empty((T, N))
+    for t in range(T):
+        for i in range(N):
+            z, x = Z[i], X[i]
+            S = z != 0.0
+            LS = support_lipschitz(D, z) if S.any() else L
+            grad = D.T @ (D @ z - x)
+            y = soft_threshold(z - grad / LS, lam / LS)
+            if np.all(S | (y == 0.0)):
+                Z[i], steps[t, i] = y, 1.0 / LS
+            else:
+                Z[i], steps[t, i] = soft_threshold(z - grad / L, lam / L), 1.0 / L
+        F[t + 1] = objective(D, X, Z, lam)
+    return (Z, F, steps) if return_steps else (Z, F)

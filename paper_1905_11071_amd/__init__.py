@@ -13,6 +13,7 @@ from .ops import (  # noqa: F401
     tune_save,
     train,
     fista,
+    oista,
     backward,
     forward,
     forward_backward,

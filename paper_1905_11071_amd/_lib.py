@@ -45,6 +45,9 @@ SIGNATURES = {
     "slista_batch_autotune": (_c_int, [_vp, _vp, ctypes.POINTER(_c_int)]),
     "slista_ckpt_for_budget": (_c_int, [_vp, _c_int, _c_int, _c_int, _size_t, ctypes.POINTER(_c_int),
                                         ctypes.POINTER(_size_t)]),
+    "slista_oista_workspace_size": (_c_int, [_vp, _c_int, _c_int, _c_int, ctypes.POINTER(_size_t)]),
+    "slista_oista": (_c_int, [_vp, _vp, _c_int, _c_float, _c_double, _c_int, _c_int, _c_int, _c_double, _vp, _vp,
+                              _vp, _vp, _vp, _size_t, _vp]),
     "slista_fista_workspace_size": (_c_int, [_vp, _c_int, _c_int, _c_int, ctypes.POINTER(_size_t)]),
     "slista_fista": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _vp, _vp, _vp, _vp, _size_t, _vp]),
     "slista_train_workspace_size": (_c_int, [_vp, _c_int, _c_int, _c_int, ctypes.POINTER(_size_t)]),

@@ -852,6 +852,90 @@ int slista_fista(const slista_dict* dict, const float* X, int N, float lambda, c
   return SLISTA_OK;
 }
 
+// ------------------------------------------------------------- Oracle-ISTA
+// Workspace of slista_oista: the forward workspace without a tape (C, norms,
+// objective partials reused as violation counts, two z buffers), the
+// gradient R [N, m_pad], the warm-start vectors V [N, m_pad], the steps [N].
+static size_t oista_offsets(const slista::Dict& d, int N, int T, size_t off[3]) {
+  const Layout L = make_layout(d, N, T, 0);
+  size_t o = align256(L.total);
+  off[0] = o;  // R
+  o += align256(L.zbytes);
+  off[1] = o;  // V
+  o += align256(L.zbytes);
+  off[2] = o;  // step
+  o += align256((size_t)(N > 0 ? N : 1) * sizeof(float));
+  return o;
+}
+
+int slista_oista_workspace_size(const slista_dict* dict, int N, int T, int prec, size_t* bytes) {
+  if (!dict || !bytes) return fail(SLISTA_EINVAL, "dict or bytes is NULL");
+  if (N < 0 || N > kMaxN || T < 0 || T > kMaxT) return fail(SLISTA_EINVAL, "sizes out of range");
+  if (prec != SLISTA_FP32 && prec != SLISTA_BF16) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
+  size_t off[3];
+  *bytes = oista_offsets(dict->d, N, T, off);
+  return SLISTA_OK;
+}
+
+int slista_oista(const slista_dict* dict, const float* X, int N, float lambda, double L, int T, int prec,
+                 int max_power_iter, double power_rtol, float* Z, float* F, float* loss, float* steps, void* ws,
+                 size_t ws_bytes, void* stream) {
+  if (!dict) return fail(SLISTA_EINVAL, "dict is NULL");
+  if (!(L > 0.0) || !std::isfinite(L)) return fail(SLISTA_EINVAL, "L must be finite and > 0");
+  if (max_power_iter < 1 || max_power_iter > 1000000) return fail(SLISTA_EINVAL, "max_power_iter outside [1, 1e6]");
+  if (!(power_rtol >= 0.0) || !std::isfinite(power_rtol)) return fail(SLISTA_EINVAL, "power_rtol must be >= 0");
+  if (dict->d.m_pad > 2048) return fail(SLISTA_ENOTSUP, "Oracle-ISTA supports m <= 2048 (m_pad=%d)", dict->d.m_pad);
+  if (T < 0 || T > kMaxT) return fail(SLISTA_EINVAL, "T=%d outside [0, %d]", T, kMaxT);
+  size_t need_fwd = 0;  // checks N, lambda, prec, X and the workspace alignment (no step sizes here)
+  int st = check_common(dict, X, N, lambda, nullptr, 0, prec, 0, ws, ws_bytes, &need_fwd);
+  if (st != SLISTA_OK) return st;
+  size_t off[3];
+  const size_t need = oista_offsets(dict->d, N, T, off);
+  if (ws_bytes < need) return fail(SLISTA_EINVAL, "workspace must hold %zu bytes", need);
+  if (N > 0 && !Z) return fail(SLISTA_EINVAL, "Z is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if (N == 0) {
+    if (loss) LAUNCH(kKOther, s, slista::launch_fill(loss, 1, 0.f, s));
+    return SLISTA_OK;
+  }
+  const Run r{&dict->d, make_layout(dict->d, N, T, 0), (char*)ws, N, T, s};
+  if (T == 0) return run_forward(r, X, lambda, nullptr, prec, Z, F, 0, loss, true);
+  const int mp = dict->d.m_pad;
+  float* R = (float*)((char*)ws + off[0]);
+  float* V = (float*)((char*)ws + off[1]);
+  float* step = (float*)((char*)ws + off[2]);
+  if ((st = prep(r, X)) != SLISTA_OK) return st;
+  LAUNCH(kKOther, s, slista::launch_fill(V, (size_t)N * mp, 0.f, s));
+  // z^0 = 0: its support is empty, so layer 0 is the ISTA step from 0
+  LAUNCH(kKOther, s, slista::launch_fill(r.slot(0), (size_t)N * mp, 0.f, s));
+  for (int t = 0; t < T; ++t) {
+    const float* zt = r.slot(t);
+    LAUNCH(kKOther, s, slista::launch_support_lipschitz(dict->d.G32, dict->d.m, mp, zt, V, L, max_power_iter,
+                                                        power_rtol, N, step, s));
+    slista::GemmArgs g = base_args(r, nullptr, lambda);
+    g.A = zt;
+    g.Bt = gram_for(*r.d, prec);
+    g.Zt = zt;
+    g.Out = R;
+    g.fpart = r.fpart();
+    LAUNCH(kKFwd, s, slista::launch_gemm(prec, slista::kEpiGrad, false, g, s));
+    LAUNCH(kKOther, s, slista::launch_oista_update(zt, R, r.fpart(), r.L.col_tiles, step, L, lambda, N, mp,
+                                                   r.slot(t + 1), steps ? steps + (size_t)t * N : nullptr, s));
+  }
+  LAUNCH(kKOther, s, slista::launch_copy_out(r.slot(T), N, mp, dict->d.m, Z, s));
+  if (F || loss) {
+    slista::GemmArgs g = base_args(r, nullptr, lambda);
+    g.A = r.slot(T);
+    g.Bt = gram_for(*r.d, prec);
+    g.Zt = r.slot(T);
+    g.fpart = r.fpart();
+    LAUNCH(kKFinal, s, slista::launch_gemm(prec, slista::kEpiFinal, false, g, s));
+    LAUNCH(kKOther, s, slista::launch_reduce_f(r.xsq(), r.fpart(), r.L.col_tiles, N, F, r.Fd(), s));
+    if (loss) LAUNCH(kKOther, s, slista::launch_reduce_loss(r.Fd(), N, loss, s));
+  }
+  return SLISTA_OK;
+}
+
 // ------------------------------------------------------------- training
 // Workspace of slista_train: the forward/backward workspace with the full
 // tape, then the gradient [T], the candidate steps [T], the FP64 loss and

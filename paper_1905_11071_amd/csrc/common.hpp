@@ -24,7 +24,8 @@ enum Epi : int {
   kEpiFinal = 2,  // F(z^T) partial only                                 (objective)
   kEpiSeed = 3,   // v^{T-1} = [z^T != 0] (dF (P - c + lam sign z^T) + dZ)  (backward seed)
   kEpiBwd = 4,    // dalpha_t partial; v^{t-1} = [z^t != 0] (v^t - a P)  (one layer back)
-  kEpiFista = 5   // z^{t+1} = ST(y^t - a (P - c), lam a), y^{t+1} = z^{t+1} + b (z^{t+1} - z^t)  (FISTA)
+  kEpiFista = 5,  // z^{t+1} = ST(y^t - a (P - c), lam a), y^{t+1} = z^{t+1} + b (z^{t+1} - z^t)  (FISTA)
+  kEpiGrad = 6    // R = P - c; per-row count of z_j = 0 with |R_j| > lam  (Oracle-ISTA)
 };
 
 struct Dict {
@@ -92,6 +93,14 @@ hipError_t launch_mean_d(const double* Fd, int N, double* out, hipStream_t s);
 hipError_t launch_alpha_step(const float* alpha, const float* g, double eta, int T, float* cand, hipStream_t s);
 // FISTA momentum weights beta[0..T) (FP64 recurrence, one thread).
 hipError_t launch_fista_beta(int T, float* beta, hipStream_t s);
+// Oracle-ISTA: per sample, L_S of the support of z (FP64 power iteration on
+// G restricted to S, warm-started from V) -> step[i] = 1/L_S (1/L if S is
+// empty); then z' = ST(z - a_i R, lam a_i) with a_i = step[i], or 1/L where
+// the row's violation count (sum over col tiles of flags) is nonzero.
+hipError_t launch_support_lipschitz(const float* G32, int m, int mp, const float* Z, float* V, double L,
+                                    int max_iter, double tol, int N, float* step, hipStream_t s);
+hipError_t launch_oista_update(const float* Z, const float* R, const double* flags, int col_tiles, const float* step,
+                               double L, float lam, int N, int mp, float* Zout, float* steps_used, hipStream_t s);
 hipError_t launch_bwd0(const float* V0, const float* Z1, int N, int ldz, double* dpart, int nblocks,
                        hipStream_t s);
 hipError_t launch_reduce_dalpha(const double* dpart, int T, int P, int count0, int count, const float* alpha,

@@ -235,6 +235,10 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
           if (g.dZ && col < g.m) gv += g.dZ[(size_t)row * g.m + col];
           g.Out[idx] = (z != 0.f) ? gv : 0.f;
           if (g.fpart) fs[fm][r4] += (double)(0.5f * z * p - z * c + lam * fabsf(z));
+        } else if constexpr (EPI == kEpiGrad) {
+          const float z = g.Zt[idx], r = p - g.C[idx];
+          g.Out[idx] = r;
+          if (z == 0.f && fabsf(r) > lam) fs[fm][r4] += 1.0;
         } else if constexpr (EPI == kEpiFista) {
           // A = y^t (Zt: its FP32 copy), Zt1 = z^t
           const float y = g.Zt[idx], zo = g.Zt1[idx], c = g.C[idx];
@@ -251,7 +255,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
     }
   }
 
-  if constexpr (EPI == kEpiFwd || EPI == kEpiFinal || EPI == kEpiSeed) {
+  if constexpr (EPI == kEpiFwd || EPI == kEpiFinal || EPI == kEpiSeed || EPI == kEpiGrad) {
     if (g.fpart) {  // uniform across the workgroup
       double* red = (double*)smem;  // [2][BM]
 #pragma unroll
@@ -311,6 +315,7 @@ hipError_t launch_gemm(int prec, int epi, bool safe, const GemmArgs& a, hipStrea
       case kEpiSeed: return launch_one<kF32, kEpiSeed, false>(a, s);
       case kEpiBwd: return launch_one<kF32, kEpiBwd, false>(a, s);
       case kEpiFista: return launch_one<kF32, kEpiFista, false>(a, s);
+      case kEpiGrad: return launch_one<kF32, kEpiGrad, false>(a, s);
       default: return hipErrorInvalidValue;
     }
   }
@@ -320,6 +325,7 @@ hipError_t launch_gemm(int prec, int epi, bool safe, const GemmArgs& a, hipStrea
     case kEpiSeed: return launch_one<kBF16, kEpiSeed, false>(a, s);
     case kEpiBwd: return launch_one<kBF16, kEpiBwd, false>(a, s);
     case kEpiFista: return launch_one<kBF16, kEpiFista, false>(a, s);
+    case kEpiGrad: return launch_one<kBF16, kEpiGrad, false>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

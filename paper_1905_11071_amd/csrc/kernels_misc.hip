@@ -229,6 +229,114 @@ __global__ void k_fista_beta(int T, float* __restrict__ beta) {
   }
 }
 
+// L_S of one sample's support per workgroup (Oracle-ISTA, Section 3): the
+// support S of row i of Z is compacted in index order (deterministic), then
+// power iteration on G_SS in FP64 from the previous layer's vector V[i]
+// restricted to S (or the hash start vector when that is ~0), until
+// successive Rayleigh quotients agree to tol or max_iter. step[i] = 1/L_S,
+// 1/L for an empty support; V[i] gets the final vector (0 off S).
+constexpr int kLsThreads = 256;
+__global__ __launch_bounds__(kLsThreads) void k_support_lipschitz(const float* __restrict__ G, int m, int mp,
+                                                                 const float* __restrict__ Z, float* __restrict__ V,
+                                                                 double L, int max_iter, double tol,
+                                                                 float* __restrict__ step) {
+  extern __shared__ __attribute__((aligned(16))) char sm[];
+  double* v = (double*)sm;          // [mp]
+  double* w = v + mp;               // [mp]
+  int* idx = (int*)(w + mp);        // [mp]
+  int* cnt = idx + mp;              // [kLsThreads + 1]
+  __shared__ double sh[kLsThreads];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const float* z = Z + (size_t)i * mp;
+  float* vrow = V + (size_t)i * mp;
+  const int chunk = (m + kLsThreads - 1) / kLsThreads;
+  const int j0 = tid * chunk, j1 = min(j0 + chunk, m);
+  int c = 0;
+  for (int j = j0; j < j1; ++j) c += z[j] != 0.f;
+  cnt[tid] = c;
+  __syncthreads();
+  if (tid == 0) {  // exclusive scan of the per-thread counts, in thread order
+    int acc = 0;
+    for (int k = 0; k < kLsThreads; ++k) {
+      const int ck = cnt[k];
+      cnt[k] = acc;
+      acc += ck;
+    }
+    cnt[kLsThreads] = acc;
+  }
+  __syncthreads();
+  int pos = cnt[tid];
+  for (int j = j0; j < j1; ++j)
+    if (z[j] != 0.f) idx[pos++] = j;
+  const int ns = cnt[kLsThreads];
+  __syncthreads();
+  if (ns == 0) {
+    if (tid == 0) step[i] = (float)(1.0 / L);
+    return;
+  }
+  double nrm = 0.0;
+  for (int k = tid; k < ns; k += kLsThreads) {
+    v[k] = (double)vrow[idx[k]];
+    nrm += v[k] * v[k];
+  }
+  nrm = block_sum(nrm, sh);
+  if (!(nrm > 1e-24)) {
+    nrm = 0.0;
+    for (int k = tid; k < ns; k += kLsThreads) {
+      v[k] = start_value(idx[k]);
+      nrm += v[k] * v[k];
+    }
+    nrm = block_sum(nrm, sh);
+  }
+  nrm = sqrt(nrm);
+  for (int k = tid; k < ns; k += kLsThreads) v[k] /= nrm;
+  __syncthreads();
+  double rq = 0.0, prev = 0.0;
+  for (int it = 0; it < max_iter; ++it) {
+    for (int k = tid; k < ns; k += kLsThreads) {
+      const float* grow = G + (size_t)idx[k] * mp;
+      double s = 0.0;
+      for (int l = 0; l < ns; ++l) s += (double)grow[idx[l]] * v[l];
+      w[k] = s;
+    }
+    __syncthreads();
+    double pr = 0.0, pw = 0.0;
+    for (int k = tid; k < ns; k += kLsThreads) {
+      pr += v[k] * w[k];
+      pw += w[k] * w[k];
+    }
+    rq = block_sum(pr, sh);
+    const double nw = sqrt(block_sum(pw, sh));
+    if (nw == 0.0) break;
+    for (int k = tid; k < ns; k += kLsThreads) v[k] = w[k] / nw;
+    __syncthreads();
+    if (it > 0 && fabs(rq - prev) <= tol * fabs(rq)) break;
+    prev = rq;
+  }
+  for (int j = tid; j < mp; j += kLsThreads) vrow[j] = 0.f;
+  __syncthreads();
+  for (int k = tid; k < ns; k += kLsThreads) vrow[idx[k]] = (float)v[k];
+  if (tid == 0) step[i] = (float)(rq > 0.0 ? 1.0 / rq : 1.0 / L);
+}
+
+// Oracle-ISTA update: row i takes a_i = step[i] if its support condition
+// holds (no violations counted by the gradient epilogue), else 1/L.
+__global__ void k_oista_update(const float* __restrict__ Z, const float* __restrict__ R,
+                               const double* __restrict__ flags, int col_tiles, const float* __restrict__ step,
+                               double L, float lam, int N, int mp, float* __restrict__ Zout,
+                               float* __restrict__ steps_used) {
+  const size_t total = (size_t)N * mp;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / mp);
+    double viol = 0.0;
+    for (int ct = 0; ct < col_tiles; ++ct) viol += flags[(size_t)ct * N + i];
+    const float a = viol == 0.0 ? step[i] : (float)(1.0 / L);
+    const float u = Z[e] - a * R[e], th = lam * a;
+    Zout[e] = fabsf(u) - th > 0.f ? copysignf(fabsf(u) - th, u) : 0.f;
+    if (steps_used && e == (size_t)i * mp) steps_used[i] = a;
+  }
+}
+
 // Layer 0 of the adjoint: z^(0) = 0, so the partial is sum v^0 (0 - z^(1)).
 __global__ void k_bwd0(const float* __restrict__ V0, const float* __restrict__ Z1, size_t total,
                        double* __restrict__ dpart) {
@@ -369,6 +477,27 @@ hipError_t launch_mean_d(const double* Fd, int N, double* out, hipStream_t s) {
 hipError_t launch_alpha_step(const float* alpha, const float* g, double eta, int T, float* cand, hipStream_t s) {
   if (T == 0) return hipSuccess;
   hipLaunchKernelGGL(k_alpha_step, dim3((T + 255) / 256), dim3(256), 0, s, alpha, g, eta, T, cand);
+  return hipGetLastError();
+}
+
+hipError_t launch_support_lipschitz(const float* G32, int m, int mp, const float* Z, float* V, double L,
+                                    int max_iter, double tol, int N, float* step, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  const size_t lds = (size_t)mp * (2 * sizeof(double) + sizeof(int)) + (kLsThreads + 1) * sizeof(int);
+  hipError_t e = hipFuncSetAttribute((const void*)k_support_lipschitz, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_support_lipschitz, dim3(N), dim3(kLsThreads), lds, s, G32, m, mp, Z, V, L, max_iter, tol,
+                     step);
+  return hipGetLastError();
+}
+
+hipError_t launch_oista_update(const float* Z, const float* R, const double* flags, int col_tiles, const float* step,
+                               double L, float lam, int N, int mp, float* Zout, float* steps_used, hipStream_t s) {
+  const size_t total = (size_t)N * mp;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_oista_update, dim3(grid_for(total, 256 * 4)), dim3(256), 0, s, Z, R, flags, col_tiles, step, L,
+                     lam, N, mp, Zout, steps_used);
   return hipGetLastError();
 }
 

@@ -220,6 +220,27 @@ def fista(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, prec=
     return Z, F, loss
 
 
+def oista(d: Dictionary, X: torch.Tensor, lam: float, L: float, T: int, prec="fp32", max_power_iter: int = 5000,
+          power_rtol: float = 1e-12):
+    """T layers of Oracle-ISTA. Returns (Z, F of z^T, mean loss, steps [T, N])."""
+    X = _dev_f32(X, "X")
+    if X.dim() != 2 or X.shape[1] != d.n:
+        raise ValueError(f"X must be [N, {d.n}]")
+    N = int(X.shape[0])
+    p = _prec(prec)
+    nbytes = ctypes.c_size_t()
+    check(lib().slista_oista_workspace_size(d.handle, N, T, p, ctypes.byref(nbytes)))
+    ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=d.device)
+    Z = torch.empty(N, d.m, device=d.device, dtype=torch.float32)
+    F = torch.empty(N, device=d.device, dtype=torch.float32)
+    loss = torch.empty(1, device=d.device, dtype=torch.float32)
+    steps = torch.empty(max(T, 1), N, device=d.device, dtype=torch.float32)
+    check(lib().slista_oista(d.handle, X.data_ptr(), N, float(lam), float(L), int(T), p, int(max_power_iter),
+                             float(power_rtol), Z.data_ptr(), F.data_ptr(), loss.data_ptr(), steps.data_ptr(),
+                             ws.data_ptr(), ws.numel(), _stream(d.device)))
+    return Z, F, loss, steps[:T]
+
+
 def train(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, iters: int, lr: float,
           prec="fp32", max_halvings: int = 30):
     """Learn the step sizes in place (alpha, a device float32 [T] tensor) by

@@ -251,3 +251,30 @@ def test_fista_meets_its_rate_bound():
     bound = 2.0 * L * np.sum(zs * zs, axis=1)
     for t in range(1, T + 1):
         assert np.all(F[t] - Fs <= bound / (t + 1) ** 2 + 1e-12)
+
+
+# --- Oracle-ISTA (Section 3, Algorithm 1) -------------------------------------
+
+def test_oista_first_layer_is_ista_and_descends():
+    pb = synth.make_binf_problem(10, 50, 30, 0.5, seed=1201)
+    L = oracle.lipschitz(pb.D)
+    Z1, _ = oracle.oista(pb.D, pb.X, pb.lam, 1)           # S is empty at z^(0) = 0: L_S = L
+    Zi, _ = oracle.forward(pb.D, pb.X, pb.lam, np.array([1.0 / L]))[:2]
+    np.testing.assert_allclose(Z1, Zi, rtol=1e-13, atol=1e-15)   # same step; only the BLAS order differs
+    _, F = oracle.oista(pb.D, pb.X, pb.lam, 80)
+    assert np.all(np.diff(F, axis=0) <= 1e-14 * np.abs(F[:-1]))   # every layer lowers F
+
+
+def test_oista_converges_faster_than_ista_and_reaches_kkt():
+    """Fig. 2 setting (10 x 50 dictionary, lambda = 0.5, samples on B_inf)."""
+    pb = synth.make_binf_problem(10, 50, 30, 0.5, seed=1201)
+    L = oracle.lipschitz(pb.D)
+    T = 100
+    Zo, Fo, steps = oracle.oista(pb.D, pb.X, pb.lam, T, return_steps=True)
+    _, Fi = oracle.forward(pb.D, pb.X, pb.lam, np.full(T, 1.0 / L))[:2]
+    zs = oracle.lasso_solution(pb.D, pb.X, pb.lam)
+    Fs = oracle.objective(pb.D, pb.X, zs, pb.lam)
+    assert np.mean(Fo[T] - Fs) < 1e-2 * np.mean(Fi[T] - Fs)
+    assert np.all(steps >= 1.0 / L * (1 - 1e-12)) and np.any(steps > 1.5 / L)
+    _, Flong = oracle.oista(pb.D, pb.X, pb.lam, 400)
+    assert np.max(Flong[-1] - Fs) < 1e-9
