@@ -19,4 +19,7 @@ from .slista import (  # noqa: F401
     fista_momentum,
     fista,
     oista,
+    lista_layer,
+    lista_forward,
+    lista_forward_backward,
 )

@@ -37,6 +37,9 @@ __all__ = [
     "fista_momentum",
     "fista",
     "oista",
+    "lista_layer",
+    "lista_forward",
+    "lista_forward_backward",
 ]
 
 
@@ -407,3 +410,88 @@ def oista(D, X, lam, T: int, return_steps: bool = False):
                 Z[i], steps[t, i] = soft_threshold(z - grad / L, lam / L), 1.0 / L
         F[t + 1] = objective(D, X, Z, lam)
     return (Z, F, steps) if return_steps else (Z, F)
+
+
+def lista_layer(D, X, lam, Z, W, a, b) -> np.ndarray:
+    """One coupled LISTA layer, Section 4, Eq. (11):
+        phi_theta(z, x) = ST(z - a W^T (D z - x), b lam),  theta = (W, a, b),
+    W in R^{n x m} (the coupling W_z = I - W_x^T D that precedes Eq. (11))."""
+    D, X, Z, W = _f64(D), _f64(X), _f64(Z), _f64(W)
+    R = Z @ D.T - X                          # D z - x
+    return soft_threshold(Z - a * (R @ W), lam * b)
+
+
+def lista_forward(D, X, lam, W, alpha, beta, return_iterates: bool = False):
+    """The LISTA network of Section 4, Eq. (12): z^(0) = 0 and
+    z^(t+1) = phi_{theta_t}(z^(t), x) with per-layer theta_t = (W_t, alpha_t, beta_t),
+    W [T, n, m]. With W_t = D and alpha_t = beta_t this is the Step-LISTA /
+    ISTA recursion (the remark after Eq. (12)).
+
+    Returns Z^(T) [N, m] and F [T+1, N] (F[t] = F_x(z^(t)), Eq. (1)), plus the
+    iterates if asked. Pins: ISTA equivalence for W_t = D, alpha_t = beta_t;
+    the closed form of one layer from z^(0) = 0, z^(1) = ST(alpha_0 W_0^T x,
+    beta_0 lam); a Lasso solution is a fixed point of every layer with
+    alpha W = beta D (the "if" direction of Lemma 4.3)."""
+    D, X, W = _f64(D), _f64(X), _f64(W)
+    alpha = _f64(alpha).reshape(-1)
+    beta = _f64(beta).reshape(-1)
+    if W.ndim != 3 or W.shape[0] != alpha.shape[0] or beta.shape != alpha.shape:
+        raise ValueError("W must be [T, n, m] with alpha, beta of length T")
+    N, m = X.shape[0], D.shape[1]
+    Z = np.zeros((N, m))
+    iterates = [Z]
+    trace = [objective(D, X, Z, lam)]
+    for t in range(alpha.shape[0]):
+        Z = lista_layer(D, X, lam, Z, W[t], alpha[t], beta[t])
+        iterates.append(Z)
+        trace.append(objective(D, X, Z, lam))
+    F = np.stack(trace)
+    return (Z, F, iterates) if return_iterates else (Z, F)
+
+
+def lista_forward_backward(D, X, lam, W, alpha, beta, dZ=None, dF=None):
+    """LISTA forward pass plus the reverse-mode derivative of
+    J = sum_i dF_i F_{x_i}(z_i^(T)) + <dZ, Z^(T)> with respect to every layer's
+    (W_t, alpha_t, beta_t); with dF_i = 1/N, J is the unsupervised loss of
+    Eq. (15) that the paper trains LISTA on (Section 5 / Appendix D).
+
+    Written out by hand (the paper uses automatic differentiation): with
+    r = D z^(t) - x, u = z^(t) - alpha_t W_t^T r, M = [|u| > beta_t lam],
+      seed         g = dZ + dF_i (D^T (D z^(T) - x) + lam sign z^(T))
+      v            = g * M
+      dJ/dalpha_t  = - sum v * (W_t^T r)
+      dJ/dbeta_t   = - lam sum v * sign(u)
+      dJ/dW_t      = - alpha_t sum_i r_i v_i^T          ([n, m])
+      g            = v - alpha_t D^T (W_t v)             (back through the layer)
+
+    Returns (Z [N, m], F [T+1, N], dW [T, n, m], dalpha [T], dbeta [T]).
+    Pins: central finite differences of lista_forward; for W_t = D and
+    alpha_t = beta_t, dalpha + dbeta equals the Step-LISTA derivative of
+    forward_backward; the rescaling (W, alpha) -> (c W, alpha / c) leaves the
+    network unchanged, so sum W_t * dW_t = alpha_t dalpha_t for every t."""
+    D, X, W = _f64(D), _f64(X), _f64(W)
+    alpha = _f64(alpha).reshape(-1)
+    beta = _f64(beta).reshape(-1)
+    Z, F, iterates = lista_forward(D, X, lam, W, alpha, beta, return_iterates=True)
+    if dZ is None and dF is None:
+        raise ValueError("lista_forward_backward needs dZ and/or dF")
+    N, m = X.shape[0], D.shape[1]
+    g = np.zeros((N, m)) if dZ is None else _f64(dZ).copy()
+    if dF is not None:
+        dF = _f64(dF).reshape(-1)
+        g = g + dF[:, None] * ((Z @ D.T - X) @ D + lam * np.sign(Z))
+    T = alpha.shape[0]
+    dW = np.zeros_like(W)
+    dalpha = np.zeros(T)
+    dbeta = np.zeros(T)
+    for t in range(T - 1, -1, -1):
+        a, b, Wt, Zt = alpha[t], beta[t], W[t], iterates[t]
+        R = Zt @ D.T - X                     # D z^(t) - x
+        WR = R @ Wt                          # W_t^T (D z^(t) - x)
+        U = Zt - a * WR
+        v = np.where(np.abs(U) > lam * b, g, 0.0)
+        dalpha[t] = -np.sum(v * WR)
+        dbeta[t] = -lam * np.sum(v * np.sign(U))
+        dW[t] = -a * (R.T @ v)
+        g = v - a * ((v @ Wt.T) @ D)
+    return Z, F, dW, dalpha, dbeta

@@ -278,3 +278,116 @@ def test_oista_converges_faster_than_ista_and_reaches_kkt():
     assert np.all(steps >= 1.0 / L * (1 - 1e-12)) and np.any(steps > 1.5 / L)
     _, Flong = oracle.oista(pb.D, pb.X, pb.lam, 400)
     assert np.max(Flong[-1] - Fs) < 1e-9
+
+
+# --- coupled LISTA (Section 4, Eq. (11)-(12); Lemma 4.3, Theorem 4.4) -------
+
+def _lista_params(pb, T, seed, spread=0.3):
+    """Per-layer parameters near the ISTA point: W_t = D + spread E_t,
+    alpha_t, beta_t around 1/L."""
+    rng = np.random.default_rng(seed)
+    L = oracle.lipschitz(pb.D)
+    W = pb.D[None] + spread * rng.standard_normal((T, pb.n, pb.m)) / np.sqrt(pb.n)
+    alpha = (1.0 / L) * rng.uniform(0.6, 1.4, T)
+    beta = (1.0 / L) * rng.uniform(0.6, 1.4, T)
+    return W, alpha, beta
+
+
+def test_lista_coupled_to_dictionary_is_ista():
+    """W_t = D, alpha_t = beta_t gives the Step-LISTA recursion (the remark
+    after Eq. (12)); with alpha_t = 1/L, ISTA."""
+    pb = synth.make_problem(8, 16, 30, 0.2, 0.01, 0.1, seed=31)
+    L = oracle.lipschitz(pb.D)
+    for alpha in (np.full(7, 1.0 / L), synth.perturbed_steps(L, 7, seed=2)):
+        W = np.repeat(pb.D[None], 7, axis=0)
+        Zl, Fl = oracle.lista_forward(pb.D, pb.X, pb.lam, W, alpha, alpha)
+        Zs, Fs = oracle.forward(pb.D, pb.X, pb.lam, alpha)
+        np.testing.assert_allclose(Zl, Zs, rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(Fl, Fs, rtol=1e-13)
+
+
+def test_lista_one_layer_closed_form():
+    """From z^(0) = 0 the residual is -x, so z^(1) = ST(alpha W^T x, beta lam)
+    = sign(W^T x) max(alpha |W^T x| - beta lam, 0), checked coordinate by
+    coordinate with plain Python arithmetic."""
+    pb = synth.make_problem(5, 9, 4, 0.3, 0.01, 0.1, seed=32)
+    W, a, b = _lista_params(pb, 1, seed=3)
+    Z, _ = oracle.lista_forward(pb.D, pb.X, pb.lam, W, a, b)
+    for i in range(pb.N):
+        for j in range(pb.m):
+            wx = sum(W[0, k, j] * pb.X[i, k] for k in range(pb.n))
+            mag = a[0] * abs(wx) - b[0] * pb.lam
+            want = (1.0 if wx > 0 else -1.0) * mag if mag > 0 else 0.0
+            assert Z[i, j] == pytest.approx(want, rel=1e-12, abs=1e-15)
+
+
+@pytest.mark.parametrize("use_dz", [False, True])
+def test_lista_adjoint_vs_finite_differences(use_dz):
+    pb = synth.make_problem(6, 12, 20, 0.25, 0.01, 0.1, seed=33)
+    T = 5
+    W, alpha, beta = _lista_params(pb, T, seed=4)
+    dF = np.full(pb.N, 1.0 / pb.N)
+    rng = np.random.default_rng(6)
+    dZ = rng.standard_normal((pb.N, pb.m)) if use_dz else None
+    _, _, dW, da, db = oracle.lista_forward_backward(pb.D, pb.X, pb.lam, W, alpha, beta, dZ=dZ, dF=dF)
+
+    def J(W_, a_, b_):
+        Z, F = oracle.lista_forward(pb.D, pb.X, pb.lam, W_, a_, b_)
+        return float(np.sum(dF * F[-1])) + (float(np.sum(dZ * Z)) if use_dz else 0.0)
+
+    h = 1e-6
+    for t in range(T):
+        e = np.zeros(T)
+        e[t] = h
+        fa = (J(W, alpha + e, beta) - J(W, alpha - e, beta)) / (2 * h)
+        fb = (J(W, alpha, beta + e) - J(W, alpha, beta - e)) / (2 * h)
+        assert da[t] == pytest.approx(fa, rel=1e-5, abs=1e-7 * max(1.0, abs(fa)))
+        assert db[t] == pytest.approx(fb, rel=1e-5, abs=1e-7 * max(1.0, abs(fb)))
+    scale = np.max(np.abs(dW))
+    for _ in range(25):
+        t, k, j = rng.integers(T), rng.integers(pb.n), rng.integers(pb.m)
+        Wp, Wm = W.copy(), W.copy()
+        Wp[t, k, j] += h
+        Wm[t, k, j] -= h
+        fd = (J(Wp, alpha, beta) - J(Wm, alpha, beta)) / (2 * h)
+        assert abs(dW[t, k, j] - fd) <= 1e-6 * scale
+
+
+def test_lista_adjoint_reduces_to_step_lista():
+    """With W_t = D and alpha_t = beta_t = a_t, a_t drives both the step and the
+    threshold, so the Step-LISTA derivative (itself pinned by finite
+    differences) is dalpha_t + dbeta_t of the LISTA network."""
+    pb = synth.make_problem(8, 16, 24, 0.2, 0.01, 0.1, seed=34)
+    L = oracle.lipschitz(pb.D)
+    a = synth.perturbed_steps(L, 6, seed=5)
+    dF = np.full(pb.N, 1.0 / pb.N)
+    W = np.repeat(pb.D[None], 6, axis=0)
+    _, _, _, da, db = oracle.lista_forward_backward(pb.D, pb.X, pb.lam, W, a, a, dF=dF)
+    _, _, g = oracle.forward_backward(pb.D, pb.X, pb.lam, a, dF=dF)
+    np.testing.assert_allclose(da + db, g, rtol=1e-10, atol=1e-14)
+
+
+def test_lista_adjoint_rescaling_invariant():
+    """(W_t, alpha_t) -> (c W_t, alpha_t / c) leaves every layer unchanged, so
+    the derivative along that direction vanishes: <W_t, dW_t> = alpha_t dalpha_t."""
+    pb = synth.make_problem(8, 20, 30, 0.2, 0.01, 0.1, seed=35)
+    W, alpha, beta = _lista_params(pb, 6, seed=7, spread=0.5)
+    _, _, dW, da, _ = oracle.lista_forward_backward(pb.D, pb.X, pb.lam, W, alpha, beta,
+                                                    dF=np.full(pb.N, 1.0 / pb.N))
+    lhs = np.einsum("tkj,tkj->t", W, dW)
+    np.testing.assert_allclose(lhs, alpha * da, rtol=1e-10, atol=1e-14)
+
+
+def test_lista_fixed_point_iff_aligned_lemma43():
+    """Lemma 4.3 on the Lemma 4.2 construction: z* = (1 - lam) e_j is a fixed
+    point of a layer with alpha W = beta D, and is moved by a layer whose
+    column j is not aligned with D_j."""
+    D, X, lam, Z, _ = pins.lemma42_case()
+    rng = np.random.default_rng(8)
+    for a, b in ((0.3, 0.3), (0.5, 0.2), (0.1, 0.4)):
+        W = (b / a) * D
+        np.testing.assert_allclose(oracle.lista_layer(D, X, lam, Z, W, a, b), Z, atol=1e-12)
+    j = int(np.flatnonzero(Z[0])[0])
+    W = D.copy()
+    W[:, j] += 0.5 * rng.standard_normal(D.shape[0])
+    assert np.max(np.abs(oracle.lista_layer(D, X, lam, Z, W, 0.3, 0.3) - Z)) > 1e-3
