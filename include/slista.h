@@ -308,6 +308,57 @@ SLISTA_API int slista_oista(const slista_dict* dict, const float* X, int N, floa
                             void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Coupled LISTA (Section 4, Eq. (11)-(12)): T layers with their own
+ * parameters theta_t = (W_t, alpha_t, beta_t), from z^(0) = 0,
+ *     z^(t+1) = ST(z^(t) - alpha_t W_t^T (D z^(t) - x), beta_t lambda),
+ * the architecture whose deep layers Theorem 4.4 shows must reduce to
+ * Step-LISTA (alpha_t W_t -> beta_t D). W_t = D and alpha_t = beta_t give
+ * slista_forward's recursion.
+ *
+ * Computed in the factored form: per layer the residual R = Z D^T - X (a
+ * contraction over m) and R W_t (over n), both on MFMA in the given
+ * precision, with the soft-threshold and the objective partials fused into
+ * their epilogues. Per-layer kernels.
+ *
+ *   W      device FP32 [T, n, m] (row-major per layer; W_t has D's shape).
+ *   alpha, beta  device FP32 [T] (alpha_t, beta_t > 0 is a precondition).
+ *   Z      device FP32 [N, m] out: z^(T).
+ *   F      device FP32 [N] out or NULL: F_{x_i}(z_i^(T)) (Eq. (1)) from the
+ *          FP32 residual, accumulated in FP64.
+ *   loss   device FP32 [1] out or NULL: mean_i F_{x_i}(z_i^(T)) (Eq. (15)).
+ *   tape   nonzero: keep z^(0..T) and D z^(t) - x for slista_lista_backward.
+ *   ws     device workspace of slista_lista_workspace_size(dict, N, T,
+ *          prec, tape) bytes, 256-byte aligned; it also holds the operand
+ *          copies of D and W that the backward reads.
+ *
+ * slista_lista_backward differentiates J = sum_i dF_i F_{x_i}(z_i^(T)) +
+ * <dZ, Z^(T)> (dF [N] and dZ [N, m] device, each may be NULL but not both)
+ * with respect to every layer's parameters: dW device FP32 [T, n, m] (NULL
+ * = skip the weight gradient), dalpha and dbeta device FP32 [T]. The
+ * derivative of ST is 1 where |u| > beta_t lambda and 0 elsewhere; sign(0) =
+ * 0 in the sub-gradient of |z|. The weight gradient dW_t = -alpha_t sum_i
+ * r_i v_i^T is a sum over the samples, computed with FP32 operands in both
+ * precisions. Precondition: ws holds the tape of a slista_lista_forward call
+ * with tape != 0 and the same dict, N, lambda, W, alpha, beta, T and prec.
+ * slista_lista_forward_backward does both for the mean loss (dF_i = 1/N).
+ *
+ * Errors: SLISTA_EINVAL for a NULL dict or required pointer, N or T out of
+ * range, lambda not finite and > 0, an unknown precision, or a short or
+ * misaligned workspace. N = 0 writes zero gradients and loss.
+ * ------------------------------------------------------------------------- */
+SLISTA_API int slista_lista_workspace_size(const slista_dict* dict, int N, int T, int prec, int tape, size_t* bytes);
+SLISTA_API int slista_lista_forward(const slista_dict* dict, const float* X, int N, float lambda, const float* W,
+                                    const float* alpha, const float* beta, int T, int prec, float* Z, float* F,
+                                    float* loss, int tape, void* ws, size_t ws_bytes, void* stream);
+SLISTA_API int slista_lista_backward(const slista_dict* dict, int N, float lambda, const float* alpha,
+                                     const float* beta, int T, int prec, const float* dZ, const float* dF, float* dW,
+                                     float* dalpha, float* dbeta, void* ws, size_t ws_bytes, void* stream);
+SLISTA_API int slista_lista_forward_backward(const slista_dict* dict, const float* X, int N, float lambda,
+                                             const float* W, const float* alpha, const float* beta, int T, int prec,
+                                             float* Z, float* F, float* loss, float* dW, float* dalpha, float* dbeta,
+                                             void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Learning the step sizes (Appendix D, "Training the networks"): full-batch
  * sub-gradient descent on the mean loss of Eq. (15) with a backtracking
  * learning rate. From steps alpha with loss J and gradient g, each iteration

@@ -14,6 +14,12 @@ from .ops import (  # noqa: F401
     train,
     fista,
     oista,
+    lista,
+    lista_backward,
+    lista_forward,
+    lista_forward_backward,
+    lista_workspace,
+    ListaFunction,
     backward,
     forward,
     forward_backward,

@@ -54,6 +54,13 @@ SIGNATURES = {
     "slista_train": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _c_int, _c_double, _c_int, _vp,
                               ctypes.POINTER(_c_double), ctypes.POINTER(_c_int), ctypes.POINTER(_c_double), _vp,
                               _size_t, _vp]),
+    "slista_lista_workspace_size": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_size_t)]),
+    "slista_lista_forward": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _vp, _vp, _c_int, _c_int, _vp, _vp, _vp,
+                                      _c_int, _vp, _size_t, _vp]),
+    "slista_lista_backward": (_c_int, [_vp, _c_int, _c_float, _vp, _vp, _c_int, _c_int, _vp, _vp, _vp, _vp, _vp,
+                                       _vp, _size_t, _vp]),
+    "slista_lista_forward_backward": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _vp, _vp, _c_int, _c_int, _vp, _vp,
+                                               _vp, _vp, _vp, _vp, _vp, _size_t, _vp]),
     "slista_tune_save": (_c_int, [ctypes.c_char_p]),
     "slista_tune_load": (_c_int, [ctypes.c_char_p]),
     "slista_batch_create": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_vp)]),

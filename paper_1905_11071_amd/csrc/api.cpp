@@ -506,6 +506,250 @@ int run_backward(const Run& r, float lam, const float* alpha, int prec, const fl
   return SLISTA_OK;
 }
 
+// ------------------------------------------------------------- coupled LISTA
+// Factored form of Eq. (11): per layer R^t = Z^t D^T - X (contraction over
+// m_pad) then z^{t+1} = ST(z^t - alpha_t R^t W_t, lam beta_t) (contraction
+// over n_pad). The adjoint runs Q = V W_t^T, v' = [z^t != 0](v - alpha_t Q D)
+// and dW_t = -alpha_t (R^t)^T V, the last as a split contraction over the
+// samples on transposed copies of R^t and V (FP32 in both precisions).
+// Workspace: operand copies of D and of the W stack, the padded samples, the
+// iterates z^0..z^T and residuals R^0..R^T (tape) or two z and one R buffer,
+// objective partials and, with the tape, the adjoint buffers.
+struct ListaLayout {
+  int n_pad = 0, m_pad = 0, ctn = 0, ctm = 0, Pa = 0, Pb = 0, S = 1, Kc = 0, Np = 0, opb = 4;
+  bool tape = false;
+  size_t zbytes = 0, rbytes = 0;
+  size_t Xp = 0, Dr = 0, DT = 0, Wr = 0, WT = 0, zs = 0, rs = 0, fres = 0, fl1 = 0, Fd = 0;
+  size_t vb = 0, q = 0, dpa = 0, dpb = 0, RT = 0, VT = 0, wpart = 0, total = 0;
+};
+
+ListaLayout lista_layout(const slista::Dict& d, int N, int T, int prec, bool tape) {
+  ListaLayout L;
+  L.tape = tape;
+  L.m_pad = d.m_pad;
+  L.n_pad = (d.n + slista::kPadM - 1) / slista::kPadM * slista::kPadM;
+  L.opb = prec == slista::kF32 ? 4 : 2;
+  L.zbytes = (size_t)N * L.m_pad * sizeof(float);
+  L.rbytes = (size_t)N * L.n_pad * sizeof(float);
+  const int row_tiles = (N + kTileRows - 1) / kTileRows;
+  L.ctn = (L.n_pad + kTileCols - 1) / kTileCols;
+  L.ctm = (L.m_pad + kTileCols - 1) / kTileCols;
+  L.Pa = row_tiles * L.ctn;
+  L.Pb = row_tiles * L.ctm;
+  // sample chunks of the weight-gradient contraction: enough workgroups to
+  // fill the chip, at least ~256 samples (8 K steps) per chunk
+  const int wtiles = ((d.n + kTileRows - 1) / kTileRows) * ((d.m + kTileCols - 1) / kTileCols);
+  int S = 512 / wtiles;
+  const int by_n = (N + 255) / 256;
+  if (S > by_n) S = by_n;
+  if (S < 1) S = 1;
+  const int per = (N + S - 1) / S;
+  L.Kc = (per + 31) / 32 * 32;
+  if (L.Kc < 32) L.Kc = 32;
+  L.S = (N + L.Kc - 1) / L.Kc;
+  if (L.S < 1) L.S = 1;
+  L.Np = L.S * L.Kc;
+  const size_t dmat = (size_t)L.n_pad * L.m_pad * L.opb;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes > 0 ? bytes : 1);
+    return o;
+  };
+  L.Xp = take(L.rbytes);
+  L.Dr = take(dmat);
+  L.DT = take(dmat);
+  L.Wr = take(dmat * (size_t)T);
+  L.WT = take(dmat * (size_t)T);
+  L.zs = take(L.zbytes * (tape ? (size_t)T + 1 : 2));
+  L.rs = take(L.rbytes * (tape ? (size_t)T + 1 : 1));
+  L.fres = take((size_t)L.ctn * N * sizeof(double));
+  L.fl1 = take((size_t)L.ctm * N * sizeof(double));
+  L.Fd = take((size_t)N * sizeof(double));
+  if (tape) {
+    L.vb = take(2 * L.zbytes);
+    L.q = take(L.rbytes);
+    L.dpa = take((size_t)T * L.Pa * sizeof(double));
+    L.dpb = take((size_t)T * L.Pb * sizeof(double));
+    L.RT = take((size_t)d.n * L.Np * sizeof(float));
+    L.VT = take((size_t)d.m * L.Np * sizeof(float));
+    L.wpart = take((size_t)L.S * d.n * d.m * sizeof(float));
+  }
+  L.total = off;
+  return L;
+}
+
+struct ListaRun {
+  const slista::Dict* d;
+  ListaLayout L;
+  char* ws;
+  int N, T, prec;
+  hipStream_t s;
+  float* z(int t) const {
+    const int slot = L.tape ? t : (t & 1);
+    return (float*)(ws + L.zs + (size_t)slot * L.zbytes);
+  }
+  float* r(int t) const { return (float*)(ws + L.rs + (size_t)(L.tape ? t : 0) * L.rbytes); }
+  float* v(int t) const { return (float*)(ws + L.vb + (size_t)(t & 1) * L.zbytes); }
+  const void* Wr(int t) const { return ws + L.Wr + (size_t)t * L.n_pad * L.m_pad * L.opb; }
+  const void* WT(int t) const { return ws + L.WT + (size_t)t * L.n_pad * L.m_pad * L.opb; }
+  float* Xp() const { return (float*)(ws + L.Xp); }
+  double* fres() const { return (double*)(ws + L.fres); }
+  double* fl1() const { return (double*)(ws + L.fl1); }
+  double* Fd() const { return (double*)(ws + L.Fd); }
+};
+
+// Contraction with N sample rows: A [N][lda] times the K-contiguous operand Bt.
+slista::GemmArgs lista_args(const ListaRun& r, const float* A, int lda, const void* Bt, int K, int ncols, float* Out) {
+  slista::GemmArgs g;
+  std::memset(&g, 0, sizeof g);
+  g.A = A;
+  g.lda = lda;
+  g.Bt = Bt;
+  g.ldb = K;
+  g.K = K;
+  g.rows = r.N;
+  g.ncols = ncols;
+  g.ldz = ncols;
+  g.Out = Out;
+  g.m = r.d->m;
+  slista::gemm_grid(r.N, ncols, g);
+  return g;
+}
+
+// R^t = Z^t D^T - X; fpart (may be NULL) gets 1/2 |R^t|^2 by column tile.
+int lista_resid(const ListaRun& r, int t, double* fpart) {
+  const ListaLayout& L = r.L;
+  slista::GemmArgs g = lista_args(r, r.z(t), L.m_pad, r.ws + L.Dr, L.m_pad, L.n_pad, r.r(t));
+  g.C = r.Xp();
+  g.fpart = fpart;
+  LAUNCH(kKFwd, r.s, slista::launch_gemm(r.prec, slista::kEpiResid, false, g, r.s));
+  return SLISTA_OK;
+}
+
+int lista_check(const slista_dict* dict, int N, int T, float lambda, int prec) {
+  if (!dict) return fail(SLISTA_EINVAL, "dict is NULL");
+  if (N < 0 || N > kMaxN) return fail(SLISTA_EINVAL, "N=%d outside [0, %d]", N, kMaxN);
+  if (T < 0 || T > kMaxT) return fail(SLISTA_EINVAL, "T=%d outside [0, %d]", T, kMaxT);
+  if (!(lambda > 0.f) || !std::isfinite(lambda))
+    return fail(SLISTA_EINVAL, "lambda=%g must be finite and > 0", (double)lambda);
+  if (prec != SLISTA_FP32 && prec != SLISTA_BF16) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
+  return SLISTA_OK;
+}
+
+int lista_check_ws(const ListaLayout& L, void* ws, size_t ws_bytes) {
+  if (!ws) return fail(SLISTA_EINVAL, "workspace is NULL (%zu bytes needed)", L.total);
+  if (((uintptr_t)ws & 255) != 0) return fail(SLISTA_EINVAL, "workspace not 256-byte aligned");
+  if (ws_bytes < L.total) return fail(SLISTA_EINVAL, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+  return SLISTA_OK;
+}
+
+int lista_forward_run(const ListaRun& r, const float* X, float lam, const float* W, const float* alpha,
+                      const float* beta, float* Z, float* F, float* loss) {
+  const slista::Dict& d = *r.d;
+  const ListaLayout& L = r.L;
+  const int N = r.N, T = r.T;
+  hipStream_t s = r.s;
+  LAUNCH(kKOther, s, slista::launch_lista_pack(d.Dt, 1, d.n, d.m, d.n, 0, 1, L.n_pad, L.m_pad, r.prec, r.ws + L.Dr,
+                                               r.ws + L.DT, s));
+  if (T > 0)
+    LAUNCH(kKOther, s, slista::launch_lista_pack(W, T, d.n, d.m, d.m, (size_t)d.n * d.m, 0, L.n_pad, L.m_pad, r.prec,
+                                                 r.ws + L.Wr, r.ws + L.WT, s));
+  LAUNCH(kKOther, s, slista::launch_pad_rows(X, N, d.n, L.n_pad, r.Xp(), s));
+  LAUNCH(kKOther, s, slista::launch_fill(r.z(0), (size_t)N * L.m_pad, 0.f, s));
+  const bool want_f = F || loss;
+  int st;
+  for (int t = 0; t < T; ++t) {
+    if ((st = lista_resid(r, t, nullptr)) != SLISTA_OK) return st;
+    slista::GemmArgs g = lista_args(r, r.r(t), L.n_pad, r.WT(t), L.n_pad, L.m_pad, r.z(t + 1));
+    g.Zt = r.z(t);
+    g.alpha = alpha;
+    g.beta = beta;
+    g.t = t;
+    g.lam = lam;
+    g.fpart = (want_f && t == T - 1) ? r.fl1() : nullptr;
+    LAUNCH(kKFwd, s, slista::launch_gemm(r.prec, slista::kEpiLista, false, g, s));
+  }
+  // R^T: the residual term of F(z^T) and the backward seed's input
+  if (want_f || L.tape)
+    if ((st = lista_resid(r, T, want_f ? r.fres() : nullptr)) != SLISTA_OK) return st;
+  LAUNCH(kKOther, s, slista::launch_copy_out(r.z(T), N, L.m_pad, d.m, Z, s));
+  if (want_f) {
+    LAUNCH(kKOther, s, slista::launch_lista_reduce_f(r.fres(), L.ctn, r.fl1(), T > 0 ? L.ctm : 0, N, F, r.Fd(), s));
+    if (loss) LAUNCH(kKOther, s, slista::launch_reduce_loss(r.Fd(), N, loss, s));
+  }
+  return SLISTA_OK;
+}
+
+int lista_backward_run(const ListaRun& r, float lam, const float* alpha, const float* dZ, const float* dF,
+                       float dF_scalar, float* dW, float* dalpha, float* dbeta) {
+  const slista::Dict& d = *r.d;
+  const ListaLayout& L = r.L;
+  const int N = r.N, T = r.T;
+  hipStream_t s = r.s;
+  if (T == 0) return SLISTA_OK;
+  {  // seed v^{T-1} = [z^T != 0] (dF D^T R^T + dF lam sign z^T + dZ)
+    slista::GemmArgs g = lista_args(r, r.r(T), L.n_pad, r.ws + L.DT, L.n_pad, L.m_pad, r.v(T - 1));
+    g.Zt = r.z(T);
+    g.C = nullptr;
+    g.dF = dF;
+    g.dF_scalar = dF_scalar;
+    g.dZ = dZ;
+    g.lam = lam;
+    LAUNCH(kKSeed, s, slista::launch_gemm(r.prec, slista::kEpiSeed, false, g, s));
+  }
+  double* dpa = (double*)(r.ws + L.dpa);
+  double* dpb = (double*)(r.ws + L.dpb);
+  float* q = (float*)(r.ws + L.q);
+  float* RT = (float*)(r.ws + L.RT);
+  float* VT = (float*)(r.ws + L.VT);
+  float* wpart = (float*)(r.ws + L.wpart);
+  for (int t = T - 1; t >= 0; --t) {
+    const float* v = r.v(t);
+    {  // Q = V W_t^T, dalpha_t partials against R^t
+      slista::GemmArgs g = lista_args(r, v, L.m_pad, r.Wr(t), L.m_pad, L.n_pad, q);
+      g.C = r.r(t);
+      g.dpart = dpa + (size_t)t * L.Pa;
+      LAUNCH(kKBwd, s, slista::launch_gemm(r.prec, slista::kEpiListaQ, false, g, s));
+    }
+    if (dW) {  // dW_t = -alpha_t sum_i r_i v_i^T
+      LAUNCH(kKOther, s, slista::launch_transpose_pad(r.r(t), N, L.n_pad, d.n, L.Np, RT, s));
+      LAUNCH(kKOther, s, slista::launch_transpose_pad(v, N, L.m_pad, d.m, L.Np, VT, s));
+      slista::GemmArgs g;
+      std::memset(&g, 0, sizeof g);
+      g.A = RT;
+      g.lda = L.Np;
+      g.Bt = VT;
+      g.ldb = L.Np;
+      g.K = L.Kc;
+      g.rows = d.n;
+      g.ncols = d.m;
+      g.ldz = d.m;
+      g.Out = wpart;
+      g.ksplit = L.S;
+      g.a_split = (size_t)L.Kc;
+      g.b_split = (size_t)L.Kc;
+      g.out_split = (size_t)d.n * d.m;
+      slista::gemm_grid(d.n, d.m, g);
+      LAUNCH(kKBwd, s, slista::launch_gemm(slista::kF32, slista::kEpiSplit, false, g, s));
+      LAUNCH(kKOther, s, slista::launch_lista_reduce_w(wpart, L.S, (size_t)d.n * d.m, alpha, t,
+                                                       dW + (size_t)t * d.n * d.m, s));
+    }
+    {  // v^{t-1} = [z^t != 0] (v^t - alpha_t Q D), dbeta_t partials
+      slista::GemmArgs g = lista_args(r, q, L.n_pad, r.ws + L.DT, L.n_pad, L.m_pad, r.v(t - 1));
+      g.Vin = v;
+      g.Zt = r.z(t);
+      g.Zt1 = r.z(t + 1);
+      g.alpha = alpha;
+      g.t = t;
+      g.dpart = dpb + (size_t)t * L.Pb;
+      LAUNCH(kKBwd, s, slista::launch_gemm(r.prec, slista::kEpiListaBwd, false, g, s));
+    }
+  }
+  LAUNCH(kKOther, s, slista::launch_lista_reduce_ab(dpa, L.Pa, dpb, L.Pb, T, lam, dalpha, dbeta, s));
+  return SLISTA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -934,6 +1178,80 @@ int slista_oista(const slista_dict* dict, const float* X, int N, float lambda, d
     if (loss) LAUNCH(kKOther, s, slista::launch_reduce_loss(r.Fd(), N, loss, s));
   }
   return SLISTA_OK;
+}
+
+int slista_lista_workspace_size(const slista_dict* dict, int N, int T, int prec, int tape, size_t* bytes) {
+  if (!bytes) return fail(SLISTA_EINVAL, "bytes is NULL");
+  int st = lista_check(dict, N, T, 1.f, prec);
+  if (st != SLISTA_OK) return st;
+  *bytes = lista_layout(dict->d, N, T, prec, tape != 0).total;
+  return SLISTA_OK;
+}
+
+int slista_lista_forward(const slista_dict* dict, const float* X, int N, float lambda, const float* W,
+                         const float* alpha, const float* beta, int T, int prec, float* Z, float* F, float* loss,
+                         int tape, void* ws, size_t ws_bytes, void* stream) {
+  int st = lista_check(dict, N, T, lambda, prec);
+  if (st != SLISTA_OK) return st;
+  if (N > 0 && (!X || !Z)) return fail(SLISTA_EINVAL, "X or Z is NULL");
+  if (T > 0 && (!W || !alpha || !beta)) return fail(SLISTA_EINVAL, "W, alpha or beta is NULL");
+  const ListaLayout L = lista_layout(dict->d, N, T, prec, tape != 0);
+  if ((st = lista_check_ws(L, ws, ws_bytes)) != SLISTA_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (N == 0) {
+    if (loss) LAUNCH(kKOther, s, slista::launch_fill(loss, 1, 0.f, s));
+    return SLISTA_OK;
+  }
+  const ListaRun r{&dict->d, L, (char*)ws, N, T, prec, s};
+  return lista_forward_run(r, X, lambda, W, alpha, beta, Z, F, loss);
+}
+
+int slista_lista_backward(const slista_dict* dict, int N, float lambda, const float* alpha, const float* beta, int T,
+                          int prec, const float* dZ, const float* dF, float* dW, float* dalpha, float* dbeta,
+                          void* ws, size_t ws_bytes, void* stream) {
+  int st = lista_check(dict, N, T, lambda, prec);
+  if (st != SLISTA_OK) return st;
+  if (!dZ && !dF) return fail(SLISTA_EINVAL, "dZ and dF are both NULL");
+  if (T > 0 && (!alpha || !beta || !dalpha || !dbeta)) return fail(SLISTA_EINVAL, "alpha, beta, dalpha or dbeta is NULL");
+  const ListaLayout L = lista_layout(dict->d, N, T, prec, true);
+  if ((st = lista_check_ws(L, ws, ws_bytes)) != SLISTA_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (N == 0 || T == 0) {
+    if (T > 0) {
+      LAUNCH(kKOther, s, slista::launch_fill(dalpha, T, 0.f, s));
+      LAUNCH(kKOther, s, slista::launch_fill(dbeta, T, 0.f, s));
+      if (dW) LAUNCH(kKOther, s, slista::launch_fill(dW, (size_t)T * dict->d.n * dict->d.m, 0.f, s));
+    }
+    return SLISTA_OK;
+  }
+  const ListaRun r{&dict->d, L, (char*)ws, N, T, prec, s};
+  return lista_backward_run(r, lambda, alpha, dZ, dF, 0.f, dW, dalpha, dbeta);
+}
+
+int slista_lista_forward_backward(const slista_dict* dict, const float* X, int N, float lambda, const float* W,
+                                  const float* alpha, const float* beta, int T, int prec, float* Z, float* F,
+                                  float* loss, float* dW, float* dalpha, float* dbeta, void* ws, size_t ws_bytes,
+                                  void* stream) {
+  int st = lista_check(dict, N, T, lambda, prec);
+  if (st != SLISTA_OK) return st;
+  if (N > 0 && (!X || !Z)) return fail(SLISTA_EINVAL, "X or Z is NULL");
+  if (T > 0 && (!W || !alpha || !beta || !dalpha || !dbeta))
+    return fail(SLISTA_EINVAL, "W, alpha, beta, dalpha or dbeta is NULL");
+  const ListaLayout L = lista_layout(dict->d, N, T, prec, true);
+  if ((st = lista_check_ws(L, ws, ws_bytes)) != SLISTA_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (N == 0) {
+    if (loss) LAUNCH(kKOther, s, slista::launch_fill(loss, 1, 0.f, s));
+    if (T > 0) {
+      LAUNCH(kKOther, s, slista::launch_fill(dalpha, T, 0.f, s));
+      LAUNCH(kKOther, s, slista::launch_fill(dbeta, T, 0.f, s));
+      if (dW) LAUNCH(kKOther, s, slista::launch_fill(dW, (size_t)T * dict->d.n * dict->d.m, 0.f, s));
+    }
+    return SLISTA_OK;
+  }
+  const ListaRun r{&dict->d, L, (char*)ws, N, T, prec, s};
+  if ((st = lista_forward_run(r, X, lambda, W, alpha, beta, Z, F, loss)) != SLISTA_OK) return st;
+  return lista_backward_run(r, lambda, alpha, nullptr, nullptr, (float)(1.0 / N), dW, dalpha, dbeta);
 }
 
 // ------------------------------------------------------------- training

@@ -25,7 +25,13 @@ enum Epi : int {
   kEpiSeed = 3,   // v^{T-1} = [z^T != 0] (dF (P - c + lam sign z^T) + dZ)  (backward seed)
   kEpiBwd = 4,    // dalpha_t partial; v^{t-1} = [z^t != 0] (v^t - a P)  (one layer back)
   kEpiFista = 5,  // z^{t+1} = ST(y^t - a (P - c), lam a), y^{t+1} = z^{t+1} + b (z^{t+1} - z^t)  (FISTA)
-  kEpiGrad = 6    // R = P - c; per-row count of z_j = 0 with |R_j| > lam  (Oracle-ISTA)
+  kEpiGrad = 6,   // R = P - c; per-row count of z_j = 0 with |R_j| > lam  (Oracle-ISTA)
+  // coupled LISTA (factored form, per-layer W_t)
+  kEpiResid = 7,    // R = P - x (P = Z D^T); objective partial 1/2 |R|^2
+  kEpiLista = 8,    // z^{t+1} = ST(z^t - a P, lam b) (P = R W_t); objective partial lam |z^{t+1}|
+  kEpiListaQ = 9,   // Q = P (P = V W_t^T); dalpha partial sum Q . R^t
+  kEpiListaBwd = 10,  // v^{t-1} = [z^t != 0] (v^t - a P) (P = Q D); dbeta partial sum v^t sign z^{t+1}
+  kEpiSplit = 11    // Out + s out_split = P over the K chunk s = blockIdx.y (FP32 only)
 };
 
 struct Dict {
@@ -64,8 +70,12 @@ struct GemmArgs {
   float dF_scalar;
   const float* dZ;    // [rows][m] upstream gradient of z^T, or null
   int m;
-  const float* beta;  // [T] momentum weights (kEpiFista)
+  const float* beta;  // [T] momentum weights (kEpiFista), thresholds (kEpiLista)
   float* Out2;        // [rows][ldz] second output: y^{t+1} (kEpiFista)
+  // kEpiSplit: grid.y = ksplit chunks of K; chunk s reads A + s a_split,
+  // Bt + s b_split and writes Out + s out_split (element offsets)
+  int ksplit;
+  size_t a_split, b_split, out_split;
 };
 
 // Launchers (kernels_gemm.hip)
@@ -101,6 +111,26 @@ hipError_t launch_support_lipschitz(const float* G32, int m, int mp, const float
                                     int max_iter, double tol, int N, float* step, hipStream_t s);
 hipError_t launch_oista_update(const float* Z, const float* R, const double* flags, int col_tiles, const float* step,
                                double L, float lam, int N, int mp, float* Zout, float* steps_used, hipStream_t s);
+// Coupled LISTA helpers (kernels_lista.hip).
+// Operand copies of a stack of T matrices M_t [n][m] (entry (t, k, j) at
+// M[t mstride + k ld + j], or at M[t mstride + j ld + k] when trans != 0):
+// Mr [T][n_pad][m_pad] (rows of M_t) and Mt [T][m_pad][n_pad] (columns of
+// M_t), zero padded, as FP32 or BF16 bit patterns.
+hipError_t launch_lista_pack(const float* M, int T, int n, int m, int ld, size_t mstride, int trans, int n_pad,
+                             int m_pad, int prec, void* Mr, void* Mt, hipStream_t s);
+// Xp [N][n_pad] = X [N][n] zero padded.
+hipError_t launch_pad_rows(const float* X, int N, int n, int n_pad, float* Xp, hipStream_t s);
+// dst [cols][Np] = src [N][ld] transposed (columns 0..cols), 0 for samples >= N.
+hipError_t launch_transpose_pad(const float* src, int N, int ld, int cols, int Np, float* dst, hipStream_t s);
+// F_i = sum of the residual partials + sum of the l1 partials (FP64).
+hipError_t launch_lista_reduce_f(const double* fres, int ctn, const double* fl1, int ctm, int N, float* F,
+                                 double* Fd, hipStream_t s);
+// dalpha_t = -sum_p dpa[t][p]; dbeta_t = -lam sum_p dpb[t][p].
+hipError_t launch_lista_reduce_ab(const double* dpa, int Pa, const double* dpb, int Pb, int T, float lam,
+                                  float* dalpha, float* dbeta, hipStream_t s);
+// dW_t = -alpha_t sum_s part[s] (count entries per chunk, FP64 sum).
+hipError_t launch_lista_reduce_w(const float* part, int S, size_t count, const float* alpha, int t, float* dW,
+                                 hipStream_t s);
 hipError_t launch_bwd0(const float* V0, const float* Z1, int N, int ldz, double* dpart, int nblocks,
                        hipStream_t s);
 hipError_t launch_reduce_dalpha(const double* dpart, int T, int P, int count0, int count, const float* alpha,

@@ -165,6 +165,12 @@ __device__ __forceinline__ float soft_thresh(float u, float th) {
 template <int P, int EPI, bool SAFE>
 __global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) char smem[2 * STAGE_BYTES];
+  if constexpr (EPI == kEpiSplit) {  // K chunk blockIdx.y of a split contraction
+    const size_t sp = blockIdx.y;
+    g.A += sp * g.a_split;
+    g.Bt = (const float*)g.Bt + sp * g.b_split;
+    g.Out += sp * g.out_split;
+  }
   const int b = blockIdx.x;
   const int tile = (b & 7) * g.tiles_per_xcd + (b >> 3);
   if (tile >= g.row_tiles * g.col_tiles) return;
@@ -199,6 +205,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
   const float lam = g.lam;
   const float th = lam * a;
   const float bt = (EPI == kEpiFista) ? g.beta[g.t] : 0.f;
+  const float lth = (EPI == kEpiLista) ? lam * g.beta[g.t] : 0.f;  // LISTA threshold lam beta_t
   double fs[4][4];
   double dsum = 0.0;
 #pragma unroll
@@ -220,8 +227,23 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
         if (col >= g.ncols) continue;
         const size_t idx = (size_t)row * g.ldz + col;
         const float p = acc[fm][fn][r4];
-        if constexpr (EPI == kEpiCorr) {
+        if constexpr (EPI == kEpiCorr || EPI == kEpiSplit) {
           g.Out[idx] = p;
+        } else if constexpr (EPI == kEpiResid) {
+          const float r = p - g.C[idx];  // D z - x
+          g.Out[idx] = r;
+          if (g.fpart) fs[fm][r4] += 0.5 * (double)r * (double)r;
+        } else if constexpr (EPI == kEpiLista) {
+          const float zn = soft_thresh(g.Zt[idx] - a * p, lth);
+          g.Out[idx] = zn;
+          if (g.fpart) fs[fm][r4] += (double)lam * fabs((double)zn);
+        } else if constexpr (EPI == kEpiListaQ) {
+          g.Out[idx] = p;  // W_t v
+          dsum += (double)p * (double)g.C[idx];  // (W_t v) . (D z^t - x)
+        } else if constexpr (EPI == kEpiListaBwd) {
+          const float v = g.Vin[idx], zt = g.Zt[idx];
+          dsum += (double)v * (double)sgnf(g.Zt1[idx]);
+          g.Out[idx] = (zt != 0.f) ? v - a * p : 0.f;
         } else if constexpr (EPI == kEpiFwd) {
           const float z = g.Zt[idx], c = g.C[idx];
           g.Out[idx] = soft_thresh(z - a * (p - c), th);
@@ -230,7 +252,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
           const float z = g.Zt[idx], c = g.C[idx];
           fs[fm][r4] += (double)(0.5f * z * p - z * c + lam * fabsf(z));
         } else if constexpr (EPI == kEpiSeed) {
-          const float z = g.Zt[idx], c = g.C[idx];
+          const float z = g.Zt[idx], c = g.C ? g.C[idx] : 0.f;  // LISTA seeds pass P = D^T (D z - x), no c
           float gv = w * (p - c + lam * sgnf(z));
           if (g.dZ && col < g.m) gv += g.dZ[(size_t)row * g.m + col];
           g.Out[idx] = (z != 0.f) ? gv : 0.f;
@@ -255,7 +277,8 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
     }
   }
 
-  if constexpr (EPI == kEpiFwd || EPI == kEpiFinal || EPI == kEpiSeed || EPI == kEpiGrad) {
+  if constexpr (EPI == kEpiFwd || EPI == kEpiFinal || EPI == kEpiSeed || EPI == kEpiGrad || EPI == kEpiResid ||
+                EPI == kEpiLista) {
     if (g.fpart) {  // uniform across the workgroup
       double* red = (double*)smem;  // [2][BM]
 #pragma unroll
@@ -276,7 +299,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
       }
     }
   }
-  if constexpr (EPI == kEpiBwd) {
+  if constexpr (EPI == kEpiBwd || EPI == kEpiListaQ || EPI == kEpiListaBwd) {
     double* red = (double*)smem;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) dsum += __shfl_xor(dsum, o);
@@ -289,8 +312,9 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
 template <int P, int EPI, bool SAFE>
 hipError_t launch_one(const GemmArgs& a, hipStream_t s) {
   const int grid = 8 * a.tiles_per_xcd;
-  if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL((gemm_fused<P, EPI, SAFE>), dim3(grid), dim3(NTHREADS), 0, s, a);
+  const int splits = EPI == kEpiSplit ? a.ksplit : 1;
+  if (grid == 0 || splits < 1) return grid == 0 ? hipSuccess : hipErrorInvalidValue;
+  hipLaunchKernelGGL((gemm_fused<P, EPI, SAFE>), dim3(grid, splits), dim3(NTHREADS), 0, s, a);
   return hipGetLastError();
 }
 
@@ -316,6 +340,11 @@ hipError_t launch_gemm(int prec, int epi, bool safe, const GemmArgs& a, hipStrea
       case kEpiBwd: return launch_one<kF32, kEpiBwd, false>(a, s);
       case kEpiFista: return launch_one<kF32, kEpiFista, false>(a, s);
       case kEpiGrad: return launch_one<kF32, kEpiGrad, false>(a, s);
+      case kEpiResid: return launch_one<kF32, kEpiResid, false>(a, s);
+      case kEpiLista: return launch_one<kF32, kEpiLista, false>(a, s);
+      case kEpiListaQ: return launch_one<kF32, kEpiListaQ, false>(a, s);
+      case kEpiListaBwd: return launch_one<kF32, kEpiListaBwd, false>(a, s);
+      case kEpiSplit: return launch_one<kF32, kEpiSplit, false>(a, s);
       default: return hipErrorInvalidValue;
     }
   }
@@ -326,6 +355,10 @@ hipError_t launch_gemm(int prec, int epi, bool safe, const GemmArgs& a, hipStrea
     case kEpiBwd: return launch_one<kBF16, kEpiBwd, false>(a, s);
     case kEpiFista: return launch_one<kBF16, kEpiFista, false>(a, s);
     case kEpiGrad: return launch_one<kBF16, kEpiGrad, false>(a, s);
+    case kEpiResid: return launch_one<kBF16, kEpiResid, false>(a, s);
+    case kEpiLista: return launch_one<kBF16, kEpiLista, false>(a, s);
+    case kEpiListaQ: return launch_one<kBF16, kEpiListaQ, false>(a, s);
+    case kEpiListaBwd: return launch_one<kBF16, kEpiListaBwd, false>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

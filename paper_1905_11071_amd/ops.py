@@ -409,3 +409,121 @@ def slista(alpha: torch.Tensor, d: Dictionary, X: torch.Tensor, lam: float, prec
     ckpt_every: checkpoint spacing of the tape (1 = keep every layer), or
     "auto" for the smallest spacing whose workspace fits the free memory."""
     return SlistaFunction.apply(alpha, d, X, lam, prec, ckpt_every)
+
+
+# --------------------------------------------------------------- coupled LISTA
+
+def _check_lista(d: Dictionary, W: torch.Tensor, alpha: torch.Tensor, beta: torch.Tensor):
+    alpha = _dev_f32(alpha, "alpha")
+    if alpha.dim() != 1:
+        raise ValueError("alpha must be [T]")
+    T = int(alpha.shape[0])
+    beta = _dev_f32(beta, "beta", (T,))
+    W = _dev_f32(W, "W", (T, d.n, d.m))
+    return W, alpha, beta
+
+
+def lista_workspace(d: Dictionary, N: int, T: int, prec="fp32", tape: bool = False) -> torch.Tensor:
+    nbytes = ctypes.c_size_t()
+    check(lib().slista_lista_workspace_size(d.handle, int(N), int(T), _prec(prec), int(bool(tape)),
+                                            ctypes.byref(nbytes)))
+    return torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=d.device)
+
+
+def lista_forward(d: Dictionary, X: torch.Tensor, lam: float, W: torch.Tensor, alpha: torch.Tensor,
+                  beta: torch.Tensor, prec="fp32", tape: bool = False, ws: Optional[torch.Tensor] = None):
+    """T coupled LISTA layers (per-layer W_t [n, m], alpha_t, beta_t; W is
+    [T, n, m]). Returns (Z, F of z^T, mean loss, ws); with tape the workspace
+    keeps what lista_backward reads."""
+    X = _dev_f32(X, "X")
+    if X.dim() != 2 or X.shape[1] != d.n:
+        raise ValueError(f"X must be [N, {d.n}]")
+    W, alpha, beta = _check_lista(d, W, alpha, beta)
+    N, T = int(X.shape[0]), int(alpha.shape[0])
+    p = _prec(prec)
+    if ws is None:
+        ws = lista_workspace(d, N, T, p, tape)
+    Z = torch.empty(N, d.m, device=d.device, dtype=torch.float32)
+    F = torch.empty(N, device=d.device, dtype=torch.float32)
+    loss = torch.empty(1, device=d.device, dtype=torch.float32)
+    check(lib().slista_lista_forward(d.handle, X.data_ptr(), N, float(lam), W.data_ptr(), alpha.data_ptr(),
+                                     beta.data_ptr(), T, p, Z.data_ptr(), F.data_ptr(), loss.data_ptr(),
+                                     int(bool(tape)), ws.data_ptr(), ws.numel(), _stream(d.device)))
+    return Z, F, loss, ws
+
+
+def lista_backward(d: Dictionary, N: int, lam: float, alpha: torch.Tensor, beta: torch.Tensor, ws: torch.Tensor,
+                   dZ: Optional[torch.Tensor] = None, dF: Optional[torch.Tensor] = None, prec="fp32",
+                   want_dW: bool = True):
+    """(dW [T, n, m] or None, dalpha [T], dbeta [T]) of J = sum dF_i F_i(z^T) +
+    <dZ, Z^T>, from the tape of a lista_forward(tape=True) call in ws."""
+    alpha = _dev_f32(alpha, "alpha")
+    T = int(alpha.shape[0])
+    beta = _dev_f32(beta, "beta", (T,))
+    if dZ is not None:
+        dZ = _dev_f32(dZ, "dZ", (N, d.m))
+    if dF is not None:
+        dF = _dev_f32(dF, "dF", (N,))
+    dW = torch.empty(T, d.n, d.m, device=d.device, dtype=torch.float32) if want_dW else None
+    dalpha = torch.empty(T, device=d.device, dtype=torch.float32)
+    dbeta = torch.empty(T, device=d.device, dtype=torch.float32)
+    check(lib().slista_lista_backward(d.handle, int(N), float(lam), alpha.data_ptr(), beta.data_ptr(), T,
+                                      _prec(prec), _ptr(dZ), _ptr(dF), _ptr(dW), dalpha.data_ptr(),
+                                      dbeta.data_ptr(), ws.data_ptr(), ws.numel(), _stream(d.device)))
+    return dW, dalpha, dbeta
+
+
+def lista_forward_backward(d: Dictionary, X: torch.Tensor, lam: float, W: torch.Tensor, alpha: torch.Tensor,
+                           beta: torch.Tensor, prec="fp32", want_dW: bool = True, ws: Optional[torch.Tensor] = None):
+    """Forward plus the gradient of the mean loss (Eq. (15)) in every layer's
+    parameters. Returns (Z, F, loss, dW or None, dalpha, dbeta, ws)."""
+    X = _dev_f32(X, "X")
+    if X.dim() != 2 or X.shape[1] != d.n:
+        raise ValueError(f"X must be [N, {d.n}]")
+    W, alpha, beta = _check_lista(d, W, alpha, beta)
+    N, T = int(X.shape[0]), int(alpha.shape[0])
+    p = _prec(prec)
+    if ws is None:
+        ws = lista_workspace(d, N, T, p, True)
+    Z = torch.empty(N, d.m, device=d.device, dtype=torch.float32)
+    F = torch.empty(N, device=d.device, dtype=torch.float32)
+    loss = torch.empty(1, device=d.device, dtype=torch.float32)
+    dW = torch.empty(T, d.n, d.m, device=d.device, dtype=torch.float32) if want_dW else None
+    dalpha = torch.empty(T, device=d.device, dtype=torch.float32)
+    dbeta = torch.empty(T, device=d.device, dtype=torch.float32)
+    check(lib().slista_lista_forward_backward(d.handle, X.data_ptr(), N, float(lam), W.data_ptr(), alpha.data_ptr(),
+                                              beta.data_ptr(), T, p, Z.data_ptr(), F.data_ptr(), loss.data_ptr(),
+                                              _ptr(dW), dalpha.data_ptr(), dbeta.data_ptr(), ws.data_ptr(),
+                                              ws.numel(), _stream(d.device)))
+    return Z, F, loss, dW, dalpha, dbeta, ws
+
+
+class ListaFunction(torch.autograd.Function):
+    """Coupled LISTA as an autograd node: (W, alpha, beta) -> (z^(T), F(z^(T))),
+    differentiated by the library's hand-written adjoint over the tape the
+    forward kept in its workspace."""
+
+    @staticmethod
+    def forward(ctx, W, alpha, beta, d: Dictionary, X, lam, prec="fp32"):
+        Z, F, _, ws = lista_forward(d, X, lam, W, alpha, beta, prec=prec, tape=True)
+        ctx.save_for_backward(alpha, beta)
+        ctx.d, ctx.lam, ctx.prec, ctx.ws, ctx.N = d, lam, prec, ws, int(X.shape[0])
+        return Z, F
+
+    @staticmethod
+    def backward(ctx, gZ, gF):
+        alpha, beta = ctx.saved_tensors
+        if gZ is None and gF is None:
+            return None, None, None, None, None, None, None
+        dW, dalpha, dbeta = lista_backward(ctx.d, ctx.N, ctx.lam, alpha, beta, ctx.ws,
+                                           dZ=None if gZ is None else gZ.contiguous(),
+                                           dF=None if gF is None else gF.contiguous(), prec=ctx.prec,
+                                           want_dW=ctx.needs_input_grad[0])
+        return dW, dalpha, dbeta, None, None, None, None
+
+
+def lista(W: torch.Tensor, alpha: torch.Tensor, beta: torch.Tensor, d: Dictionary, X: torch.Tensor, lam: float,
+          prec="fp32"):
+    """Differentiable coupled LISTA network: returns (Z, F) with gradients to
+    W [T, n, m], alpha [T] and beta [T]."""
+    return ListaFunction.apply(W, alpha, beta, d, X, lam, prec)
