@@ -248,6 +248,52 @@ def training_report(sl, torch, iters: int) -> dict:
     return out
 
 
+def lista_report(sl, torch, reps: int, precs) -> dict:
+    """Coupled LISTA forward+backward (all parameter gradients, dW included) on
+    the 64 x 256 Gaussian workload, N = 10000, T = 40: sample-layers/s and the
+    useful contraction rate. Useful flops per call: forward 2 contractions of
+    2nm per sample-layer, backward 3 (W v, D^T (W v), the sum for dW), plus
+    the final residual and the seed: N (10 n m T + 4 n m)."""
+    import synth
+    c = synth.CONFIGS["lista_64x256"]
+    pb = synth.make_problem(c["n"], c["m"], c["N"], c["p"], c["sigma"], c["lam_frac"], c["seed"])
+    dev = torch.device("cuda:0")
+    d = sl.Dictionary(torch.tensor(pb.D32(), device=dev))
+    L, _ = d.lipschitz(max_iter=100_000, rtol=1e-12)
+    W, a, b = (torch.tensor(v, device=dev, dtype=torch.float32)
+               for v in synth.lista_params(pb.D, L, c["T"], c["seed"], c["spread"]))
+    X = torch.tensor(pb.X32(), device=dev)
+    N, T, n, m = pb.N, c["T"], pb.n, pb.m
+    flops = N * (10.0 * n * m * T + 4.0 * n * m)
+    out = {"workload": "lista_64x256", "n": n, "m": m, "N": N, "T": T, "pass": "forward+backward (dW, dalpha, dbeta)"}
+    for p in precs:
+        ws = sl.lista_workspace(d, N, T, p, tape=True)
+        for _ in range(2):
+            sl.lista_forward_backward(d, X, pb.lam, W, a, b, prec=p, ws=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            res = sl.lista_forward_backward(d, X, pb.lam, W, a, b, prec=p, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        # per-class breakdown from one more call with per-launch events (which
+        # add their own gaps, so it is not the timed figure)
+        sl.profile_begin()
+        sl.lista_forward_backward(d, X, pb.lam, W, a, b, prec=p, ws=ws)
+        torch.cuda.synchronize()
+        prof = sl.profile_end()
+        peak = PEAK["bf16_tflops"] if p == "bf16" else PEAK["fp32_tflops"]
+        tf = flops / (ms * 1e-3) / 1e12
+        out[p] = {"ms_per_call": round(ms, 4), "value": round(N * T / (ms * 1e-3), 1), "unit": "sample-layers/s",
+                  "useful_tflops": round(tf, 2), "mfma_frac": round(tf / peak, 5), "loss": float(res[2].item()),
+                  "kernels_ms": {k: [v[0], round(v[1], 4)] for k, v in prof.items() if k != "dropped" and v[0] > 0}}
+        del ws
+    d.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +310,8 @@ def main() -> int:
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven 64-problem batch")
     ap.add_argument("--no-train", action="store_true", help="skip the step-size training report")
     ap.add_argument("--train-iters", type=int, default=30)
+    ap.add_argument("--no-lista", action="store_true", help="skip the coupled LISTA report")
+    ap.add_argument("--lista-reps", type=int, default=10)
     ap.add_argument("--uneven-precs", default="bf16,fp32")
     ap.add_argument("--uneven-reps", type=int, default=3)
     ap.add_argument("--copy-calib", action="store_true",
@@ -346,6 +394,11 @@ def main() -> int:
         train = training_report(sl, torch, args.train_iters)
         print(f"[bench] training {train}", file=sys.stderr, flush=True)
 
+    lista = None
+    if not args.no_lista:
+        lista = lista_report(sl, torch, args.lista_reps, ("fp32", "bf16"))
+        print(f"[bench] lista {lista}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pb, np.asarray(alpha.cpu().numpy(), np.float64), min(args.cpu_sample, pb.N))
@@ -379,6 +432,7 @@ def main() -> int:
         "objective_gap": gap,
         "uneven_batch": uneven,
         "training": train,
+        "lista": lista,
         "autotune": tuned or {"forced_variant": args.variant},
     }
     print(json.dumps(line))

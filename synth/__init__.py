@@ -114,6 +114,19 @@ def perturbed_steps(L: float, T: int, seed: int, spread: float = 0.3) -> np.ndar
     return _f32(a)
 
 
+def lista_params(D: np.ndarray, L: float, T: int, seed: int, spread: float):
+    """Per-layer LISTA parameters near the ISTA point, rounded to float32:
+    W_t = D + spread E_t / sqrt(n) with E_t standard normal [n, m], and
+    alpha_t, beta_t drawn uniformly from (0.6 / L, 1.4 / L). Returns
+    (W [T, n, m], alpha [T], beta [T])."""
+    rng = np.random.default_rng(seed)
+    n, m = D.shape
+    W = np.asarray(D, np.float64)[None] + spread * rng.standard_normal((T, n, m)) / np.sqrt(n)
+    a = (1.0 / L) * rng.uniform(0.6, 1.4, T)
+    b = (1.0 / L) * rng.uniform(0.6, 1.4, T)
+    return _f32(W), _f32(a), _f32(b)
+
+
 # The five workloads. Seeds: config k uses 1000 + k; problem p of the uneven
 # batch uses 5000 + p.
 CONFIGS: Dict[str, dict] = {
@@ -125,6 +138,9 @@ CONFIGS: Dict[str, dict] = {
     "grad_64x256": dict(n=64, m=256, N=4096, T=20, p=0.05, sigma=0.01, lam_frac=0.1, seed=1003),
     # Precision study, 256x1024, N=65536, T=50, forward+backward.
     "prec_256x1024": dict(n=256, m=1024, N=65_536, T=50, p=0.02, sigma=0.0, lam_frac=0.05, seed=1004),
+    # Coupled LISTA (per-layer W_t, alpha_t, beta_t) on the 64x256 Gaussian
+    # setting, forward+backward with the weight gradient.
+    "lista_64x256": dict(n=64, m=256, N=10_000, T=40, p=0.05, sigma=0.01, lam_frac=0.1, seed=1006, spread=0.2),
 }
 
 # The uneven batch (sizes from uneven_problem_specs): common depth and checkpoint spacing.

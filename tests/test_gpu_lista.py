@@ -10,7 +10,6 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_common import round_to_bf16
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -48,14 +47,8 @@ def _f32(a):
 
 
 def _params(pb, T, seed, spread):
-    """W_t = D + spread E_t / sqrt(n), alpha_t, beta_t in (0.6, 1.4) / L; the
-    FP32 values, so both sides see the same parameters."""
-    rng = np.random.default_rng(seed)
-    L = oracle.lipschitz(pb.D)
-    W = pb.D[None] + spread * rng.standard_normal((T, pb.n, pb.m)) / np.sqrt(pb.n)
-    a = (1.0 / L) * rng.uniform(0.6, 1.4, T)
-    b = (1.0 / L) * rng.uniform(0.6, 1.4, T)
-    return _f32(W), _f32(a), _f32(b)
+    """FP32 parameters near the ISTA point, so both sides see the same values."""
+    return synth.lista_params(pb.D, oracle.lipschitz(pb.D), T, seed, spread)
 
 
 def _case(name):
