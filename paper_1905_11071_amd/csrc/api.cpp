@@ -516,7 +516,7 @@ int run_backward(const Run& r, float lam, const float* alpha, int prec, const fl
 // iterates z^0..z^T and residuals R^0..R^T (tape) or two z and one R buffer,
 // objective partials and, with the tape, the adjoint buffers.
 struct ListaLayout {
-  int n_pad = 0, m_pad = 0, ctn = 0, ctm = 0, Pa = 0, Pb = 0, S = 1, Kc = 0, Np = 0, opb = 4;
+  int n_pad = 0, m_pad = 0, ctn = 0, ctm = 0, Pa = 0, Pb = 0, S = 1, Kc = 0, Np = 0, opb = 4, Gl = 1;
   bool tape = false;
   size_t zbytes = 0, rbytes = 0;
   size_t Xp = 0, Dr = 0, DT = 0, Wr = 0, WT = 0, zs = 0, rs = 0, fres = 0, fl1 = 0, Fd = 0;
@@ -537,18 +537,24 @@ ListaLayout lista_layout(const slista::Dict& d, int N, int T, int prec, bool tap
   L.Pa = row_tiles * L.ctn;
   L.Pb = row_tiles * L.ctm;
   // sample chunks of the weight-gradient contraction: enough workgroups to
-  // fill the chip, at least ~256 samples (8 K steps) per chunk
+  // fill the chip, at least ~256 samples (8 K steps) per chunk, Kc a
+  // multiple of 64 (the transpose tile)
   const int wtiles = ((d.n + kTileRows - 1) / kTileRows) * ((d.m + kTileCols - 1) / kTileCols);
   int S = 512 / wtiles;
   const int by_n = (N + 255) / 256;
   if (S > by_n) S = by_n;
   if (S < 1) S = 1;
   const int per = (N + S - 1) / S;
-  L.Kc = (per + 31) / 32 * 32;
-  if (L.Kc < 32) L.Kc = 32;
+  L.Kc = (per + 63) / 64 * 64;
+  if (L.Kc < 64) L.Kc = 64;
   L.S = (N + L.Kc - 1) / L.Kc;
   if (L.S < 1) L.S = 1;
   L.Np = L.S * L.Kc;
+  // layers per weight-gradient launch: about 1024 workgroups per launch
+  const int per_layer = L.S * wtiles;
+  L.Gl = (1024 + per_layer - 1) / per_layer;
+  if (L.Gl > T) L.Gl = T;
+  if (L.Gl < 1) L.Gl = 1;
   const size_t dmat = (size_t)L.n_pad * L.m_pad * L.opb;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -567,13 +573,13 @@ ListaLayout lista_layout(const slista::Dict& d, int N, int T, int prec, bool tap
   L.fl1 = take((size_t)L.ctm * N * sizeof(double));
   L.Fd = take((size_t)N * sizeof(double));
   if (tape) {
-    L.vb = take(2 * L.zbytes);
+    L.vb = take(((size_t)T + 1) * L.zbytes);  // v^t for every layer (slot T: the unused v^{-1})
     L.q = take(L.rbytes);
     L.dpa = take((size_t)T * L.Pa * sizeof(double));
     L.dpb = take((size_t)T * L.Pb * sizeof(double));
-    L.RT = take((size_t)d.n * L.Np * sizeof(float));
-    L.VT = take((size_t)d.m * L.Np * sizeof(float));
-    L.wpart = take((size_t)L.S * d.n * d.m * sizeof(float));
+    L.RT = take((size_t)L.Gl * d.n * L.Np * sizeof(float));
+    L.VT = take((size_t)L.Gl * d.m * L.Np * sizeof(float));
+    L.wpart = take((size_t)L.Gl * L.S * d.n * d.m * sizeof(float));
   }
   L.total = off;
   return L;
@@ -590,7 +596,7 @@ struct ListaRun {
     return (float*)(ws + L.zs + (size_t)slot * L.zbytes);
   }
   float* r(int t) const { return (float*)(ws + L.rs + (size_t)(L.tape ? t : 0) * L.rbytes); }
-  float* v(int t) const { return (float*)(ws + L.vb + (size_t)(t & 1) * L.zbytes); }
+  float* v(int t) const { return (float*)(ws + L.vb + (size_t)(t >= 0 ? t : T) * L.zbytes); }
   const void* Wr(int t) const { return ws + L.Wr + (size_t)t * L.n_pad * L.m_pad * L.opb; }
   const void* WT(int t) const { return ws + L.WT + (size_t)t * L.n_pad * L.m_pad * L.opb; }
   float* Xp() const { return (float*)(ws + L.Xp); }
@@ -712,29 +718,6 @@ int lista_backward_run(const ListaRun& r, float lam, const float* alpha, const f
       g.dpart = dpa + (size_t)t * L.Pa;
       LAUNCH(kKBwd, s, slista::launch_gemm(r.prec, slista::kEpiListaQ, false, g, s));
     }
-    if (dW) {  // dW_t = -alpha_t sum_i r_i v_i^T
-      LAUNCH(kKOther, s, slista::launch_transpose_pad(r.r(t), N, L.n_pad, d.n, L.Np, RT, s));
-      LAUNCH(kKOther, s, slista::launch_transpose_pad(v, N, L.m_pad, d.m, L.Np, VT, s));
-      slista::GemmArgs g;
-      std::memset(&g, 0, sizeof g);
-      g.A = RT;
-      g.lda = L.Np;
-      g.Bt = VT;
-      g.ldb = L.Np;
-      g.K = L.Kc;
-      g.rows = d.n;
-      g.ncols = d.m;
-      g.ldz = d.m;
-      g.Out = wpart;
-      g.ksplit = L.S;
-      g.a_split = (size_t)L.Kc;
-      g.b_split = (size_t)L.Kc;
-      g.out_split = (size_t)d.n * d.m;
-      slista::gemm_grid(d.n, d.m, g);
-      LAUNCH(kKBwd, s, slista::launch_gemm(slista::kF32, slista::kEpiSplit, false, g, s));
-      LAUNCH(kKOther, s, slista::launch_lista_reduce_w(wpart, L.S, (size_t)d.n * d.m, alpha, t,
-                                                       dW + (size_t)t * d.n * d.m, s));
-    }
     {  // v^{t-1} = [z^t != 0] (v^t - alpha_t Q D), dbeta_t partials
       slista::GemmArgs g = lista_args(r, q, L.n_pad, r.ws + L.DT, L.n_pad, L.m_pad, r.v(t - 1));
       g.Vin = v;
@@ -747,6 +730,37 @@ int lista_backward_run(const ListaRun& r, float lam, const float* alpha, const f
     }
   }
   LAUNCH(kKOther, s, slista::launch_lista_reduce_ab(dpa, L.Pa, dpb, L.Pb, T, lam, dalpha, dbeta, s));
+  // dW_t = -alpha_t sum_i r_i v_i^T, Gl layers per launch: R^t and v^t
+  // transposed to column-major copies, then a contraction over sample chunks
+  for (int t0 = 0; dW && t0 < T; t0 += L.Gl) {
+    const int g = T - t0 < L.Gl ? T - t0 : L.Gl;
+    LAUNCH(kKOther, s, slista::launch_transpose_pad(r.r(t0), N, L.n_pad, d.n, L.Np, L.Kc, RT, g,
+                                                    L.rbytes / sizeof(float), (size_t)d.n * L.Np, s));
+    LAUNCH(kKOther, s, slista::launch_transpose_pad(r.v(t0), N, L.m_pad, d.m, L.Np, L.Kc, VT, g,
+                                                    L.zbytes / sizeof(float), (size_t)d.m * L.Np, s));
+    slista::GemmArgs gw;
+    std::memset(&gw, 0, sizeof gw);
+    gw.A = RT;  // chunk s of layer b: [n][Kc] at RT + b n Np + s n Kc
+    gw.lda = L.Kc;
+    gw.Bt = VT;
+    gw.ldb = L.Kc;
+    gw.K = L.Kc;
+    gw.rows = d.n;
+    gw.ncols = d.m;
+    gw.ldz = d.m;
+    gw.Out = wpart;
+    gw.ksplit = L.S;
+    gw.nbatch = g;
+    gw.a_split = (size_t)d.n * L.Kc;
+    gw.b_split = (size_t)d.m * L.Kc;
+    gw.a_batch = (size_t)d.n * L.Np;
+    gw.b_batch = (size_t)d.m * L.Np;
+    gw.out_split = (size_t)d.n * d.m;
+    slista::gemm_grid(d.n, d.m, gw);
+    LAUNCH(kKBwd, s, slista::launch_gemm(slista::kF32, slista::kEpiSplit, false, gw, s));
+    LAUNCH(kKOther, s, slista::launch_lista_reduce_w(wpart, L.S, (size_t)d.n * d.m, alpha + t0, g,
+                                                     dW + (size_t)t0 * d.n * d.m, s));
+  }
   return SLISTA_OK;
 }
 

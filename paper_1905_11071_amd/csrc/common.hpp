@@ -31,7 +31,7 @@ enum Epi : int {
   kEpiLista = 8,    // z^{t+1} = ST(z^t - a P, lam b) (P = R W_t); objective partial lam |z^{t+1}|
   kEpiListaQ = 9,   // Q = P (P = V W_t^T); dalpha partial sum Q . R^t
   kEpiListaBwd = 10,  // v^{t-1} = [z^t != 0] (v^t - a P) (P = Q D); dbeta partial sum v^t sign z^{t+1}
-  kEpiSplit = 11    // Out + s out_split = P over the K chunk s = blockIdx.y (FP32 only)
+  kEpiSplit = 11    // P over one K chunk of a split, batched contraction (FP32 only)
 };
 
 struct Dict {
@@ -72,10 +72,11 @@ struct GemmArgs {
   int m;
   const float* beta;  // [T] momentum weights (kEpiFista), thresholds (kEpiLista)
   float* Out2;        // [rows][ldz] second output: y^{t+1} (kEpiFista)
-  // kEpiSplit: grid.y = ksplit chunks of K; chunk s reads A + s a_split,
-  // Bt + s b_split and writes Out + s out_split (element offsets)
-  int ksplit;
-  size_t a_split, b_split, out_split;
+  // kEpiSplit: grid.y = nbatch * ksplit (nbatch 0 counts as 1); y = b * ksplit + s is K chunk s of
+  // batch entry b: it reads A + b a_batch + s a_split, Bt + b b_batch +
+  // s b_split and writes Out + y out_split (element offsets)
+  int ksplit, nbatch;
+  size_t a_split, b_split, out_split, a_batch, b_batch;
 };
 
 // Launchers (kernels_gemm.hip)
@@ -120,16 +121,21 @@ hipError_t launch_lista_pack(const float* M, int T, int n, int m, int ld, size_t
                              int m_pad, int prec, void* Mr, void* Mt, hipStream_t s);
 // Xp [N][n_pad] = X [N][n] zero padded.
 hipError_t launch_pad_rows(const float* X, int N, int n, int n_pad, float* Xp, hipStream_t s);
-// dst [cols][Np] = src [N][ld] transposed (columns 0..cols), 0 for samples >= N.
-hipError_t launch_transpose_pad(const float* src, int N, int ld, int cols, int Np, float* dst, hipStream_t s);
+// For each of `batch` matrices b: src_b [N][ld] (columns 0..cols) transposed
+// into chunks of Kc samples, dst_b [Np / Kc][cols][Kc] (Kc a multiple of 64
+// dividing Np), 0 for samples >= N; src_b = src + b src_stride, dst_b = dst +
+// b dst_stride (elements).
+hipError_t launch_transpose_pad(const float* src, int N, int ld, int cols, int Np, int Kc, float* dst, int batch,
+                                size_t src_stride, size_t dst_stride, hipStream_t s);
 // F_i = sum of the residual partials + sum of the l1 partials (FP64).
 hipError_t launch_lista_reduce_f(const double* fres, int ctn, const double* fl1, int ctm, int N, float* F,
                                  double* Fd, hipStream_t s);
 // dalpha_t = -sum_p dpa[t][p]; dbeta_t = -lam sum_p dpb[t][p].
 hipError_t launch_lista_reduce_ab(const double* dpa, int Pa, const double* dpb, int Pb, int T, float lam,
                                   float* dalpha, float* dbeta, hipStream_t s);
-// dW_t = -alpha_t sum_s part[s] (count entries per chunk, FP64 sum).
-hipError_t launch_lista_reduce_w(const float* part, int S, size_t count, const float* alpha, int t, float* dW,
+// For every layer t < T: dW_t = -alpha_t sum_s part[t][s] (part [T][S][count],
+// dW [T][count]; FP64 sums in a fixed order).
+hipError_t launch_lista_reduce_w(const float* part, int S, size_t count, const float* alpha, int T, float* dW,
                                  hipStream_t s);
 hipError_t launch_bwd0(const float* V0, const float* Z1, int N, int ldz, double* dpart, int nblocks,
                        hipStream_t s);

@@ -165,14 +165,16 @@ __device__ __forceinline__ float soft_thresh(float u, float th) {
 template <int P, int EPI, bool SAFE>
 __global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) char smem[2 * STAGE_BYTES];
-  if constexpr (EPI == kEpiSplit) {  // K chunk blockIdx.y of a split contraction
-    const size_t sp = blockIdx.y;
-    g.A += sp * g.a_split;
-    g.Bt = (const float*)g.Bt + sp * g.b_split;
-    g.Out += sp * g.out_split;
+  if constexpr (EPI == kEpiSplit) {  // K chunk of one batch entry of a split contraction
+    const size_t y = blockIdx.y, bi = y / g.ksplit, sp = y - bi * g.ksplit;
+    g.A += bi * g.a_batch + sp * g.a_split;
+    g.Bt = (const float*)g.Bt + bi * g.b_batch + sp * g.b_split;
+    g.Out += y * g.out_split;
   }
   const int b = blockIdx.x;
-  const int tile = (b & 7) * g.tiles_per_xcd + (b >> 3);
+  // split contractions launch exactly their tiles in x, so that the (tile,
+  // chunk) workgroups spread over all XCDs; the others order tiles XCD-contiguously
+  const int tile = EPI == kEpiSplit ? b : (b & 7) * g.tiles_per_xcd + (b >> 3);
   if (tile >= g.row_tiles * g.col_tiles) return;
   const int rt = tile / g.col_tiles, ct = tile - rt * g.col_tiles;
   const int row0 = rt * BM, col0 = ct * BN;
@@ -311,8 +313,8 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
 
 template <int P, int EPI, bool SAFE>
 hipError_t launch_one(const GemmArgs& a, hipStream_t s) {
-  const int grid = 8 * a.tiles_per_xcd;
-  const int splits = EPI == kEpiSplit ? a.ksplit : 1;
+  const int grid = EPI == kEpiSplit ? a.row_tiles * a.col_tiles : 8 * a.tiles_per_xcd;
+  const int splits = EPI == kEpiSplit ? a.ksplit * (a.nbatch > 0 ? a.nbatch : 1) : 1;
   if (grid == 0 || splits < 1) return grid == 0 ? hipSuccess : hipErrorInvalidValue;
   hipLaunchKernelGGL((gemm_fused<P, EPI, SAFE>), dim3(grid, splits), dim3(NTHREADS), 0, s, a);
   return hipGetLastError();

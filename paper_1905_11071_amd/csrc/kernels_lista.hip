@@ -61,21 +61,27 @@ __global__ void k_pad_rows(const float* __restrict__ X, int N, int n, int n_pad,
 }
 
 // 64 x 64 tile through LDS: coalesced row reads of the sample-major source and
-// coalesced row writes of the column-major destination; the 65-float row
-// stride keeps the transposed LDS reads on distinct banks.
+// coalesced row writes of the chunk-major destination (chunk = Kc samples, a
+// multiple of 64: dst[i / Kc][c][i % Kc]); the 65-float row stride keeps the
+// transposed LDS reads on distinct banks.
 __global__ __launch_bounds__(kThreads) void k_transpose_pad(const float* __restrict__ src, int N, int ld, int cols,
-                                                            int Np, float* __restrict__ dst) {
+                                                            int Np, int Kc, float* __restrict__ dst, size_t src_stride,
+                                                            size_t dst_stride) {
   __shared__ float tile[64][65];
   const int i0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  src += blockIdx.z * src_stride;
+  dst += blockIdx.z * dst_stride;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int r = ty; r < 64; r += kThreads / 64) {
     const int i = i0 + r, c = c0 + tx;
     tile[r][tx] = (i < N && c < cols) ? src[(size_t)i * ld + c] : 0.f;
   }
   __syncthreads();
+  const size_t chunk = (size_t)(i0 / Kc) * cols * Kc;  // the 64 samples share one chunk
+  const int ic = i0 % Kc + tx;
   for (int r = ty; r < 64; r += kThreads / 64) {
-    const int c = c0 + r, i = i0 + tx;
-    if (c < cols && i < Np) dst[(size_t)c * Np + i] = tile[tx][r];
+    const int c = c0 + r;
+    if (c < cols && i0 + tx < Np) dst[chunk + (size_t)c * Kc + ic] = tile[tx][r];
   }
 }
 
@@ -110,14 +116,16 @@ __global__ __launch_bounds__(kThreads) void k_lista_reduce_ab(const double* __re
   }
 }
 
-// dW_t[e] = -alpha_t sum_s part[s][e] over the K chunks of the sample sum.
+// dW_t[e] = -alpha_t sum_s part[t][s][e] over the K chunks of the sample sum,
+// for every layer t (one thread per entry of the [T][count] output).
 __global__ void k_lista_reduce_w(const float* __restrict__ part, int S, size_t count, const float* __restrict__ alpha,
-                                 int t, float* __restrict__ dW) {
-  const double a = alpha[t];
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
+                                 size_t total, float* __restrict__ dW) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t t = e / count, j = e - t * count;
+    const float* p = part + t * (size_t)S * count + j;
     double s = 0.0;
-    for (int c = 0; c < S; ++c) s += (double)part[(size_t)c * count + e];
-    dW[e] = (float)(-a * s);
+    for (int c = 0; c < S; ++c) s += (double)p[(size_t)c * count];
+    dW[e] = (float)(-(double)alpha[t] * s);
   }
 }
 
@@ -146,10 +154,12 @@ hipError_t launch_pad_rows(const float* X, int N, int n, int n_pad, float* Xp, h
   return hipGetLastError();
 }
 
-hipError_t launch_transpose_pad(const float* src, int N, int ld, int cols, int Np, float* dst, hipStream_t s) {
-  if (Np == 0 || cols == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_transpose_pad, dim3((Np + 63) / 64, (cols + 63) / 64), dim3(kThreads), 0, s, src, N, ld, cols,
-                     Np, dst);
+hipError_t launch_transpose_pad(const float* src, int N, int ld, int cols, int Np, int Kc, float* dst, int batch,
+                                size_t src_stride, size_t dst_stride, hipStream_t s) {
+  if (Np == 0 || cols == 0 || batch == 0) return hipSuccess;
+  if (batch < 0 || batch > 65535 || Kc <= 0 || Kc % 64 != 0 || Np % Kc != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_transpose_pad, dim3((Np + 63) / 64, (cols + 63) / 64, batch), dim3(kThreads), 0, s, src, N, ld,
+                     cols, Np, Kc, dst, src_stride, dst_stride);
   return hipGetLastError();
 }
 
@@ -168,10 +178,12 @@ hipError_t launch_lista_reduce_ab(const double* dpa, int Pa, const double* dpb, 
   return hipGetLastError();
 }
 
-hipError_t launch_lista_reduce_w(const float* part, int S, size_t count, const float* alpha, int t, float* dW,
+hipError_t launch_lista_reduce_w(const float* part, int S, size_t count, const float* alpha, int T, float* dW,
                                  hipStream_t s) {
-  if (count == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lista_reduce_w, dim3(blocks_for(count)), dim3(kThreads), 0, s, part, S, count, alpha, t, dW);
+  const size_t total = count * (size_t)T;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lista_reduce_w, dim3(blocks_for(total)), dim3(kThreads), 0, s, part, S, count, alpha, total,
+                     dW);
   return hipGetLastError();
 }
 
