@@ -31,6 +31,7 @@
 #include "../../include/slista.h"
 #include "common.hpp"
 #include "persist.hpp"
+#include "lista_persist.hpp"
 
 struct slista_dict {
   slista::Dict d;
@@ -516,7 +517,7 @@ int run_backward(const Run& r, float lam, const float* alpha, int prec, const fl
 // iterates z^0..z^T and residuals R^0..R^T (tape) or two z and one R buffer,
 // objective partials and, with the tape, the adjoint buffers.
 struct ListaLayout {
-  int n_pad = 0, m_pad = 0, ctn = 0, ctm = 0, Pa = 0, Pb = 0, S = 1, Kc = 0, Np = 0, opb = 4, Gl = 1;
+  int n_pad = 0, m_pad = 0, ctn = 0, ctm = 0, Pa = 0, Pb = 0, S = 1, Kc = 0, Np = 0, opb = 4, Gl = 1, nwg = 0;
   bool tape = false;
   size_t zbytes = 0, rbytes = 0;
   size_t Xp = 0, Dr = 0, DT = 0, Wr = 0, WT = 0, zs = 0, rs = 0, fres = 0, fl1 = 0, Fd = 0;
@@ -536,6 +537,7 @@ ListaLayout lista_layout(const slista::Dict& d, int N, int T, int prec, bool tap
   L.ctm = (L.m_pad + kTileCols - 1) / kTileCols;
   L.Pa = row_tiles * L.ctn;
   L.Pb = row_tiles * L.ctm;
+  L.nwg = (N + slista::kListaRows - 1) / slista::kListaRows;  // persistent kernels' workgroups
   // sample chunks of the weight-gradient contraction: enough workgroups to
   // fill the chip, at least ~256 samples (8 K steps) per chunk, Kc a
   // multiple of 64 (the transpose tile)
@@ -575,8 +577,8 @@ ListaLayout lista_layout(const slista::Dict& d, int N, int T, int prec, bool tap
   if (tape) {
     L.vb = take(((size_t)T + 1) * L.zbytes);  // v^t for every layer (slot T: the unused v^{-1})
     L.q = take(L.rbytes);
-    L.dpa = take((size_t)T * L.Pa * sizeof(double));
-    L.dpb = take((size_t)T * L.Pb * sizeof(double));
+    L.dpa = take((size_t)T * std::max(L.Pa, L.nwg) * sizeof(double));
+    L.dpb = take((size_t)T * std::max(L.Pb, L.nwg) * sizeof(double));
     L.RT = take((size_t)L.Gl * d.n * L.Np * sizeof(float));
     L.VT = take((size_t)L.Gl * d.m * L.Np * sizeof(float));
     L.wpart = take((size_t)L.Gl * L.S * d.n * d.m * sizeof(float));
@@ -633,6 +635,36 @@ int lista_resid(const ListaRun& r, int t, double* fpart) {
   return SLISTA_OK;
 }
 
+// The persistent kernels carry each 32-sample tile through every layer; they
+// apply when their LDS tile fits (and the per-layer family is not forced).
+bool use_lista_persist(const ListaRun& r) {
+  if (kernel_family() == 1 || r.N <= 0 || r.T <= 0) return false;
+  return slista::lista_persist_lds(r.prec, true, r.L.n_pad, r.L.m_pad) <= slista::kListaMaxLds &&
+         slista::lista_persist_lds(r.prec, false, r.L.n_pad, r.L.m_pad) <= slista::kListaMaxLds;
+}
+
+slista::ListaPersistArgs lista_persist_args(const ListaRun& r, float lam, const float* alpha, const float* beta) {
+  slista::ListaPersistArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.N = r.N;
+  a.n_pad = r.L.n_pad;
+  a.m_pad = r.L.m_pad;
+  a.T = r.T;
+  a.Xp = r.Xp();
+  a.Dr = r.ws + r.L.Dr;
+  a.DT = r.ws + r.L.DT;
+  a.Wr = r.ws + r.L.Wr;
+  a.WT = r.ws + r.L.WT;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.lam = lam;
+  a.zs = (float*)(r.ws + r.L.zs);
+  a.rs = (float*)(r.ws + r.L.rs);
+  a.tape = r.L.tape ? 1 : 0;
+  a.nwg = r.L.nwg;
+  return a;
+}
+
 int lista_check(const slista_dict* dict, int N, int T, float lambda, int prec) {
   if (!dict) return fail(SLISTA_EINVAL, "dict is NULL");
   if (N < 0 || N > kMaxN) return fail(SLISTA_EINVAL, "N=%d outside [0, %d]", N, kMaxN);
@@ -665,6 +697,18 @@ int lista_forward_run(const ListaRun& r, const float* X, float lam, const float*
   LAUNCH(kKOther, s, slista::launch_fill(r.z(0), (size_t)N * L.m_pad, 0.f, s));
   const bool want_f = F || loss;
   int st;
+  if (use_lista_persist(r)) {  // every layer, R^T and the objective partials in one launch
+    slista::ListaPersistArgs pa = lista_persist_args(r, lam, alpha, beta);
+    pa.fres = want_f ? r.fres() : nullptr;
+    pa.fl1 = want_f ? r.fl1() : nullptr;
+    LAUNCH(kKFwd, s, slista::launch_lista_persist(r.prec, true, pa, s));
+    LAUNCH(kKOther, s, slista::launch_copy_out(r.z(T), N, L.m_pad, d.m, Z, s));
+    if (want_f) {
+      LAUNCH(kKOther, s, slista::launch_lista_reduce_f(r.fres(), 1, r.fl1(), 1, N, F, r.Fd(), s));
+      if (loss) LAUNCH(kKOther, s, slista::launch_reduce_loss(r.Fd(), N, loss, s));
+    }
+    return SLISTA_OK;
+  }
   for (int t = 0; t < T; ++t) {
     if ((st = lista_resid(r, t, nullptr)) != SLISTA_OK) return st;
     slista::GemmArgs g = lista_args(r, r.r(t), L.n_pad, r.WT(t), L.n_pad, L.m_pad, r.z(t + 1));
@@ -710,7 +754,15 @@ int lista_backward_run(const ListaRun& r, float lam, const float* alpha, const f
   float* RT = (float*)(r.ws + L.RT);
   float* VT = (float*)(r.ws + L.VT);
   float* wpart = (float*)(r.ws + L.wpart);
-  for (int t = T - 1; t >= 0; --t) {
+  const bool persist = use_lista_persist(r);
+  if (persist) {  // all layers back in one launch; v^t kept for the weight gradient
+    slista::ListaPersistArgs pa = lista_persist_args(r, lam, alpha, nullptr);
+    pa.vs = r.v(0);
+    pa.dpa = dpa;
+    pa.dpb = dpb;
+    LAUNCH(kKBwd, s, slista::launch_lista_persist(r.prec, false, pa, s));
+  }
+  for (int t = persist ? -1 : T - 1; t >= 0; --t) {
     const float* v = r.v(t);
     {  // Q = V W_t^T, dalpha_t partials against R^t
       slista::GemmArgs g = lista_args(r, v, L.m_pad, r.Wr(t), L.m_pad, L.n_pad, q);
@@ -729,7 +781,8 @@ int lista_backward_run(const ListaRun& r, float lam, const float* alpha, const f
       LAUNCH(kKBwd, s, slista::launch_gemm(r.prec, slista::kEpiListaBwd, false, g, s));
     }
   }
-  LAUNCH(kKOther, s, slista::launch_lista_reduce_ab(dpa, L.Pa, dpb, L.Pb, T, lam, dalpha, dbeta, s));
+  LAUNCH(kKOther, s, slista::launch_lista_reduce_ab(dpa, persist ? L.nwg : L.Pa, dpb, persist ? L.nwg : L.Pb, T, lam,
+                                                    dalpha, dbeta, s));
   // dW_t = -alpha_t sum_i r_i v_i^T, Gl layers per launch: R^t and v^t
   // transposed to column-major copies, then a contraction over sample chunks
   for (int t0 = 0; dW && t0 < T; t0 += L.Gl) {

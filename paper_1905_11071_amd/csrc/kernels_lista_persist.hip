@@ -1,0 +1,395 @@
+// Persistent coupled-LISTA kernels (Section 4, Eq. (11)-(12)): one workgroup
+// carries RB = 32 samples through every layer, so the two contractions of a
+// layer run back to back on chip instead of as two launches with an HBM round
+// trip between them.
+//
+// Forward, layer t (factored form of Eq. (11)):
+//   phase A  r = z D^T - x          [RB x n_pad], K = m_pad   (A = z from LDS)
+//   phase B  z' = ST(z - a_t r W_t, lam b_t)  [RB x m_pad], K = n_pad  (A = r from LDS)
+// and one more phase A for R^T = D z^T - x (the objective and the backward seed).
+// Backward, layer t = T-1 .. 0 (v^{T-1} comes from the seed contraction):
+//   phase A' q = v W_t^T  (+ dalpha_t partial q . R^t)        K = m_pad
+//   phase B' v' = [z^t != 0] (v - a_t q D)  (+ dbeta_t partial v sign z^{t+1})  K = n_pad
+// with v' also written to the tape for the weight-gradient contraction.
+//
+// MFMA tiling: 4 waves; wave w owns the 16-column blocks w, w+4, ... of a
+// phase's output and both 16-row blocks. Per K step of 64 bytes each lane
+// reads 16 bytes of its A row from LDS and 16 bytes of its B row (a row of the
+// K-contiguous operand: D, D^T, W_t or W_t^T) from global memory, where the
+// operands stay L2-resident across the workgroups; FP32 issues four
+// v_mfma_f32_16x16x4_f32 per 16-byte pair, BF16 one v_mfma_f32_16x16x32_bf16.
+// Even and odd K steps go to separate accumulators (two more independent MFMA
+// chains), summed before the epilogue. LDS rows are padded by 16 bytes, which
+// spreads the 16 rows of a fragment read over distinct banks. B fragments are
+// loaded two K steps at a time, which keeps both kernels within 256 VGPRs:
+// two waves per SIMD (two workgroups per CU) hide each other's load latency.
+#include "common.hpp"
+#include "lista_persist.hpp"
+
+namespace slista {
+namespace {
+
+constexpr int RB = kListaRows;
+constexpr int NW = 4;
+constexpr int NT = 64 * NW;
+constexpr int G = 4;   // column blocks per wave and pass
+constexpr int U = 2;   // K steps whose B fragments are loaded together
+
+template <int P> struct LElem { static constexpr int bytes = 4; };
+template <> struct LElem<kBF16> { static constexpr int bytes = 2; };
+
+__device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
+
+__device__ __forceinline__ float soft_thresh(float u, float th) {
+  const float au = fabsf(u) - th;
+  return au > 0.f ? copysignf(au, u) : 0.f;
+}
+
+// Store one element into an operand tile in LDS (FP32, or BF16 rounded to nearest even).
+template <int P>
+__device__ __forceinline__ void put_op(char* tile, int rowb, int row, int col, float v) {
+  if constexpr (P == kF32)
+    *(float*)(tile + row * rowb + col * 4) = v;
+  else
+    *(uint16_t*)(tile + row * rowb + col * 2) = __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+
+template <int P>
+__device__ __forceinline__ f32x4 mma(const uint4& a, const uint4& b, f32x4 c) {
+  if constexpr (P == kF32) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+  } else {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                0, 0);
+  }
+  return c;
+}
+
+// acc[g][rb] = A[rb 16 .., 0..K) * B[cb_g 16 .., 0..K)^T for cb_g = cb0 + 4 g < ncb:
+// A in LDS (row stride arowb bytes), B in global memory (row stride browb
+// bytes), nk K steps of 64 bytes.
+template <int P>
+__device__ __forceinline__ void contract(const char* A, int arowb, const char* B, size_t browb, int nk, int cb0,
+                                         int ncb, f32x4 (&acc)[G][2], int lr, int lg) {
+  f32x4 odd[G][2];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      acc[g][rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      odd[g][rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  for (int k0 = 0; k0 < nk; k0 += U) {
+    uint4 bf[U][G];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int cb = cb0 + 4 * g;
+        bf[u][g] = (k0 + u < nk && cb < ncb)
+                       ? *(const uint4*)(B + (size_t)(cb * 16 + lr) * browb + (size_t)(k0 + u) * 64 + 16 * lg)
+                       : make_uint4(0, 0, 0, 0);
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (k0 + u >= nk) break;
+      uint4 af[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) af[rb] = *(const uint4*)(A + (rb * 16 + lr) * arowb + (k0 + u) * 64 + 16 * lg);
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (cb0 + 4 * g >= ncb) continue;  // wave-uniform: no MFMAs on an empty column block
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          if (u & 1)
+            odd[g][rb] = mma<P>(af[rb], bf[u][g], odd[g][rb]);
+          else
+            acc[g][rb] = mma<P>(af[rb], bf[u][g], acc[g][rb]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) acc[g][rb] += odd[g][rb];
+}
+
+// Sum of one double per (wave, row) over the 16 lanes of a row group, then
+// over the waves in a fixed order; returns the row sums to threads 0..RB-1.
+__device__ __forceinline__ double rows_sum(double (&part)[2][4], double* red, int wave, int lr, int lg, int tid) {
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) {
+      double v = part[rb][r4];
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
+      v += __shfl_xor(v, 4);
+      v += __shfl_xor(v, 8);
+      if (lr == 0) red[wave * RB + rb * 16 + 4 * lg + r4] = v;
+    }
+  __syncthreads();
+  double s = 0.0;
+  if (tid < RB) s = ((red[tid] + red[RB + tid]) + red[2 * RB + tid]) + red[3 * RB + tid];
+  __syncthreads();
+  return s;
+}
+
+template <int P>
+__global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  constexpr int E = LElem<P>::bytes;
+  const int n_pad = a.n_pad, m_pad = a.m_pad, N = a.N, T = a.T;
+  const int zrowb = m_pad * E + 16, rrowb = n_pad * E + 16;
+  char* zA = lds;                                         // z^t, operand precision
+  char* rA = zA + RB * zrowb;                             // r^t, operand precision
+  float* xs = (float*)(rA + RB * rrowb);                  // x, FP32
+  float* zM = xs + RB * n_pad;                            // z^t FP32 master (BF16 mode)
+  double* red = (double*)(zM + (P == kF32 ? 0 : RB * m_pad));  // [NW][RB]
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lg = lane >> 4;
+  const int row0 = blockIdx.x * RB;
+  for (int e = tid; e < RB * n_pad; e += NT) {
+    const int r = e / n_pad, c = e - r * n_pad;
+    xs[e] = row0 + r < N ? a.Xp[(size_t)(row0 + r) * n_pad + c] : 0.f;
+  }
+  for (int e = tid; e < RB * m_pad; e += NT) {
+    const int r = e / m_pad, c = e - r * m_pad;
+    put_op<P>(zA, zrowb, r, c, 0.f);
+    if constexpr (P != kF32) zM[e] = 0.f;
+  }
+  __syncthreads();
+
+  const int ncbA = n_pad / 16, ncbB = m_pad / 16;
+  const int nkA = m_pad * E / 64, nkB = n_pad * E / 64;
+  const size_t zslot = (size_t)N * m_pad, rslot = (size_t)N * n_pad;
+  for (int t = 0; t <= T; ++t) {
+    const bool last = t == T;
+    {  // phase A: r = z D^T - x
+      float* rout = a.tape ? a.rs + (size_t)t * rslot : (last ? a.rs : nullptr);
+      const bool want_f = last && a.fres;
+      double fr[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+      for (int c0 = wave; c0 < ncbA; c0 += 4 * G) {
+        f32x4 acc[G][2];
+        contract<P>(zA, zrowb, (const char*)a.Dr, (size_t)m_pad * E, nkA, c0, ncbA, acc, lr, lg);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int cb = c0 + 4 * g;
+          if (cb >= ncbA) continue;
+          const int col = cb * 16 + lr;
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+              const int row = rb * 16 + 4 * lg + r4;
+              const float r = acc[g][rb][r4] - xs[row * n_pad + col];
+              put_op<P>(rA, rrowb, row, col, r);
+              if (rout && row0 + row < N) rout[(size_t)(row0 + row) * n_pad + col] = r;
+              if (want_f) fr[rb][r4] += 0.5 * (double)r * (double)r;
+            }
+        }
+      }
+      if (want_f) {  // uniform
+        const double s = rows_sum(fr, red, wave, lr, lg, tid);
+        if (tid < RB && row0 + tid < N) a.fres[row0 + tid] = s;
+      }
+    }
+    if (last) break;
+    __syncthreads();  // r^t complete
+    {  // phase B: z^{t+1} = ST(z^t - a_t r W_t, lam b_t)
+      const float al = a.alpha[t], th = a.lam * a.beta[t];
+      const bool out = a.tape || t == T - 1;
+      float* zout = a.zs + (size_t)(a.tape ? t + 1 : ((t + 1) & 1)) * zslot;
+      const bool want_l1 = t == T - 1 && a.fl1;
+      double fl[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+      const char* Wt = (const char*)a.WT + (size_t)t * m_pad * n_pad * E;
+      for (int c0 = wave; c0 < ncbB; c0 += 4 * G) {
+        f32x4 acc[G][2];
+        contract<P>(rA, rrowb, Wt, (size_t)n_pad * E, nkB, c0, ncbB, acc, lr, lg);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int cb = c0 + 4 * g;
+          if (cb >= ncbB) continue;
+          const int col = cb * 16 + lr;
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+              const int row = rb * 16 + 4 * lg + r4;
+              float z;
+              if constexpr (P == kF32)
+                z = *(const float*)(zA + row * zrowb + col * 4);
+              else
+                z = zM[row * m_pad + col];
+              const float zn = soft_thresh(z - al * acc[g][rb][r4], th);
+              if constexpr (P != kF32) zM[row * m_pad + col] = zn;
+              put_op<P>(zA, zrowb, row, col, zn);
+              if (out && row0 + row < N) zout[(size_t)(row0 + row) * m_pad + col] = zn;
+              if (want_l1) fl[rb][r4] += (double)a.lam * fabs((double)zn);
+            }
+        }
+      }
+      if (want_l1) {
+        const double s = rows_sum(fl, red, wave, lr, lg, tid);
+        if (tid < RB && row0 + tid < N) a.fl1[row0 + tid] = s;
+      }
+    }
+    __syncthreads();  // z^{t+1} complete
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  constexpr int E = LElem<P>::bytes;
+  const int n_pad = a.n_pad, m_pad = a.m_pad, N = a.N, T = a.T;
+  const int vrowb = m_pad * E + 16, qrowb = n_pad * E + 16;
+  char* vA = lds;                                   // v^t, operand precision
+  char* qA = vA + RB * vrowb;                       // W_t v, operand precision
+  float* vM = (float*)(qA + RB * qrowb);            // v^t FP32 master (BF16 mode)
+  double* red = (double*)(vM + (P == kF32 ? 0 : RB * m_pad));  // [2][NW]
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lg = lane >> 4;
+  const int row0 = blockIdx.x * RB;
+  const size_t zslot = (size_t)N * m_pad, rslot = (size_t)N * n_pad;
+  {  // v^{T-1} from the seed
+    const float* v0 = a.vs + (size_t)(T - 1) * zslot;
+    for (int e = tid; e < RB * m_pad; e += NT) {
+      const int r = e / m_pad, c = e - r * m_pad;
+      const float v = row0 + r < N ? v0[(size_t)(row0 + r) * m_pad + c] : 0.f;
+      put_op<P>(vA, vrowb, r, c, v);
+      if constexpr (P != kF32) vM[e] = v;
+    }
+  }
+  __syncthreads();
+
+  const int ncbA = n_pad / 16, ncbB = m_pad / 16;
+  const int nkA = m_pad * E / 64, nkB = n_pad * E / 64;
+  for (int t = T - 1; t >= 0; --t) {
+    const float al = a.alpha[t];
+    double da = 0.0, db = 0.0;
+    {  // phase A': q = W_t v (rows: samples), dalpha_t partial q . R^t
+      const float* R = a.rs + (size_t)t * rslot;
+      const char* W = (const char*)a.Wr + (size_t)t * n_pad * m_pad * E;
+      for (int c0 = wave; c0 < ncbA; c0 += 4 * G) {
+        f32x4 acc[G][2];
+        contract<P>(vA, vrowb, W, (size_t)m_pad * E, nkA, c0, ncbA, acc, lr, lg);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int cb = c0 + 4 * g;
+          if (cb >= ncbA) continue;
+          const int col = cb * 16 + lr;
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+              const int row = rb * 16 + 4 * lg + r4;
+              const float q = acc[g][rb][r4];
+              put_op<P>(qA, qrowb, row, col, q);
+              if (row0 + row < N) da += (double)q * (double)R[(size_t)(row0 + row) * n_pad + col];
+            }
+        }
+      }
+    }
+    __syncthreads();  // q complete
+    {  // phase B': v^{t-1} = [z^t != 0] (v^t - a_t q D), dbeta_t partial v^t sign z^{t+1}
+      const float* Z0 = a.zs + (size_t)t * zslot;
+      const float* Z1 = a.zs + (size_t)(t + 1) * zslot;
+      float* vout = t >= 1 ? a.vs + (size_t)(t - 1) * zslot : nullptr;
+      for (int c0 = wave; c0 < ncbB; c0 += 4 * G) {
+        f32x4 acc[G][2];
+        contract<P>(qA, qrowb, (const char*)a.DT, (size_t)n_pad * E, nkB, c0, ncbB, acc, lr, lg);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int cb = c0 + 4 * g;
+          if (cb >= ncbB) continue;
+          const int col = cb * 16 + lr;
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+              const int row = rb * 16 + 4 * lg + r4;
+              float v;
+              if constexpr (P == kF32)
+                v = *(const float*)(vA + row * vrowb + col * 4);
+              else
+                v = vM[row * m_pad + col];
+              float vn = 0.f;
+              if (row0 + row < N) {
+                const size_t idx = (size_t)(row0 + row) * m_pad + col;
+                db += (double)v * (double)sgnf(Z1[idx]);
+                vn = Z0[idx] != 0.f ? v - al * acc[g][rb][r4] : 0.f;
+                if (vout) vout[idx] = vn;
+              }
+              if constexpr (P != kF32) vM[row * m_pad + col] = vn;
+              put_op<P>(vA, vrowb, row, col, vn);
+            }
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      da += __shfl_xor(da, o);
+      db += __shfl_xor(db, o);
+    }
+    if (lane == 0) {
+      red[wave] = da;
+      red[NW + wave] = db;
+    }
+    __syncthreads();  // v^{t-1} and the partials complete
+    if (tid == 0) {
+      a.dpa[(size_t)t * a.nwg + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+      a.dpb[(size_t)t * a.nwg + blockIdx.x] = ((red[NW] + red[NW + 1]) + red[NW + 2]) + red[NW + 3];
+    }
+  }
+}
+
+template <int P>
+size_t fwd_lds(int n_pad, int m_pad) {
+  constexpr int E = LElem<P>::bytes;
+  size_t b = (size_t)RB * (m_pad * E + 16) + (size_t)RB * (n_pad * E + 16) + (size_t)RB * n_pad * 4;
+  if (P != kF32) b += (size_t)RB * m_pad * 4;
+  return b + (size_t)NW * RB * sizeof(double);
+}
+
+template <int P>
+size_t bwd_lds(int n_pad, int m_pad) {
+  constexpr int E = LElem<P>::bytes;
+  size_t b = (size_t)RB * (m_pad * E + 16) + (size_t)RB * (n_pad * E + 16);
+  if (P != kF32) b += (size_t)RB * m_pad * 4;
+  return b + 2 * NW * sizeof(double);
+}
+
+template <int P>
+hipError_t launch_one(bool fwd, const ListaPersistArgs& a, hipStream_t s) {
+  const size_t lds = fwd ? fwd_lds<P>(a.n_pad, a.m_pad) : bwd_lds<P>(a.n_pad, a.m_pad);
+  const void* fn = fwd ? (const void*)lista_fwd_persist<P> : (const void*)lista_bwd_persist<P>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int grid = (a.N + RB - 1) / RB;
+  if (fwd)
+    hipLaunchKernelGGL(lista_fwd_persist<P>, dim3(grid), dim3(NT), lds, s, a);
+  else
+    hipLaunchKernelGGL(lista_bwd_persist<P>, dim3(grid), dim3(NT), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t lista_persist_lds(int prec, bool fwd, int n_pad, int m_pad) {
+  if (prec == kF32) return fwd ? fwd_lds<kF32>(n_pad, m_pad) : bwd_lds<kF32>(n_pad, m_pad);
+  return fwd ? fwd_lds<kBF16>(n_pad, m_pad) : bwd_lds<kBF16>(n_pad, m_pad);
+}
+
+hipError_t launch_lista_persist(int prec, bool fwd, const ListaPersistArgs& a, hipStream_t s) {
+  if (a.N <= 0 || a.T <= 0) return hipSuccess;
+  if (a.n_pad % 64 != 0 || a.m_pad % 64 != 0 || lista_persist_lds(prec, fwd, a.n_pad, a.m_pad) > kListaMaxLds)
+    return hipErrorInvalidValue;
+  return prec == kF32 ? launch_one<kF32>(fwd, a, s) : launch_one<kBF16>(fwd, a, s);
+}
+
+}  // namespace slista

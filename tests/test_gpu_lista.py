@@ -193,3 +193,28 @@ def test_lista_edge_cases(sl):
     with pytest.raises(sl.SlistaError):
         sl.lista_backward(d, pb.N, pb.lam, _gpu(a), _gpu(b), sl.lista_workspace(d, pb.N, 3, tape=True))
     d.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_lista_persistent_matches_per_layer(sl, prec):
+    """The persistent kernels (one workgroup carries 32 samples through every
+    layer) and the per-layer kernels compute the same network: same operand
+    rounding, different accumulation order."""
+    pb, W, a, b, *_ = _reference("gauss_64x256")
+    d = sl.Dictionary(_gpu(pb.D))
+    args = (d, _gpu(pb.X), pb.lam, _gpu(W), _gpu(a), _gpu(b))
+    try:
+        sl.set_kernel_family("layer")
+        ref = sl.lista_forward_backward(*args, prec=prec)
+        sl.set_kernel_family("persistent")
+        got = sl.lista_forward_backward(*args, prec=prec)
+    finally:
+        sl.set_kernel_family("auto")
+    torch.cuda.synchronize()
+    tol = 1e-5 if prec == "fp32" else 5e-2
+    for k, i in (("Z", 0), ("F", 1), ("dW", 3), ("dalpha", 4), ("dbeta", 5)):
+        r = ref[i].cpu().numpy().astype(np.float64)
+        err = _rel(got[i].cpu().numpy(), r)
+        _say(f"[{prec}] persistent vs per-layer {k}: rel {err:.2e}")
+        assert err <= tol, k
+    d.close()
