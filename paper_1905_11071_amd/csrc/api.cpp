@@ -511,18 +511,31 @@ int run_backward(const Run& r, float lam, const float* alpha, int prec, const fl
 // Factored form of Eq. (11): per layer R^t = Z^t D^T - X (contraction over
 // m_pad) then z^{t+1} = ST(z^t - alpha_t R^t W_t, lam beta_t) (contraction
 // over n_pad). The adjoint runs Q = V W_t^T, v' = [z^t != 0](v - alpha_t Q D)
-// and dW_t = -alpha_t (R^t)^T V, the last as a split contraction over the
-// samples on transposed copies of R^t and V (FP32 in both precisions).
-// Workspace: operand copies of D and of the W stack, the padded samples, the
-// iterates z^0..z^T and residuals R^0..R^T (tape) or two z and one R buffer,
-// objective partials and, with the tape, the adjoint buffers.
+// and dW_t = -alpha_t (R^t)^T V, the last as a split contraction over sample
+// chunks of chunk-major copies of R^t and V (FP32 in both precisions).
+//
+// Two kernel families. Persistent (default where the 32-sample tile fits in
+// LDS): one forward and one backward launch for all layers; the tape holds
+// R^t and v^t chunk-major and one code byte per element ([z^t != 0], sign
+// z^{t+1}). Per-layer: two fused contractions per layer and direction; the
+// tape holds z^0..z^T, R^0..R^T and v^0..v^{T-1} sample-major, transposed
+// per layer group for the weight gradient. Both keep the operand copies of D
+// and of the W stack and the padded samples.
 struct ListaLayout {
   int n_pad = 0, m_pad = 0, ctn = 0, ctm = 0, Pa = 0, Pb = 0, S = 1, Kc = 0, Np = 0, opb = 4, Gl = 1, nwg = 0;
-  bool tape = false;
+  bool tape = false, persist = false;
   size_t zbytes = 0, rbytes = 0;
   size_t Xp = 0, Dr = 0, DT = 0, Wr = 0, WT = 0, zs = 0, rs = 0, fres = 0, fl1 = 0, Fd = 0;
-  size_t vb = 0, q = 0, dpa = 0, dpb = 0, RT = 0, VT = 0, wpart = 0, total = 0;
+  size_t vb = 0, q = 0, dpa = 0, dpb = 0, RT = 0, VT = 0, wpart = 0, codes = 0, total = 0;
 };
+
+// The persistent kernels apply when their LDS tile fits and the per-layer
+// family is not forced.
+bool lista_persist_ok(int prec, int n_pad, int m_pad, int N, int T) {
+  if (kernel_family() == 1 || N <= 0 || T <= 0) return false;
+  return slista::lista_persist_lds(prec, true, n_pad, m_pad) <= slista::kListaMaxLds &&
+         slista::lista_persist_lds(prec, false, n_pad, m_pad) <= slista::kListaMaxLds;
+}
 
 ListaLayout lista_layout(const slista::Dict& d, int N, int T, int prec, bool tape) {
   ListaLayout L;
@@ -530,6 +543,7 @@ ListaLayout lista_layout(const slista::Dict& d, int N, int T, int prec, bool tap
   L.m_pad = d.m_pad;
   L.n_pad = (d.n + slista::kPadM - 1) / slista::kPadM * slista::kPadM;
   L.opb = prec == slista::kF32 ? 4 : 2;
+  L.persist = lista_persist_ok(prec, L.n_pad, L.m_pad, N, T);
   L.zbytes = (size_t)N * L.m_pad * sizeof(float);
   L.rbytes = (size_t)N * L.n_pad * sizeof(float);
   const int row_tiles = (N + kTileRows - 1) / kTileRows;
@@ -537,7 +551,7 @@ ListaLayout lista_layout(const slista::Dict& d, int N, int T, int prec, bool tap
   L.ctm = (L.m_pad + kTileCols - 1) / kTileCols;
   L.Pa = row_tiles * L.ctn;
   L.Pb = row_tiles * L.ctm;
-  L.nwg = (N + slista::kListaRows - 1) / slista::kListaRows;  // persistent kernels' workgroups
+  L.nwg = (N + slista::kListaRows - 1) / slista::kListaRows;
   // sample chunks of the weight-gradient contraction: enough workgroups to
   // fill the chip, at least ~256 samples (8 K steps) per chunk, Kc a
   // multiple of 64 (the transpose tile)
@@ -569,19 +583,36 @@ ListaLayout lista_layout(const slista::Dict& d, int N, int T, int prec, bool tap
   L.DT = take(dmat);
   L.Wr = take(dmat * (size_t)T);
   L.WT = take(dmat * (size_t)T);
-  L.zs = take(L.zbytes * (tape ? (size_t)T + 1 : 2));
-  L.rs = take(L.rbytes * (tape ? (size_t)T + 1 : 1));
-  L.fres = take((size_t)L.ctn * N * sizeof(double));
-  L.fl1 = take((size_t)L.ctm * N * sizeof(double));
-  L.Fd = take((size_t)N * sizeof(double));
-  if (tape) {
-    L.vb = take(((size_t)T + 1) * L.zbytes);  // v^t for every layer (slot T: the unused v^{-1})
-    L.q = take(L.rbytes);
-    L.dpa = take((size_t)T * std::max(L.Pa, L.nwg) * sizeof(double));
-    L.dpb = take((size_t)T * std::max(L.Pb, L.nwg) * sizeof(double));
-    L.RT = take((size_t)L.Gl * d.n * L.Np * sizeof(float));
-    L.VT = take((size_t)L.Gl * d.m * L.Np * sizeof(float));
-    L.wpart = take((size_t)L.Gl * L.S * d.n * d.m * sizeof(float));
+  if (L.persist) {
+    L.zs = take(L.zbytes);  // z^T
+    L.rs = take(L.rbytes);  // R^T
+    L.fres = take((size_t)N * sizeof(double));
+    L.fl1 = take((size_t)N * sizeof(double));
+    L.Fd = take((size_t)N * sizeof(double));
+    if (tape) {
+      L.RT = take((size_t)T * d.n * L.Np * sizeof(float));                       // R^t, chunk-major
+      L.codes = take((size_t)T * L.nwg * (slista::kListaRows / 4) * L.m_pad * 4);  // mask / sign codes
+      L.vb = take(L.zbytes);                                                     // v^{T-1} from the seed
+      L.VT = take((size_t)T * d.m * L.Np * sizeof(float));                       // v^t, chunk-major
+      L.dpa = take((size_t)T * L.nwg * sizeof(double));
+      L.dpb = take((size_t)T * L.nwg * sizeof(double));
+      L.wpart = take((size_t)L.Gl * L.S * d.n * d.m * sizeof(float));
+    }
+  } else {
+    L.zs = take(L.zbytes * (tape ? (size_t)T + 1 : 2));
+    L.rs = take(L.rbytes * (tape ? (size_t)T + 1 : 1));
+    L.fres = take((size_t)L.ctn * N * sizeof(double));
+    L.fl1 = take((size_t)L.ctm * N * sizeof(double));
+    L.Fd = take((size_t)N * sizeof(double));
+    if (tape) {
+      L.vb = take(((size_t)T + 1) * L.zbytes);  // v^t for every layer (slot T: the unused v^{-1})
+      L.q = take(L.rbytes);
+      L.dpa = take((size_t)T * L.Pa * sizeof(double));
+      L.dpb = take((size_t)T * L.Pb * sizeof(double));
+      L.RT = take((size_t)L.Gl * d.n * L.Np * sizeof(float));
+      L.VT = take((size_t)L.Gl * d.m * L.Np * sizeof(float));
+      L.wpart = take((size_t)L.Gl * L.S * d.n * d.m * sizeof(float));
+    }
   }
   L.total = off;
   return L;
@@ -593,18 +624,25 @@ struct ListaRun {
   char* ws;
   int N, T, prec;
   hipStream_t s;
+  // per-layer family: z^t, R^t and v^t slots
   float* z(int t) const {
     const int slot = L.tape ? t : (t & 1);
     return (float*)(ws + L.zs + (size_t)slot * L.zbytes);
   }
   float* r(int t) const { return (float*)(ws + L.rs + (size_t)(L.tape ? t : 0) * L.rbytes); }
   float* v(int t) const { return (float*)(ws + L.vb + (size_t)(t >= 0 ? t : T) * L.zbytes); }
+  // persistent family: z^T, R^T and the seed's v^{T-1}
+  float* zT() const { return (float*)(ws + L.zs); }
+  float* rT() const { return (float*)(ws + L.rs); }
+  float* vseed() const { return (float*)(ws + L.vb); }
   const void* Wr(int t) const { return ws + L.Wr + (size_t)t * L.n_pad * L.m_pad * L.opb; }
   const void* WT(int t) const { return ws + L.WT + (size_t)t * L.n_pad * L.m_pad * L.opb; }
   float* Xp() const { return (float*)(ws + L.Xp); }
   double* fres() const { return (double*)(ws + L.fres); }
   double* fl1() const { return (double*)(ws + L.fl1); }
   double* Fd() const { return (double*)(ws + L.Fd); }
+  float* RT() const { return (float*)(ws + L.RT); }
+  float* VT() const { return (float*)(ws + L.VT); }
 };
 
 // Contraction with N sample rows: A [N][lda] times the K-contiguous operand Bt.
@@ -635,21 +673,17 @@ int lista_resid(const ListaRun& r, int t, double* fpart) {
   return SLISTA_OK;
 }
 
-// The persistent kernels carry each 32-sample tile through every layer; they
-// apply when their LDS tile fits (and the per-layer family is not forced).
-bool use_lista_persist(const ListaRun& r) {
-  if (kernel_family() == 1 || r.N <= 0 || r.T <= 0) return false;
-  return slista::lista_persist_lds(r.prec, true, r.L.n_pad, r.L.m_pad) <= slista::kListaMaxLds &&
-         slista::lista_persist_lds(r.prec, false, r.L.n_pad, r.L.m_pad) <= slista::kListaMaxLds;
-}
-
 slista::ListaPersistArgs lista_persist_args(const ListaRun& r, float lam, const float* alpha, const float* beta) {
   slista::ListaPersistArgs a;
   std::memset(&a, 0, sizeof a);
   a.N = r.N;
+  a.n = r.d->n;
+  a.m = r.d->m;
   a.n_pad = r.L.n_pad;
   a.m_pad = r.L.m_pad;
   a.T = r.T;
+  a.Kc = r.L.Kc;
+  a.Np = r.L.Np;
   a.Xp = r.Xp();
   a.Dr = r.ws + r.L.Dr;
   a.DT = r.ws + r.L.DT;
@@ -658,10 +692,15 @@ slista::ListaPersistArgs lista_persist_args(const ListaRun& r, float lam, const 
   a.alpha = alpha;
   a.beta = beta;
   a.lam = lam;
-  a.zs = (float*)(r.ws + r.L.zs);
-  a.rs = (float*)(r.ws + r.L.rs);
-  a.tape = r.L.tape ? 1 : 0;
   a.nwg = r.L.nwg;
+  if (r.L.tape) {
+    a.rtape = r.RT();
+    a.codes = (uint32_t*)(r.ws + r.L.codes);
+    a.vseed = r.vseed();
+    a.vtape = r.VT();
+    a.dpa = (double*)(r.ws + r.L.dpa);
+    a.dpb = (double*)(r.ws + r.L.dpb);
+  }
   return a;
 }
 
@@ -694,21 +733,25 @@ int lista_forward_run(const ListaRun& r, const float* X, float lam, const float*
     LAUNCH(kKOther, s, slista::launch_lista_pack(W, T, d.n, d.m, d.m, (size_t)d.n * d.m, 0, L.n_pad, L.m_pad, r.prec,
                                                  r.ws + L.Wr, r.ws + L.WT, s));
   LAUNCH(kKOther, s, slista::launch_pad_rows(X, N, d.n, L.n_pad, r.Xp(), s));
-  LAUNCH(kKOther, s, slista::launch_fill(r.z(0), (size_t)N * L.m_pad, 0.f, s));
   const bool want_f = F || loss;
   int st;
-  if (use_lista_persist(r)) {  // every layer, R^T and the objective partials in one launch
+  if (L.persist) {  // every layer, R^T and the objective partials in one launch
     slista::ListaPersistArgs pa = lista_persist_args(r, lam, alpha, beta);
+    pa.zT = r.zT();
+    pa.rT = (want_f || L.tape) ? r.rT() : nullptr;
     pa.fres = want_f ? r.fres() : nullptr;
     pa.fl1 = want_f ? r.fl1() : nullptr;
+    if (L.tape)  // chunk rows past the last workgroup's tile stay zero
+      LAUNCH(kKOther, s, slista::launch_zero_tape_rows(r.RT(), T, d.n, L.Kc, L.Np, L.nwg * slista::kListaRows, s));
     LAUNCH(kKFwd, s, slista::launch_lista_persist(r.prec, true, pa, s));
-    LAUNCH(kKOther, s, slista::launch_copy_out(r.z(T), N, L.m_pad, d.m, Z, s));
+    LAUNCH(kKOther, s, slista::launch_copy_out(r.zT(), N, L.m_pad, d.m, Z, s));
     if (want_f) {
       LAUNCH(kKOther, s, slista::launch_lista_reduce_f(r.fres(), 1, r.fl1(), 1, N, F, r.Fd(), s));
       if (loss) LAUNCH(kKOther, s, slista::launch_reduce_loss(r.Fd(), N, loss, s));
     }
     return SLISTA_OK;
   }
+  LAUNCH(kKOther, s, slista::launch_fill(r.z(0), (size_t)N * L.m_pad, 0.f, s));
   for (int t = 0; t < T; ++t) {
     if ((st = lista_resid(r, t, nullptr)) != SLISTA_OK) return st;
     slista::GemmArgs g = lista_args(r, r.r(t), L.n_pad, r.WT(t), L.n_pad, L.m_pad, r.z(t + 1));
@@ -731,6 +774,35 @@ int lista_forward_run(const ListaRun& r, const float* X, float lam, const float*
   return SLISTA_OK;
 }
 
+// dW_t = -alpha_t sum_i r_i v_i^T for g layers t0.. whose R^t and v^t are
+// chunk-major at RT and VT ([g][Np / Kc][n or m][Kc]).
+int lista_dw_group(const ListaRun& r, const float* RT, const float* VT, int g, const float* alpha, float* dW) {
+  const slista::Dict& d = *r.d;
+  const ListaLayout& L = r.L;
+  slista::GemmArgs gw;
+  std::memset(&gw, 0, sizeof gw);
+  gw.A = RT;  // chunk s of layer b: [n][Kc] at RT + b n Np + s n Kc
+  gw.lda = L.Kc;
+  gw.Bt = VT;
+  gw.ldb = L.Kc;
+  gw.K = L.Kc;
+  gw.rows = d.n;
+  gw.ncols = d.m;
+  gw.ldz = d.m;
+  gw.Out = (float*)(r.ws + L.wpart);
+  gw.ksplit = L.S;
+  gw.nbatch = g;
+  gw.a_split = (size_t)d.n * L.Kc;
+  gw.b_split = (size_t)d.m * L.Kc;
+  gw.a_batch = (size_t)d.n * L.Np;
+  gw.b_batch = (size_t)d.m * L.Np;
+  gw.out_split = (size_t)d.n * d.m;
+  slista::gemm_grid(d.n, d.m, gw);
+  LAUNCH(kKBwd, r.s, slista::launch_gemm(slista::kF32, slista::kEpiSplit, false, gw, r.s));
+  LAUNCH(kKOther, r.s, slista::launch_lista_reduce_w(gw.Out, L.S, (size_t)d.n * d.m, alpha, g, dW, r.s));
+  return SLISTA_OK;
+}
+
 int lista_backward_run(const ListaRun& r, float lam, const float* alpha, const float* dZ, const float* dF,
                        float dF_scalar, float* dW, float* dalpha, float* dbeta) {
   const slista::Dict& d = *r.d;
@@ -739,8 +811,9 @@ int lista_backward_run(const ListaRun& r, float lam, const float* alpha, const f
   hipStream_t s = r.s;
   if (T == 0) return SLISTA_OK;
   {  // seed v^{T-1} = [z^T != 0] (dF D^T R^T + dF lam sign z^T + dZ)
-    slista::GemmArgs g = lista_args(r, r.r(T), L.n_pad, r.ws + L.DT, L.n_pad, L.m_pad, r.v(T - 1));
-    g.Zt = r.z(T);
+    float* vs = L.persist ? r.vseed() : r.v(T - 1);
+    slista::GemmArgs g = lista_args(r, L.persist ? r.rT() : r.r(T), L.n_pad, r.ws + L.DT, L.n_pad, L.m_pad, vs);
+    g.Zt = L.persist ? r.zT() : r.z(T);
     g.C = nullptr;
     g.dF = dF;
     g.dF_scalar = dF_scalar;
@@ -750,19 +823,22 @@ int lista_backward_run(const ListaRun& r, float lam, const float* alpha, const f
   }
   double* dpa = (double*)(r.ws + L.dpa);
   double* dpb = (double*)(r.ws + L.dpb);
-  float* q = (float*)(r.ws + L.q);
-  float* RT = (float*)(r.ws + L.RT);
-  float* VT = (float*)(r.ws + L.VT);
-  float* wpart = (float*)(r.ws + L.wpart);
-  const bool persist = use_lista_persist(r);
-  if (persist) {  // all layers back in one launch; v^t kept for the weight gradient
+  int st;
+  if (L.persist) {  // all layers back in one launch; R^t and v^t chunk-major on the tape
     slista::ListaPersistArgs pa = lista_persist_args(r, lam, alpha, nullptr);
-    pa.vs = r.v(0);
-    pa.dpa = dpa;
-    pa.dpb = dpb;
+    LAUNCH(kKOther, s, slista::launch_zero_tape_rows(r.VT(), T, d.m, L.Kc, L.Np, L.nwg * slista::kListaRows, s));
     LAUNCH(kKBwd, s, slista::launch_lista_persist(r.prec, false, pa, s));
+    LAUNCH(kKOther, s, slista::launch_lista_reduce_ab(dpa, L.nwg, dpb, L.nwg, T, lam, dalpha, dbeta, s));
+    for (int t0 = 0; dW && t0 < T; t0 += L.Gl) {
+      const int g = T - t0 < L.Gl ? T - t0 : L.Gl;
+      if ((st = lista_dw_group(r, r.RT() + (size_t)t0 * d.n * L.Np, r.VT() + (size_t)t0 * d.m * L.Np, g,
+                               alpha + t0, dW + (size_t)t0 * d.n * d.m)) != SLISTA_OK)
+        return st;
+    }
+    return SLISTA_OK;
   }
-  for (int t = persist ? -1 : T - 1; t >= 0; --t) {
+  float* q = (float*)(r.ws + L.q);
+  for (int t = T - 1; t >= 0; --t) {
     const float* v = r.v(t);
     {  // Q = V W_t^T, dalpha_t partials against R^t
       slista::GemmArgs g = lista_args(r, v, L.m_pad, r.Wr(t), L.m_pad, L.n_pad, q);
@@ -781,38 +857,15 @@ int lista_backward_run(const ListaRun& r, float lam, const float* alpha, const f
       LAUNCH(kKBwd, s, slista::launch_gemm(r.prec, slista::kEpiListaBwd, false, g, s));
     }
   }
-  LAUNCH(kKOther, s, slista::launch_lista_reduce_ab(dpa, persist ? L.nwg : L.Pa, dpb, persist ? L.nwg : L.Pb, T, lam,
-                                                    dalpha, dbeta, s));
-  // dW_t = -alpha_t sum_i r_i v_i^T, Gl layers per launch: R^t and v^t
-  // transposed to column-major copies, then a contraction over sample chunks
+  LAUNCH(kKOther, s, slista::launch_lista_reduce_ab(dpa, L.Pa, dpb, L.Pb, T, lam, dalpha, dbeta, s));
+  // dW in layer groups: R^t and v^t transposed to chunk-major copies first
   for (int t0 = 0; dW && t0 < T; t0 += L.Gl) {
     const int g = T - t0 < L.Gl ? T - t0 : L.Gl;
-    LAUNCH(kKOther, s, slista::launch_transpose_pad(r.r(t0), N, L.n_pad, d.n, L.Np, L.Kc, RT, g,
+    LAUNCH(kKOther, s, slista::launch_transpose_pad(r.r(t0), N, L.n_pad, d.n, L.Np, L.Kc, r.RT(), g,
                                                     L.rbytes / sizeof(float), (size_t)d.n * L.Np, s));
-    LAUNCH(kKOther, s, slista::launch_transpose_pad(r.v(t0), N, L.m_pad, d.m, L.Np, L.Kc, VT, g,
+    LAUNCH(kKOther, s, slista::launch_transpose_pad(r.v(t0), N, L.m_pad, d.m, L.Np, L.Kc, r.VT(), g,
                                                     L.zbytes / sizeof(float), (size_t)d.m * L.Np, s));
-    slista::GemmArgs gw;
-    std::memset(&gw, 0, sizeof gw);
-    gw.A = RT;  // chunk s of layer b: [n][Kc] at RT + b n Np + s n Kc
-    gw.lda = L.Kc;
-    gw.Bt = VT;
-    gw.ldb = L.Kc;
-    gw.K = L.Kc;
-    gw.rows = d.n;
-    gw.ncols = d.m;
-    gw.ldz = d.m;
-    gw.Out = wpart;
-    gw.ksplit = L.S;
-    gw.nbatch = g;
-    gw.a_split = (size_t)d.n * L.Kc;
-    gw.b_split = (size_t)d.m * L.Kc;
-    gw.a_batch = (size_t)d.n * L.Np;
-    gw.b_batch = (size_t)d.m * L.Np;
-    gw.out_split = (size_t)d.n * d.m;
-    slista::gemm_grid(d.n, d.m, gw);
-    LAUNCH(kKBwd, s, slista::launch_gemm(slista::kF32, slista::kEpiSplit, false, gw, s));
-    LAUNCH(kKOther, s, slista::launch_lista_reduce_w(wpart, L.S, (size_t)d.n * d.m, alpha + t0, g,
-                                                     dW + (size_t)t0 * d.n * d.m, s));
+    if ((st = lista_dw_group(r, r.RT(), r.VT(), g, alpha + t0, dW + (size_t)t0 * d.n * d.m)) != SLISTA_OK) return st;
   }
   return SLISTA_OK;
 }

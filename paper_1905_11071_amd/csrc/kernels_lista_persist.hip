@@ -10,7 +10,11 @@
 // Backward, layer t = T-1 .. 0 (v^{T-1} comes from the seed contraction):
 //   phase A' q = v W_t^T  (+ dalpha_t partial q . R^t)        K = m_pad
 //   phase B' v' = [z^t != 0] (v - a_t q D)  (+ dbeta_t partial v sign z^{t+1})  K = n_pad
-// with v' also written to the tape for the weight-gradient contraction.
+// The forward leaves per layer R^t (chunk-major, the layout the weight-gradient
+// contraction reads) and one byte per element coding [z^t != 0] and sign z^{t+1},
+// four rows to a 32-bit word in the MFMA accumulator order, so each lane's
+// epilogue reads one word per four elements; the backward writes v' in the
+// same chunk-major layout as R^t.
 //
 // MFMA tiling: 4 waves; wave w owns the 16-column blocks w, w+4, ... of a
 // phase's output and both 16-row blocks. Per K step of 64 bytes each lane
@@ -143,7 +147,7 @@ template <int P>
 __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   constexpr int E = LElem<P>::bytes;
-  const int n_pad = a.n_pad, m_pad = a.m_pad, N = a.N, T = a.T;
+  const int n_pad = a.n_pad, m_pad = a.m_pad, N = a.N, T = a.T, Kc = a.Kc;
   const int zrowb = m_pad * E + 16, rrowb = n_pad * E + 16;
   char* zA = lds;                                         // z^t, operand precision
   char* rA = zA + RB * zrowb;                             // r^t, operand precision
@@ -166,11 +170,12 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
 
   const int ncbA = n_pad / 16, ncbB = m_pad / 16;
   const int nkA = m_pad * E / 64, nkB = n_pad * E / 64;
-  const size_t zslot = (size_t)N * m_pad, rslot = (size_t)N * n_pad;
+  const size_t rlayer = (size_t)a.n * a.Np, clayer = (size_t)a.nwg * (RB / 4) * m_pad;
   for (int t = 0; t <= T; ++t) {
     const bool last = t == T;
     {  // phase A: r = z D^T - x
-      float* rout = a.tape ? a.rs + (size_t)t * rslot : (last ? a.rs : nullptr);
+      float* rtape = (!last && a.rtape) ? a.rtape + (size_t)t * rlayer : nullptr;
+      float* rT = last ? a.rT : nullptr;
       const bool want_f = last && a.fres;
       double fr[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
       for (int c0 = wave; c0 < ncbA; c0 += 4 * G) {
@@ -182,15 +187,23 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
           if (cb >= ncbA) continue;
           const int col = cb * 16 + lr;
 #pragma unroll
-          for (int rb = 0; rb < 2; ++rb)
+          for (int rb = 0; rb < 2; ++rb) {
+            float rv[4];
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
               const int row = rb * 16 + 4 * lg + r4;
               const float r = acc[g][rb][r4] - xs[row * n_pad + col];
+              rv[r4] = r;
               put_op<P>(rA, rrowb, row, col, r);
-              if (rout && row0 + row < N) rout[(size_t)(row0 + row) * n_pad + col] = r;
+              if (rT && row0 + row < N) rT[(size_t)(row0 + row) * n_pad + col] = r;
               if (want_f) fr[rb][r4] += 0.5 * (double)r * (double)r;
             }
+            if (rtape && col < a.n) {  // 4 consecutive samples of one chunk (rows >= N hold 0)
+              const int i = row0 + rb * 16 + 4 * lg;
+              *(float4*)(rtape + (size_t)(i / Kc) * a.n * Kc + (size_t)col * Kc + i % Kc) =
+                  make_float4(rv[0], rv[1], rv[2], rv[3]);
+            }
+          }
         }
       }
       if (want_f) {  // uniform
@@ -202,8 +215,8 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
     __syncthreads();  // r^t complete
     {  // phase B: z^{t+1} = ST(z^t - a_t r W_t, lam b_t)
       const float al = a.alpha[t], th = a.lam * a.beta[t];
-      const bool out = a.tape || t == T - 1;
-      float* zout = a.zs + (size_t)(a.tape ? t + 1 : ((t + 1) & 1)) * zslot;
+      float* zT = t == T - 1 ? a.zT : nullptr;
+      uint32_t* codes = a.codes ? a.codes + (size_t)t * clayer : nullptr;
       const bool want_l1 = t == T - 1 && a.fl1;
       double fl[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
       const char* Wt = (const char*)a.WT + (size_t)t * m_pad * n_pad * E;
@@ -216,7 +229,8 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
           if (cb >= ncbB) continue;
           const int col = cb * 16 + lr;
 #pragma unroll
-          for (int rb = 0; rb < 2; ++rb)
+          for (int rb = 0; rb < 2; ++rb) {
+            uint32_t word = 0;
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
               const int row = rb * 16 + 4 * lg + r4;
@@ -228,9 +242,12 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
               const float zn = soft_thresh(z - al * acc[g][rb][r4], th);
               if constexpr (P != kF32) zM[row * m_pad + col] = zn;
               put_op<P>(zA, zrowb, row, col, zn);
-              if (out && row0 + row < N) zout[(size_t)(row0 + row) * m_pad + col] = zn;
+              word |= (uint32_t)((z != 0.f ? 1u : 0u) | (zn > 0.f ? 2u : 0u) | (zn < 0.f ? 4u : 0u)) << (8 * r4);
+              if (zT && row0 + row < N) zT[(size_t)(row0 + row) * m_pad + col] = zn;
               if (want_l1) fl[rb][r4] += (double)a.lam * fabs((double)zn);
             }
+            if (codes) codes[(size_t)((row0 + rb * 16) / 4 + lg) * m_pad + col] = word;
+          }
         }
       }
       if (want_l1) {
@@ -246,7 +263,7 @@ template <int P>
 __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   constexpr int E = LElem<P>::bytes;
-  const int n_pad = a.n_pad, m_pad = a.m_pad, N = a.N, T = a.T;
+  const int n_pad = a.n_pad, m_pad = a.m_pad, N = a.N, T = a.T, Kc = a.Kc;
   const int vrowb = m_pad * E + 16, qrowb = n_pad * E + 16;
   char* vA = lds;                                   // v^t, operand precision
   char* qA = vA + RB * vrowb;                       // W_t v, operand precision
@@ -255,14 +272,20 @@ __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lg = lane >> 4;
   const int row0 = blockIdx.x * RB;
-  const size_t zslot = (size_t)N * m_pad, rslot = (size_t)N * n_pad;
-  {  // v^{T-1} from the seed
-    const float* v0 = a.vs + (size_t)(T - 1) * zslot;
+  const size_t rlayer = (size_t)a.n * a.Np, vlayer = (size_t)a.m * a.Np;
+  const size_t clayer = (size_t)a.nwg * (RB / 4) * m_pad;
+  {  // v^{T-1} from the seed, into LDS and (chunk-major) onto the tape
     for (int e = tid; e < RB * m_pad; e += NT) {
       const int r = e / m_pad, c = e - r * m_pad;
-      const float v = row0 + r < N ? v0[(size_t)(row0 + r) * m_pad + c] : 0.f;
+      const float v = row0 + r < N ? a.vseed[(size_t)(row0 + r) * m_pad + c] : 0.f;
       put_op<P>(vA, vrowb, r, c, v);
       if constexpr (P != kF32) vM[e] = v;
+    }
+    float* vt = a.vtape + (size_t)(T - 1) * vlayer;
+    for (int e = tid; e < RB * a.m; e += NT) {
+      const int c = e / RB, r = e - c * RB, i = row0 + r;
+      vt[(size_t)(i / Kc) * a.m * Kc + (size_t)c * Kc + i % Kc] =
+          i < N ? a.vseed[(size_t)i * m_pad + c] : 0.f;
     }
   }
   __syncthreads();
@@ -273,7 +296,7 @@ __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
     const float al = a.alpha[t];
     double da = 0.0, db = 0.0;
     {  // phase A': q = W_t v (rows: samples), dalpha_t partial q . R^t
-      const float* R = a.rs + (size_t)t * rslot;
+      const float* R = a.rtape + (size_t)t * rlayer;
       const char* W = (const char*)a.Wr + (size_t)t * n_pad * m_pad * E;
       for (int c0 = wave; c0 < ncbA; c0 += 4 * G) {
         f32x4 acc[G][2];
@@ -284,23 +307,37 @@ __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
           if (cb >= ncbA) continue;
           const int col = cb * 16 + lr;
 #pragma unroll
-          for (int rb = 0; rb < 2; ++rb)
+          for (int rb = 0; rb < 2; ++rb) {
+            float4 rv = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (col < a.n) {  // R^t of 4 consecutive samples (0 for rows >= N)
+              const int i = row0 + rb * 16 + 4 * lg;
+              rv = *(const float4*)(R + (size_t)(i / Kc) * a.n * Kc + (size_t)col * Kc + i % Kc);
+            }
+            const float rr[4] = {rv.x, rv.y, rv.z, rv.w};
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
               const int row = rb * 16 + 4 * lg + r4;
               const float q = acc[g][rb][r4];
               put_op<P>(qA, qrowb, row, col, q);
-              if (row0 + row < N) da += (double)q * (double)R[(size_t)(row0 + row) * n_pad + col];
+              da += (double)q * (double)rr[r4];
             }
+          }
         }
       }
     }
     __syncthreads();  // q complete
     {  // phase B': v^{t-1} = [z^t != 0] (v^t - a_t q D), dbeta_t partial v^t sign z^{t+1}
-      const float* Z0 = a.zs + (size_t)t * zslot;
-      const float* Z1 = a.zs + (size_t)(t + 1) * zslot;
-      float* vout = t >= 1 ? a.vs + (size_t)(t - 1) * zslot : nullptr;
+      const uint32_t* codes = a.codes + (size_t)t * clayer;
+      float* vt = t >= 1 ? a.vtape + (size_t)(t - 1) * vlayer : nullptr;
       for (int c0 = wave; c0 < ncbB; c0 += 4 * G) {
+        uint32_t cw[G][2];  // issued before the contraction, consumed by the epilogue
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb) {
+            const int cb = c0 + 4 * g;
+            cw[g][rb] = cb < ncbB ? codes[(size_t)((row0 + rb * 16) / 4 + lg) * m_pad + cb * 16 + lr] : 0u;
+          }
         f32x4 acc[G][2];
         contract<P>(qA, qrowb, (const char*)a.DT, (size_t)n_pad * E, nkB, c0, ncbB, acc, lr, lg);
 #pragma unroll
@@ -309,7 +346,8 @@ __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
           if (cb >= ncbB) continue;
           const int col = cb * 16 + lr;
 #pragma unroll
-          for (int rb = 0; rb < 2; ++rb)
+          for (int rb = 0; rb < 2; ++rb) {
+            float vv[4];
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
               const int row = rb * 16 + 4 * lg + r4;
@@ -318,16 +356,20 @@ __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
                 v = *(const float*)(vA + row * vrowb + col * 4);
               else
                 v = vM[row * m_pad + col];
-              float vn = 0.f;
-              if (row0 + row < N) {
-                const size_t idx = (size_t)(row0 + row) * m_pad + col;
-                db += (double)v * (double)sgnf(Z1[idx]);
-                vn = Z0[idx] != 0.f ? v - al * acc[g][rb][r4] : 0.f;
-                if (vout) vout[idx] = vn;
-              }
+              const uint32_t code = cw[g][rb] >> (8 * r4);
+              const float sg = (code & 2u) ? 1.f : ((code & 4u) ? -1.f : 0.f);
+              db += (double)v * (double)sg;
+              const float vn = (code & 1u) ? v - al * acc[g][rb][r4] : 0.f;
+              vv[r4] = vn;
               if constexpr (P != kF32) vM[row * m_pad + col] = vn;
               put_op<P>(vA, vrowb, row, col, vn);
             }
+            if (vt && col < a.m) {
+              const int i = row0 + rb * 16 + 4 * lg;
+              *(float4*)(vt + (size_t)(i / Kc) * a.m * Kc + (size_t)col * Kc + i % Kc) =
+                  make_float4(vv[0], vv[1], vv[2], vv[3]);
+            }
+          }
         }
       }
     }
@@ -345,6 +387,17 @@ __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
       a.dpa[(size_t)t * a.nwg + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
       a.dpb[(size_t)t * a.nwg + blockIdx.x] = ((red[NW] + red[NW + 1]) + red[NW + 2]) + red[NW + 3];
     }
+  }
+}
+
+// Zero rows i0 .. Np-1 of every layer and column of a chunk-major tape.
+__global__ void k_zero_tape_rows(float* __restrict__ tape, int cols, int Kc, int Np, int i0, size_t total) {
+  const int span = Np - i0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t lc = e / span;
+    const int i = i0 + (int)(e - lc * span);
+    const size_t layer = lc / cols, c = lc - layer * cols;
+    tape[layer * cols * Np + (size_t)(i / Kc) * cols * Kc + c * Kc + i % Kc] = 0.f;
   }
 }
 
@@ -387,9 +440,20 @@ size_t lista_persist_lds(int prec, bool fwd, int n_pad, int m_pad) {
 
 hipError_t launch_lista_persist(int prec, bool fwd, const ListaPersistArgs& a, hipStream_t s) {
   if (a.N <= 0 || a.T <= 0) return hipSuccess;
-  if (a.n_pad % 64 != 0 || a.m_pad % 64 != 0 || lista_persist_lds(prec, fwd, a.n_pad, a.m_pad) > kListaMaxLds)
+  if (a.n_pad % 64 != 0 || a.m_pad % 64 != 0 || a.Kc <= 0 || a.Kc % 64 != 0 || a.Np % a.Kc != 0 ||
+      a.Np < a.nwg * RB || a.nwg != (a.N + RB - 1) / RB || lista_persist_lds(prec, fwd, a.n_pad, a.m_pad) > kListaMaxLds)
     return hipErrorInvalidValue;
+  if (!fwd && (!a.rtape || !a.codes || !a.vseed || !a.vtape || !a.dpa || !a.dpb)) return hipErrorInvalidValue;
   return prec == kF32 ? launch_one<kF32>(fwd, a, s) : launch_one<kBF16>(fwd, a, s);
+}
+
+hipError_t launch_zero_tape_rows(float* tape, int layers, int cols, int Kc, int Np, int i0, hipStream_t s) {
+  if (layers <= 0 || cols <= 0 || i0 >= Np) return hipSuccess;
+  const size_t total = (size_t)layers * cols * (Np - i0);
+  size_t blocks = (total + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_zero_tape_rows, dim3((unsigned)blocks), dim3(256), 0, s, tape, cols, Kc, Np, i0, total);
+  return hipGetLastError();
 }
 
 }  // namespace slista
