@@ -318,7 +318,11 @@ SLISTA_API int slista_oista(const slista_dict* dict, const float* X, int N, floa
  * Computed in the factored form: per layer the residual R = Z D^T - X (a
  * contraction over m) and R W_t (over n), both on MFMA in the given
  * precision, with the soft-threshold and the objective partials fused into
- * their epilogues. Per-layer kernels.
+ * their epilogues. Where a 32-sample tile fits in LDS (n_pad, m_pad up to a
+ * few hundred) persistent kernels carry each tile through all layers in one
+ * launch per direction; otherwise, or with SLISTA_OPT_KERNEL_FAMILY = 1, one
+ * launch per contraction. The two families keep different tapes in ws, so a
+ * backward call must see the family of its forward call.
  *
  *   W      device FP32 [T, n, m] (row-major per layer; W_t has D's shape).
  *   alpha, beta  device FP32 [T] (alpha_t, beta_t > 0 is a precondition).
@@ -339,7 +343,8 @@ SLISTA_API int slista_oista(const slista_dict* dict, const float* X, int N, floa
  * 0 in the sub-gradient of |z|. The weight gradient dW_t = -alpha_t sum_i
  * r_i v_i^T is a sum over the samples, computed with FP32 operands in both
  * precisions. Precondition: ws holds the tape of a slista_lista_forward call
- * with tape != 0 and the same dict, N, lambda, W, alpha, beta, T and prec.
+ * with tape != 0 and the same dict, N, lambda, W, alpha, beta, T, prec and
+ * kernel family.
  * slista_lista_forward_backward does both for the mean loss (dF_i = 1/N).
  *
  * Errors: SLISTA_EINVAL for a NULL dict or required pointer, N or T out of
