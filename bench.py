@@ -51,7 +51,7 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "548e5b7ab54e181c034f3473af0a27397449d5ed1bf8ef494533054e10135352",
+    "sources_sha256": "769722cf3e2d3691dd56c8fc19a42bab775dbde7c9c384f80bbff67a2639a6c9",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {
