@@ -218,3 +218,36 @@ def test_lista_persistent_matches_per_layer(sl, prec):
         _say(f"[{prec}] persistent vs per-layer {k}: rel {err:.2e}")
         assert err <= tol, k
     d.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("shape", [(100, 600, 300, 5), (64, 1500, 200, 3)])
+def test_lista_wide_dictionaries(sl, shape, prec):
+    """100 x 600 (n_pad 128, m_pad 640): the persistent kernels with several
+    column-block groups per wave and a partial last group; 64 x 1500 (m_pad
+    1536): the tile exceeds LDS and the per-layer kernels take over. Both
+    against the oracle."""
+    n, m, N, T = shape
+    pb = synth.make_problem(n, m, N, 0.05, 0.01, 0.1, seed=1307 + m)
+    W, a, b = _params(pb, T, 5, 0.2)
+    Zo, Fo, dWo, dao, dbo = oracle.lista_forward_backward(pb.D, pb.X, pb.lam, W, a, b, dF=np.full(N, 1.0 / N))
+    d = sl.Dictionary(_gpu(pb.D))
+    Z, F, loss, dW, da, db, _ = sl.lista_forward_backward(d, _gpu(pb.X), pb.lam, _gpu(W), _gpu(a), _gpu(b),
+                                                          prec=prec)
+    torch.cuda.synchronize()
+    lo = float(np.mean(Fo[-1]))
+    lerr = abs(loss.item() - lo) / lo
+    errs = {k: _rel(v.cpu().numpy(), r) for k, v, r in (("Z", Z, Zo), ("dW", dW, dWo), ("dalpha", da, dao),
+                                                        ("dbeta", db, dbo))}
+    coss = {k: _cos(v.cpu().numpy(), r) for k, v, r in (("dW", dW, dWo), ("dalpha", da, dao), ("dbeta", db, dbo))}
+    _say(f"[{n}x{m} {prec}] loss rel {lerr:.2e}; " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items())
+         + "; cos " + ", ".join(f"{k} {v:.6f}" for k, v in coss.items()))
+    assert lerr <= LOSS_TOL[prec]
+    if prec == "fp32":
+        for k, v in errs.items():
+            assert v <= GRAD_TOL_FP32, k
+    else:
+        assert errs["Z"] <= 0.1
+        for k, v in coss.items():
+            assert v >= 0.99, k
+    d.close()
