@@ -22,11 +22,11 @@
 // K-contiguous operand: D, D^T, W_t or W_t^T) from global memory, where the
 // operands stay L2-resident across the workgroups; FP32 issues four
 // v_mfma_f32_16x16x4_f32 per 16-byte pair, BF16 one v_mfma_f32_16x16x32_bf16.
-// Even and odd K steps go to separate accumulators (two more independent MFMA
-// chains), summed before the epilogue. LDS rows are padded by 16 bytes, which
-// spreads the 16 rows of a fragment read over distinct banks. B fragments are
-// loaded two K steps at a time, which keeps both kernels within 256 VGPRs:
-// two waves per SIMD (two workgroups per CU) hide each other's load latency.
+// In the one-block phases even and odd K steps go to separate accumulators
+// (two more independent MFMA chains), summed before the epilogue. LDS rows are padded by 16 bytes, which
+// spreads the 16 rows of a fragment read over distinct banks. The B batches
+// are sized to keep both kernels within 256 VGPRs: two waves per SIMD (two
+// workgroups per CU) hide each other's load latency.
 #include "common.hpp"
 #include "lista_persist.hpp"
 
@@ -36,8 +36,14 @@ namespace {
 constexpr int RB = kListaRows;
 constexpr int NW = 4;
 constexpr int NT = 64 * NW;
-constexpr int G = 4;   // column blocks per wave and pass
-constexpr int U = 2;   // K steps whose B fragments are loaded together
+// Column blocks per wave and pass (G) and K steps whose B fragments are
+// loaded together (U): the narrow phases (n_pad output columns, K = m_pad)
+// take one block and four K steps per batch, the wide phases (m_pad output
+// columns, K = n_pad) four blocks and two K steps. Each batch's loads are
+// issued before the MFMAs of the batch in front of it, and the first batch
+// of a phase before the epilogue of the phase in front of it.
+constexpr int GA = 1, UA = 4;
+constexpr int GB = 4, UB = 2;
 
 template <int P> struct LElem { static constexpr int bytes = 4; };
 template <> struct LElem<kBF16> { static constexpr int bytes = 2; };
@@ -72,12 +78,60 @@ __device__ __forceinline__ f32x4 mma(const uint4& a, const uint4& b, f32x4 c) {
   return c;
 }
 
+// B fragments of U consecutive K steps for the column blocks cb0 + 4 g.
+template <int G, int U>
+struct BFrags {
+  uint4 f[U][G];
+};
+
+template <int G, int U>
+__device__ __forceinline__ void load_b(BFrags<G, U>& b, const char* B, size_t browb, int k0, int nk, int cb0, int ncb,
+                                       int lr, int lg) {
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int cb = cb0 + 4 * g;
+      b.f[u][g] = (k0 + u < nk && cb < ncb)
+                      ? *(const uint4*)(B + (size_t)(cb * 16 + lr) * browb + (size_t)(k0 + u) * 64 + 16 * lg)
+                      : make_uint4(0, 0, 0, 0);
+    }
+}
+
+// MFMAs of the K steps k0 .. k0+U-1: with a single column block (G = 1) even
+// steps go into acc and odd steps into odd, two more independent MFMA chains;
+// with G > 1 the blocks already give 2 G chains and everything goes into acc.
+template <int P, int G, int U>
+__device__ __forceinline__ void mma_batch(const char* A, int arowb, const BFrags<G, U>& b, int k0, int nk, int cb0,
+                                          int ncb, f32x4 (&acc)[G][2], f32x4 (&odd)[G][2], int lr, int lg) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (k0 + u >= nk) break;
+    uint4 af[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) af[rb] = *(const uint4*)(A + (rb * 16 + lr) * arowb + (k0 + u) * 64 + 16 * lg);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (cb0 + 4 * g >= ncb) continue;  // wave-uniform: no MFMAs on an empty column block
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        if (G == 1 && (u & 1))
+          odd[g][rb] = mma<P>(af[rb], b.f[u][g], odd[g][rb]);
+        else
+          acc[g][rb] = mma<P>(af[rb], b.f[u][g], acc[g][rb]);
+      }
+    }
+  }
+}
+
 // acc[g][rb] = A[rb 16 .., 0..K) * B[cb_g 16 .., 0..K)^T for cb_g = cb0 + 4 g < ncb:
 // A in LDS (row stride arowb bytes), B in global memory (row stride browb
-// bytes), nk K steps of 64 bytes.
-template <int P>
+// bytes), nk K steps of 64 bytes. b0 holds the first U K steps' B fragments,
+// loaded by the caller (ahead of time where it can); each later batch is
+// loaded before the MFMAs of the batch in front of it (two buffers).
+template <int P, int G, int U>
 __device__ __forceinline__ void contract(const char* A, int arowb, const char* B, size_t browb, int nk, int cb0,
-                                         int ncb, f32x4 (&acc)[G][2], int lr, int lg) {
+                                         int ncb, f32x4 (&acc)[G][2], BFrags<G, U>& b0, int lr, int lg) {
   f32x4 odd[G][2];
 #pragma unroll
   for (int g = 0; g < G; ++g)
@@ -86,40 +140,20 @@ __device__ __forceinline__ void contract(const char* A, int arowb, const char* B
       acc[g][rb] = f32x4{0.f, 0.f, 0.f, 0.f};
       odd[g][rb] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-  for (int k0 = 0; k0 < nk; k0 += U) {
-    uint4 bf[U][G];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int cb = cb0 + 4 * g;
-        bf[u][g] = (k0 + u < nk && cb < ncb)
-                       ? *(const uint4*)(B + (size_t)(cb * 16 + lr) * browb + (size_t)(k0 + u) * 64 + 16 * lg)
-                       : make_uint4(0, 0, 0, 0);
-      }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (k0 + u >= nk) break;
-      uint4 af[2];
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb) af[rb] = *(const uint4*)(A + (rb * 16 + lr) * arowb + (k0 + u) * 64 + 16 * lg);
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        if (cb0 + 4 * g >= ncb) continue;  // wave-uniform: no MFMAs on an empty column block
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
-          if (u & 1)
-            odd[g][rb] = mma<P>(af[rb], bf[u][g], odd[g][rb]);
-          else
-            acc[g][rb] = mma<P>(af[rb], bf[u][g], acc[g][rb]);
-        }
-      }
-    }
+  BFrags<G, U> b1;
+  for (int k0 = 0; k0 < nk;) {
+    if (k0 + U < nk) load_b(b1, B, browb, k0 + U, nk, cb0, ncb, lr, lg);
+    mma_batch<P>(A, arowb, b0, k0, nk, cb0, ncb, acc, odd, lr, lg);
+    k0 += U;
+    if (k0 >= nk) break;
+    if (k0 + U < nk) load_b(b0, B, browb, k0 + U, nk, cb0, ncb, lr, lg);
+    mma_batch<P>(A, arowb, b1, k0, nk, cb0, ncb, acc, odd, lr, lg);
+    k0 += U;
   }
+  if constexpr (G == 1) {
 #pragma unroll
-  for (int g = 0; g < G; ++g)
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb) acc[g][rb] += odd[g][rb];
+    for (int rb = 0; rb < 2; ++rb) acc[0][rb] += odd[0][rb];
+  }
 }
 
 // Sum of one double per (wave, row) over the 16 lanes of a row group, then
@@ -171,6 +205,10 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
   const int ncbA = n_pad / 16, ncbB = m_pad / 16;
   const int nkA = m_pad * E / 64, nkB = n_pad * E / 64;
   const size_t rlayer = (size_t)a.n * a.Np, clayer = (size_t)a.nwg * (RB / 4) * m_pad;
+  const char* Dr = (const char*)a.Dr;
+  BFrags<GA, UA> preA;  // first B batch of the next phase A (rows of D)
+  BFrags<GB, UB> preB;  // first B batch of the next phase B (columns of W_t)
+  load_b(preA, Dr, (size_t)m_pad * E, 0, nkA, wave, ncbA, lr, lg);
   for (int t = 0; t <= T; ++t) {
     const bool last = t == T;
     {  // phase A: r = z D^T - x
@@ -178,11 +216,14 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
       float* rT = last ? a.rT : nullptr;
       const bool want_f = last && a.fres;
       double fr[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-      for (int c0 = wave; c0 < ncbA; c0 += 4 * G) {
-        f32x4 acc[G][2];
-        contract<P>(zA, zrowb, (const char*)a.Dr, (size_t)m_pad * E, nkA, c0, ncbA, acc, lr, lg);
+      for (int c0 = wave; c0 < ncbA; c0 += 4 * GA) {
+        f32x4 acc[GA][2];
+        if (c0 != wave) load_b(preA, Dr, (size_t)m_pad * E, 0, nkA, c0, ncbA, lr, lg);
+        contract<P, GA, UA>(zA, zrowb, Dr, (size_t)m_pad * E, nkA, c0, ncbA, acc, preA, lr, lg);
+        if (!last && c0 + 4 * GA >= ncbA)  // phase B's first W_t batch, in flight during this epilogue
+          load_b(preB, (const char*)a.WT + (size_t)t * m_pad * n_pad * E, (size_t)n_pad * E, 0, nkB, wave, ncbB, lr, lg);
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
+        for (int g = 0; g < GA; ++g) {
           const int cb = c0 + 4 * g;
           if (cb >= ncbA) continue;
           const int col = cb * 16 + lr;
@@ -220,11 +261,14 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
       const bool want_l1 = t == T - 1 && a.fl1;
       double fl[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
       const char* Wt = (const char*)a.WT + (size_t)t * m_pad * n_pad * E;
-      for (int c0 = wave; c0 < ncbB; c0 += 4 * G) {
-        f32x4 acc[G][2];
-        contract<P>(rA, rrowb, Wt, (size_t)n_pad * E, nkB, c0, ncbB, acc, lr, lg);
+      for (int c0 = wave; c0 < ncbB; c0 += 4 * GB) {
+        f32x4 acc[GB][2];
+        if (c0 != wave) load_b(preB, Wt, (size_t)n_pad * E, 0, nkB, c0, ncbB, lr, lg);
+        contract<P, GB, UB>(rA, rrowb, Wt, (size_t)n_pad * E, nkB, c0, ncbB, acc, preB, lr, lg);
+        if (c0 + 4 * GB >= ncbB)  // the next phase A's first D batch
+          load_b(preA, Dr, (size_t)m_pad * E, 0, nkA, wave, ncbA, lr, lg);
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
+        for (int g = 0; g < GB; ++g) {
           const int cb = c0 + 4 * g;
           if (cb >= ncbB) continue;
           const int col = cb * 16 + lr;
@@ -292,17 +336,23 @@ __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
 
   const int ncbA = n_pad / 16, ncbB = m_pad / 16;
   const int nkA = m_pad * E / 64, nkB = n_pad * E / 64;
+  const char* DT = (const char*)a.DT;
+  BFrags<GA, UA> preA;  // first B batch of the next phase A' (rows of W_t)
+  BFrags<GB, UB> preB;  // first B batch of the next phase B' (columns of D)
+  load_b(preA, (const char*)a.Wr + (size_t)(T - 1) * n_pad * m_pad * E, (size_t)m_pad * E, 0, nkA, wave, ncbA, lr, lg);
   for (int t = T - 1; t >= 0; --t) {
     const float al = a.alpha[t];
     double da = 0.0, db = 0.0;
     {  // phase A': q = W_t v (rows: samples), dalpha_t partial q . R^t
       const float* R = a.rtape + (size_t)t * rlayer;
       const char* W = (const char*)a.Wr + (size_t)t * n_pad * m_pad * E;
-      for (int c0 = wave; c0 < ncbA; c0 += 4 * G) {
-        f32x4 acc[G][2];
-        contract<P>(vA, vrowb, W, (size_t)m_pad * E, nkA, c0, ncbA, acc, lr, lg);
+      for (int c0 = wave; c0 < ncbA; c0 += 4 * GA) {
+        f32x4 acc[GA][2];
+        if (c0 != wave) load_b(preA, W, (size_t)m_pad * E, 0, nkA, c0, ncbA, lr, lg);
+        contract<P, GA, UA>(vA, vrowb, W, (size_t)m_pad * E, nkA, c0, ncbA, acc, preA, lr, lg);
+        if (c0 + 4 * GA >= ncbA) load_b(preB, DT, (size_t)n_pad * E, 0, nkB, wave, ncbB, lr, lg);
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
+        for (int g = 0; g < GA; ++g) {
           const int cb = c0 + 4 * g;
           if (cb >= ncbA) continue;
           const int col = cb * 16 + lr;
@@ -329,19 +379,23 @@ __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
     {  // phase B': v^{t-1} = [z^t != 0] (v^t - a_t q D), dbeta_t partial v^t sign z^{t+1}
       const uint32_t* codes = a.codes + (size_t)t * clayer;
       float* vt = t >= 1 ? a.vtape + (size_t)(t - 1) * vlayer : nullptr;
-      for (int c0 = wave; c0 < ncbB; c0 += 4 * G) {
-        uint32_t cw[G][2];  // issued before the contraction, consumed by the epilogue
+      for (int c0 = wave; c0 < ncbB; c0 += 4 * GB) {
+        uint32_t cw[GB][2];  // issued before the contraction, consumed by the epilogue
 #pragma unroll
-        for (int g = 0; g < G; ++g)
+        for (int g = 0; g < GB; ++g)
 #pragma unroll
           for (int rb = 0; rb < 2; ++rb) {
             const int cb = c0 + 4 * g;
             cw[g][rb] = cb < ncbB ? codes[(size_t)((row0 + rb * 16) / 4 + lg) * m_pad + cb * 16 + lr] : 0u;
           }
-        f32x4 acc[G][2];
-        contract<P>(qA, qrowb, (const char*)a.DT, (size_t)n_pad * E, nkB, c0, ncbB, acc, lr, lg);
+        f32x4 acc[GB][2];
+        if (c0 != wave) load_b(preB, DT, (size_t)n_pad * E, 0, nkB, c0, ncbB, lr, lg);
+        contract<P, GB, UB>(qA, qrowb, DT, (size_t)n_pad * E, nkB, c0, ncbB, acc, preB, lr, lg);
+        if (t >= 1 && c0 + 4 * GB >= ncbB)  // the next phase A''s first W_{t-1} batch
+          load_b(preA, (const char*)a.Wr + (size_t)(t - 1) * n_pad * m_pad * E, (size_t)m_pad * E, 0, nkA, wave, ncbA,
+                 lr, lg);
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
+        for (int g = 0; g < GB; ++g) {
           const int cb = c0 + 4 * g;
           if (cb >= ncbB) continue;
           const int col = cb * 16 + lr;
