@@ -248,6 +248,46 @@ def training_report(sl, torch, iters: int) -> dict:
     return out
 
 
+def baselines_report(sl, torch, reps: int) -> dict:
+    """FISTA and Oracle-ISTA (the paper's comparison methods, per-layer
+    kernels) on the 64 x 256 batched-forward workload (N = 10000, T = 40):
+    sample-layers/s of the forward pass per precision. FISTA's useful work is
+    2 m^2 flops per sample-layer (G y^t); Oracle-ISTA adds per sample and layer
+    the power iteration for L_S on the support."""
+    import numpy as np
+    import synth
+    c = synth.CONFIGS["fwd_64x256"]
+    pb = synth.make_problem(c["n"], c["m"], c["N"], c["p"], c["sigma"], c["lam_frac"], c["seed"])
+    dev = torch.device("cuda:0")
+    d = sl.Dictionary(torch.tensor(pb.D32(), device=dev))
+    X = torch.tensor(pb.X32(), device=dev)
+    L, _ = d.lipschitz(max_iter=100_000, rtol=1e-12)
+    N, T, m = pb.N, c["T"], pb.m
+    alpha = torch.full((T,), float(np.float32(1.0 / L)), device=dev, dtype=torch.float32)
+    out = {"workload": "fwd_64x256", "n": pb.n, "m": m, "N": N, "T": T, "pass": "forward"}
+    runs = {"fista": lambda p: sl.fista(d, X, pb.lam, alpha, prec=p),
+            "oista": lambda p: sl.oista(d, X, pb.lam, L, T, prec=p)}
+    for name, fn in runs.items():
+        out[name] = {}
+        for p in ("fp32", "bf16"):
+            fn(p)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                res = fn(p)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            r = {"ms_per_call": round(ms, 4), "value": round(N * T / (ms * 1e-3), 1), "unit": "sample-layers/s",
+                 "loss": float(res[2].item())}
+            if name == "fista":
+                r["useful_tflops"] = round(2.0 * m * m * N * T / (ms * 1e-3) / 1e12, 2)
+            out[name][p] = r
+    d.close()
+    return out
+
+
 def lista_report(sl, torch, reps: int, precs) -> dict:
     """Coupled LISTA forward+backward (all parameter gradients, dW included) on
     the 64 x 256 Gaussian workload, N = 10000, T = 40: sample-layers/s and the
@@ -311,6 +351,7 @@ def main() -> int:
     ap.add_argument("--no-train", action="store_true", help="skip the step-size training report")
     ap.add_argument("--train-iters", type=int, default=30)
     ap.add_argument("--no-lista", action="store_true", help="skip the coupled LISTA report")
+    ap.add_argument("--no-baselines", action="store_true", help="skip the FISTA / Oracle-ISTA report")
     ap.add_argument("--lista-reps", type=int, default=10)
     ap.add_argument("--uneven-precs", default="bf16,fp32")
     ap.add_argument("--uneven-reps", type=int, default=3)
@@ -399,6 +440,11 @@ def main() -> int:
         lista = lista_report(sl, torch, args.lista_reps, ("fp32", "bf16"))
         print(f"[bench] lista {lista}", file=sys.stderr, flush=True)
 
+    baselines = None
+    if not args.no_baselines:
+        baselines = baselines_report(sl, torch, 5)
+        print(f"[bench] baselines {baselines}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pb, np.asarray(alpha.cpu().numpy(), np.float64), min(args.cpu_sample, pb.N))
@@ -433,6 +479,7 @@ def main() -> int:
         "uneven_batch": uneven,
         "training": train,
         "lista": lista,
+        "fista_oista": baselines,
         "autotune": tuned or {"forced_variant": args.variant},
     }
     print(json.dumps(line))
