@@ -229,94 +229,107 @@ __global__ void k_fista_beta(int T, float* __restrict__ beta) {
   }
 }
 
-// L_S of one sample's support per workgroup (Oracle-ISTA, Section 3): the
-// support S of row i of Z is compacted in index order (deterministic), then
+// L_S of one sample's support per wave (Oracle-ISTA, Section 3): the support
+// S of row i of Z is compacted in index order (a ballot per 64 columns), then
 // power iteration on G_SS in FP64 from the previous layer's vector V[i]
 // restricted to S (or the hash start vector when that is ~0), until
 // successive Rayleigh quotients agree to tol or max_iter. step[i] = 1/L_S,
-// 1/L for an empty support; V[i] gets the final vector (0 off S).
-constexpr int kLsThreads = 256;
-__global__ __launch_bounds__(kLsThreads) void k_support_lipschitz(const float* __restrict__ G, int m, int mp,
-                                                                 const float* __restrict__ Z, float* __restrict__ V,
-                                                                 double L, int max_iter, double tol,
-                                                                 float* __restrict__ step) {
+// 1/L for an empty support; V[i] gets the final vector (0 off S). Supports
+// of at most kLsCache atoms keep G_SS in LDS (gathered once); larger ones
+// read G from L2 every iteration. One 64-lane workgroup per sample: the
+// reductions are fixed-order shuffles and the barriers cost one wave.
+constexpr int kLsLanes = 64;
+constexpr int kLsCache = 64;
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+size_t support_lipschitz_lds(int mp) {
+  return (size_t)mp * (2 * sizeof(double) + sizeof(int)) + (size_t)kLsCache * (kLsCache + 1) * sizeof(float);
+}
+
+__global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __restrict__ G, int m, int mp,
+                                                               const float* __restrict__ Z, float* __restrict__ V,
+                                                               double L, int max_iter, double tol,
+                                                               float* __restrict__ step) {
   extern __shared__ __attribute__((aligned(16))) char sm[];
-  double* v = (double*)sm;          // [mp]
-  double* w = v + mp;               // [mp]
-  int* idx = (int*)(w + mp);        // [mp]
-  int* cnt = idx + mp;              // [kLsThreads + 1]
-  __shared__ double sh[kLsThreads];
-  const int i = blockIdx.x, tid = threadIdx.x;
+  double* v = (double*)sm;                   // [mp]
+  double* w = v + mp;                        // [mp]
+  float* gs = (float*)(w + mp);              // [kLsCache][kLsCache + 1]
+  int* idx = (int*)(gs + kLsCache * (kLsCache + 1));  // [mp]
+  const int i = blockIdx.x, lane = threadIdx.x;
   const float* z = Z + (size_t)i * mp;
   float* vrow = V + (size_t)i * mp;
-  const int chunk = (m + kLsThreads - 1) / kLsThreads;
-  const int j0 = tid * chunk, j1 = min(j0 + chunk, m);
-  int c = 0;
-  for (int j = j0; j < j1; ++j) c += z[j] != 0.f;
-  cnt[tid] = c;
-  __syncthreads();
-  if (tid == 0) {  // exclusive scan of the per-thread counts, in thread order
-    int acc = 0;
-    for (int k = 0; k < kLsThreads; ++k) {
-      const int ck = cnt[k];
-      cnt[k] = acc;
-      acc += ck;
-    }
-    cnt[kLsThreads] = acc;
+  int ns = 0;
+  for (int j0 = 0; j0 < m; j0 += kLsLanes) {
+    const int j = j0 + lane;
+    const bool nz = j < m && z[j] != 0.f;
+    const unsigned long long ball = __ballot(nz);
+    if (nz) idx[ns + __popcll(ball & ((1ull << lane) - 1ull))] = j;
+    ns += __popcll(ball);
   }
   __syncthreads();
-  int pos = cnt[tid];
-  for (int j = j0; j < j1; ++j)
-    if (z[j] != 0.f) idx[pos++] = j;
-  const int ns = cnt[kLsThreads];
-  __syncthreads();
   if (ns == 0) {
-    if (tid == 0) step[i] = (float)(1.0 / L);
+    if (lane == 0) step[i] = (float)(1.0 / L);
     return;
   }
   double nrm = 0.0;
-  for (int k = tid; k < ns; k += kLsThreads) {
+  for (int k = lane; k < ns; k += kLsLanes) {
     v[k] = (double)vrow[idx[k]];
     nrm += v[k] * v[k];
   }
-  nrm = block_sum(nrm, sh);
+  nrm = wave_sum(nrm);
   if (!(nrm > 1e-24)) {
     nrm = 0.0;
-    for (int k = tid; k < ns; k += kLsThreads) {
+    for (int k = lane; k < ns; k += kLsLanes) {
       v[k] = start_value(idx[k]);
       nrm += v[k] * v[k];
     }
-    nrm = block_sum(nrm, sh);
+    nrm = wave_sum(nrm);
   }
   nrm = sqrt(nrm);
-  for (int k = tid; k < ns; k += kLsThreads) v[k] /= nrm;
+  for (int k = lane; k < ns; k += kLsLanes) v[k] /= nrm;
+  const bool cached = ns <= kLsCache;
+  if (cached)
+    for (int e = lane; e < ns * ns; e += kLsLanes) {
+      const int r = e / ns, c = e - r * ns;
+      gs[r * (kLsCache + 1) + c] = G[(size_t)idx[r] * mp + idx[c]];
+    }
   __syncthreads();
   double rq = 0.0, prev = 0.0;
   for (int it = 0; it < max_iter; ++it) {
-    for (int k = tid; k < ns; k += kLsThreads) {
-      const float* grow = G + (size_t)idx[k] * mp;
+    for (int k = lane; k < ns; k += kLsLanes) {
       double s = 0.0;
-      for (int l = 0; l < ns; ++l) s += (double)grow[idx[l]] * v[l];
+      if (cached) {
+        const float* grow = gs + k * (kLsCache + 1);
+        for (int l = 0; l < ns; ++l) s += (double)grow[l] * v[l];
+      } else {
+        const float* grow = G + (size_t)idx[k] * mp;
+        for (int l = 0; l < ns; ++l) s += (double)grow[idx[l]] * v[l];
+      }
       w[k] = s;
     }
     __syncthreads();
     double pr = 0.0, pw = 0.0;
-    for (int k = tid; k < ns; k += kLsThreads) {
+    for (int k = lane; k < ns; k += kLsLanes) {
       pr += v[k] * w[k];
       pw += w[k] * w[k];
     }
-    rq = block_sum(pr, sh);
-    const double nw = sqrt(block_sum(pw, sh));
+    rq = wave_sum(pr);
+    const double nw = sqrt(wave_sum(pw));
     if (nw == 0.0) break;
-    for (int k = tid; k < ns; k += kLsThreads) v[k] = w[k] / nw;
+    for (int k = lane; k < ns; k += kLsLanes) v[k] = w[k] / nw;
     __syncthreads();
     if (it > 0 && fabs(rq - prev) <= tol * fabs(rq)) break;
     prev = rq;
   }
-  for (int j = tid; j < mp; j += kLsThreads) vrow[j] = 0.f;
+  for (int j = lane; j < mp; j += kLsLanes) vrow[j] = 0.f;
   __syncthreads();
-  for (int k = tid; k < ns; k += kLsThreads) vrow[idx[k]] = (float)v[k];
-  if (tid == 0) step[i] = (float)(rq > 0.0 ? 1.0 / rq : 1.0 / L);
+  for (int k = lane; k < ns; k += kLsLanes) vrow[idx[k]] = (float)v[k];
+  if (lane == 0) step[i] = (float)(rq > 0.0 ? 1.0 / rq : 1.0 / L);
 }
 
 // Oracle-ISTA update: row i takes a_i = step[i] if its support condition
@@ -483,11 +496,11 @@ hipError_t launch_alpha_step(const float* alpha, const float* g, double eta, int
 hipError_t launch_support_lipschitz(const float* G32, int m, int mp, const float* Z, float* V, double L,
                                     int max_iter, double tol, int N, float* step, hipStream_t s) {
   if (N == 0) return hipSuccess;
-  const size_t lds = (size_t)mp * (2 * sizeof(double) + sizeof(int)) + (kLsThreads + 1) * sizeof(int);
+  const size_t lds = support_lipschitz_lds(mp);
   hipError_t e = hipFuncSetAttribute((const void*)k_support_lipschitz, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_support_lipschitz, dim3(N), dim3(kLsThreads), lds, s, G32, m, mp, Z, V, L, max_iter, tol,
+  hipLaunchKernelGGL(k_support_lipschitz, dim3(N), dim3(kLsLanes), lds, s, G32, m, mp, Z, V, L, max_iter, tol,
                      step);
   return hipGetLastError();
 }
