@@ -291,10 +291,13 @@ SLISTA_API int slista_fista(const slista_dict* dict, const float* X, int N, floa
 
 /* ---------------------------------------------------------------------------
  * Oracle-ISTA (Section 3, Algorithm 1): per sample and layer, S = supp(z^t),
- * L_S = greatest eigenvalue of G restricted to S (FP64 power iteration,
- * warm-started from the previous layer, stopped when successive Rayleigh
- * quotients agree to power_rtol or after max_power_iter steps; L_S = L for
- * an empty support); the step 1/L_S is taken when the support condition (*)
+ * L_S = greatest eigenvalue of G restricted to S (L_S = L for an empty
+ * support), by Lanczos in FP64 from a fixed start vector: the largest
+ * eigenvalue of the Lanczos tridiagonal matrix, evaluated every 8 steps,
+ * rises to L_S; the recurrence stops when two evaluations agree to
+ * power_rtol (relative), after min(|S|, max_power_iter, 128) steps, or when
+ * the Krylov space is exhausted. The step 1/L_S is taken when the support
+ * condition (*)
  * holds and 1/L otherwise. For z_j = 0 the condition fails exactly when
  * |(G z^t - c)_j| > lam, whatever the step, so one contraction per layer
  * decides it. L: the dictionary's Lipschitz constant (slista_dict_lipschitz).

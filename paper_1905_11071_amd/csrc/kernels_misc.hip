@@ -229,17 +229,21 @@ __global__ void k_fista_beta(int T, float* __restrict__ beta) {
   }
 }
 
-// L_S of one sample's support per wave (Oracle-ISTA, Section 3): the support
-// S of row i of Z is compacted in index order (a ballot per 64 columns), then
-// power iteration on G_SS in FP64 from the previous layer's vector V[i]
-// restricted to S (or the hash start vector when that is ~0), until
-// successive Rayleigh quotients agree to tol or max_iter. step[i] = 1/L_S,
-// 1/L for an empty support; V[i] gets the final vector (0 off S). Supports
-// of at most kLsCache atoms keep G_SS in LDS (gathered once); larger ones
-// read G from L2 every iteration. One 64-lane workgroup per sample: the
-// reductions are fixed-order shuffles and the barriers cost one wave.
+// L_S of one sample's support per wave (Oracle-ISTA, Section 3). The support
+// S of row i of Z is compacted in index order (a ballot per 64 columns); then
+// Lanczos (three-term recurrence in FP64, no stored basis) from a fixed start
+// vector, a hash of the atom indices, with lanes owning coordinates
+// lane + 64 c. The largest eigenvalue of the Lanczos tridiagonal matrix rises
+// to L_S; it is evaluated every 8 steps (65-point multisection with Sturm
+// counts) and the recurrence stops when two evaluations agree to tol, after
+// min(|S|, max_iter, kLsMaxSteps) steps, or when the Krylov space is
+// exhausted. Supports of at most kLsCache atoms read G_SS from LDS (gathered
+// once), larger ones read G from L2. step[i] = 1/L_S, 1/L for an empty
+// support. One 64-lane workgroup per sample: reductions are fixed-order
+// shuffles and the barriers cost one wave. V is not used.
 constexpr int kLsLanes = 64;
 constexpr int kLsCache = 64;
+constexpr int kLsMaxSteps = 128;  // Krylov dimension cap
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -247,22 +251,70 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// LDS: q, q_prev, w [mp] doubles each, the tridiagonal (2 kLsMaxSteps
+// doubles), G_SS [kLsCache][kLsCache + 1] floats, support indices [mp] ints.
+__host__ __device__ size_t support_vec_bytes(int mp) {
+  return ((size_t)3 * mp + 2 * kLsMaxSteps) * sizeof(double);
+}
+
 size_t support_lipschitz_lds(int mp) {
-  return (size_t)mp * (2 * sizeof(double) + sizeof(int)) + (size_t)kLsCache * (kLsCache + 1) * sizeof(float);
+  return support_vec_bytes(mp) + (size_t)kLsCache * (kLsCache + 1) * sizeof(float) + (size_t)mp * sizeof(int);
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal a[0..k) and off-diagonal b[1..k) (Sturm sequence of the LDL^T pivots).
+__device__ int sturm_below(const double* a, const double* b, int k, double x) {
+  int cnt = 0;
+  double d = 1.0;
+  for (int i = 0; i < k; ++i) {
+    d = (a[i] - x) - (i > 0 ? b[i] * b[i] / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    cnt += d < 0.0;
+  }
+  return cnt;
+}
+
+// Largest eigenvalue of the symmetric tridiagonal (a[0..k), b[1..k)): the
+// Gershgorin interval narrowed by 65-point multisection, lane l testing
+// lo + (l + 1)(hi - lo) / 65, until it is 1e-15 relative (at most 12 rounds).
+// Wave-uniform; returns the upper end.
+__device__ double tridiag_top(const double* a, const double* b, int k, int lane) {
+  double lo = 1e300, hi = -1e300;
+  for (int r = 0; r < k; ++r) {
+    const double off = (r > 0 ? fabs(b[r]) : 0.0) + (r + 1 < k ? fabs(b[r + 1]) : 0.0);
+    lo = fmin(lo, a[r] - off);
+    hi = fmax(hi, a[r] + off);
+  }
+  for (int round = 0; round < 12 && hi - lo > 1e-15 * fmax(fabs(hi), 1e-300); ++round) {
+    const double x = lo + (hi - lo) * (double)(lane + 1) / (double)(kLsLanes + 1);
+    const unsigned long long above = __ballot(sturm_below(a, b, k, x) == k);  // x above every eigenvalue
+    if (above == 0ull) {
+      lo = lo + (hi - lo) * (double)kLsLanes / (double)(kLsLanes + 1);
+    } else {
+      const int f = __ffsll((long long)above) - 1;  // first lane above the largest eigenvalue
+      const double nlo = f > 0 ? lo + (hi - lo) * (double)f / (double)(kLsLanes + 1) : lo;
+      hi = lo + (hi - lo) * (double)(f + 1) / (double)(kLsLanes + 1);
+      lo = nlo;
+    }
+  }
+  return hi;
 }
 
 __global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __restrict__ G, int m, int mp,
                                                                const float* __restrict__ Z, float* __restrict__ V,
                                                                double L, int max_iter, double tol,
                                                                float* __restrict__ step) {
+  (void)V;
   extern __shared__ __attribute__((aligned(16))) char sm[];
-  double* v = (double*)sm;                   // [mp]
-  double* w = v + mp;                        // [mp]
-  float* gs = (float*)(w + mp);              // [kLsCache][kLsCache + 1]
-  int* idx = (int*)(gs + kLsCache * (kLsCache + 1));  // [mp]
+  double* q = (double*)sm;                  // [mp] q_j
+  double* qp = q + mp;                      // [mp] q_{j-1}
+  double* wv = qp + mp;                     // [mp] G_SS q_j, then the next residual
+  double* la = wv + mp;                     // [kLsMaxSteps] tridiagonal: diagonal
+  double* lb = la + kLsMaxSteps;            // [kLsMaxSteps] off-diagonal (lb[j] couples j-1, j)
+  float* gs = (float*)(sm + support_vec_bytes(mp));  // [kLsCache][kLsCache + 1]
+  int* idx = (int*)(gs + kLsCache * (kLsCache + 1)); // [mp]
   const int i = blockIdx.x, lane = threadIdx.x;
   const float* z = Z + (size_t)i * mp;
-  float* vrow = V + (size_t)i * mp;
   int ns = 0;
   for (int j0 = 0; j0 < m; j0 += kLsLanes) {
     const int j = j0 + lane;
@@ -276,60 +328,64 @@ __global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __r
     if (lane == 0) step[i] = (float)(1.0 / L);
     return;
   }
-  double nrm = 0.0;
-  for (int k = lane; k < ns; k += kLsLanes) {
-    v[k] = (double)vrow[idx[k]];
-    nrm += v[k] * v[k];
-  }
-  nrm = wave_sum(nrm);
-  if (!(nrm > 1e-24)) {
-    nrm = 0.0;
-    for (int k = lane; k < ns; k += kLsLanes) {
-      v[k] = start_value(idx[k]);
-      nrm += v[k] * v[k];
-    }
-    nrm = wave_sum(nrm);
-  }
-  nrm = sqrt(nrm);
-  for (int k = lane; k < ns; k += kLsLanes) v[k] /= nrm;
   const bool cached = ns <= kLsCache;
   if (cached)
     for (int e = lane; e < ns * ns; e += kLsLanes) {
       const int r = e / ns, c = e - r * ns;
       gs[r * (kLsCache + 1) + c] = G[(size_t)idx[r] * mp + idx[c]];
     }
-  __syncthreads();
-  double rq = 0.0, prev = 0.0;
-  for (int it = 0; it < max_iter; ++it) {
-    for (int k = lane; k < ns; k += kLsLanes) {
-      double s = 0.0;
-      if (cached) {
-        const float* grow = gs + k * (kLsCache + 1);
-        for (int l = 0; l < ns; ++l) s += (double)grow[l] * v[l];
-      } else {
-        const float* grow = G + (size_t)idx[k] * mp;
-        for (int l = 0; l < ns; ++l) s += (double)grow[idx[l]] * v[l];
-      }
-      w[k] = s;
-    }
-    __syncthreads();
-    double pr = 0.0, pw = 0.0;
-    for (int k = lane; k < ns; k += kLsLanes) {
-      pr += v[k] * w[k];
-      pw += w[k] * w[k];
-    }
-    rq = wave_sum(pr);
-    const double nw = sqrt(wave_sum(pw));
-    if (nw == 0.0) break;
-    for (int k = lane; k < ns; k += kLsLanes) v[k] = w[k] / nw;
-    __syncthreads();
-    if (it > 0 && fabs(rq - prev) <= tol * fabs(rq)) break;
-    prev = rq;
+  double nrm = 0.0;
+  for (int c = lane; c < ns; c += kLsLanes) {
+    q[c] = start_value(idx[c]);
+    qp[c] = 0.0;
+    nrm += q[c] * q[c];
   }
-  for (int j = lane; j < mp; j += kLsLanes) vrow[j] = 0.f;
+  nrm = sqrt(wave_sum(nrm));
+  for (int c = lane; c < ns; c += kLsLanes) q[c] /= nrm;
   __syncthreads();
-  for (int k = lane; k < ns; k += kLsLanes) vrow[idx[k]] = (float)v[k];
-  if (lane == 0) step[i] = (float)(rq > 0.0 ? 1.0 / rq : 1.0 / L);
+  int kmax = ns < max_iter ? ns : max_iter;
+  if (kmax > kLsMaxSteps) kmax = kLsMaxSteps;
+  double beta = 0.0, top = 0.0, prev = -1.0;
+  for (int j = 0; j < kmax; ++j) {
+    double pa = 0.0;
+    for (int c = lane; c < ns; c += kLsLanes) {
+      double sacc = 0.0;
+      if (cached) {
+        const float* grow = gs + c * (kLsCache + 1);
+        for (int l = 0; l < ns; ++l) sacc += (double)grow[l] * q[l];
+      } else {
+        const float* grow = G + (size_t)idx[c] * mp;
+        for (int l = 0; l < ns; ++l) sacc += (double)grow[idx[l]] * q[l];
+      }
+      wv[c] = sacc;
+      pa += q[c] * sacc;
+    }
+    const double alpha = wave_sum(pa);
+    double pb = 0.0;
+    for (int c = lane; c < ns; c += kLsLanes) {
+      const double r = wv[c] - alpha * q[c] - beta * qp[c];
+      wv[c] = r;
+      pb += r * r;
+    }
+    const double b = sqrt(wave_sum(pb));
+    if (lane == 0) la[j] = alpha;
+    const int k = j + 1;
+    __syncthreads();  // la[j] visible
+    const bool last = k == kmax || !(b > 1e-13 * (fabs(alpha) + beta));
+    if (last || (k % 8) == 0) {
+      top = tridiag_top(la, lb, k, lane);
+      if (last || fabs(top - prev) <= tol * fabs(top)) break;
+      prev = top;
+    }
+    if (lane == 0) lb[k] = b;
+    for (int c = lane; c < ns; c += kLsLanes) {
+      qp[c] = q[c];
+      q[c] = wv[c] / b;
+    }
+    beta = b;
+    __syncthreads();  // q_{j+1} and lb[k] visible
+  }
+  if (lane == 0) step[i] = (float)(top > 0.0 ? 1.0 / top : 1.0 / L);
 }
 
 // Oracle-ISTA update: row i takes a_i = step[i] if its support condition
