@@ -50,9 +50,12 @@ def test_oista_vs_oracle(sl, name, prec):
     Zg = Z.cpu().numpy().astype(np.float64)
     sg = steps.cpu().numpy().astype(np.float64)
     Zo, Fo, so = oracle.oista(pb.D, pb.X, pb.lam, T, return_steps=True)
-    # the branch each sample took at each layer: the same step up to the power-iteration / FP32 accuracy
+    # the branch each sample took at each layer: the same step up to the FP32 accuracy of G
     same = np.isclose(sg, so, rtol=1e-4)
     frac = float(np.mean(same))
+    # where both took 1/L_S, the device's L_S (Lanczos on the FP32 Gram matrix) against LAPACK's
+    ls = same & (so > 1.0001 / L)
+    ls_err = float(np.max(np.abs(sg[ls] - so[ls]) / so[ls])) if ls.any() else 0.0
     zs = oracle.lasso_solution(pb.D, pb.X, pb.lam)
     Fs = oracle.objective(pb.D, pb.X, zs, pb.lam)
     g_gpu = float(np.mean(oracle.objective(pb.D, pb.X, Zg, pb.lam) - Fs))
@@ -61,12 +64,15 @@ def test_oista_vs_oracle(sl, name, prec):
     g_rnd = float(np.mean(oracle.objective(pb.D, pb.X, rnd(Zo), pb.lam) - Fs))
     rel = abs(g_gpu - g_orc) / g_orc
     tol = gap_tolerance(prec, T, g_orc, g_rnd)
-    _say(f"[{name} {prec}] steps agreeing {frac:.4f}, larger than 1/L {np.mean(so > 1.0001 / L):.3f}; "
-         f"mean-gap rel err {rel:.2e} (tolerance {tol:.2e}), gap/F* {g_orc / np.mean(Fs):.2e}")
+    _say(f"[{name} {prec}] steps agreeing {frac:.4f}, larger than 1/L {np.mean(so > 1.0001 / L):.3f}, "
+         f"1/L_S rel err {ls_err:.2e}; mean-gap rel err {rel:.2e} (tolerance {tol:.2e}), "
+         f"gap/F* {g_orc / np.mean(Fs):.2e}")
     # FP32 follows the oracle's trajectory, so it takes the same branch; BF16
     # contractions move the trajectory (and with it the supports), so there
     # the agreement is only a sanity bound and the gap carries the claim
     assert frac >= (0.999 if prec == "fp32" else 0.9)
+    if prec == "fp32":  # the FP32 Gram matrix moves L_S by a few units of FP32 rounding
+        assert ls_err <= 1e-5
     assert rel <= tol
     np.testing.assert_allclose(F.cpu().numpy(), oracle.objective(pb.D, pb.X, Zg, pb.lam),
                                rtol=1e-4 if prec == "fp32" else 2e-2)
