@@ -251,3 +251,24 @@ def test_lista_wide_dictionaries(sl, shape, prec):
         for k, v in coss.items():
             assert v >= 0.99, k
     d.close()
+
+
+@pytest.mark.parametrize("N,T", [(5, 1), (33, 2), (1, 3)])
+def test_lista_small_batches_and_depths(sl, N, T):
+    """One partial 32-sample tile (N = 5, 1), a full tile plus one sample
+    (N = 33), and a single layer (T = 1: the seed goes straight to the
+    weight gradient), FP32 against the oracle."""
+    pb = synth.make_problem(20, 80, N, 0.1, 0.01, 0.1, seed=1310 + N)
+    W, a, b = _params(pb, T, 9, 0.2)
+    Zo, Fo, dWo, dao, dbo = oracle.lista_forward_backward(pb.D, pb.X, pb.lam, W, a, b, dF=np.full(N, 1.0 / N))
+    d = sl.Dictionary(_gpu(pb.D))
+    Z, F, loss, dW, da, db, _ = sl.lista_forward_backward(d, _gpu(pb.X), pb.lam, _gpu(W), _gpu(a), _gpu(b))
+    torch.cuda.synchronize()
+    errs = {k: _rel(v.cpu().numpy(), r) for k, v, r in (("Z", Z, Zo), ("dW", dW, dWo), ("dalpha", da, dao),
+                                                        ("dbeta", db, dbo)) if np.max(np.abs(r)) > 0}
+    lo = float(np.mean(Fo[-1]))
+    _say(f"[N={N} T={T}] loss rel {abs(loss.item() - lo) / lo:.2e}; " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    assert abs(loss.item() - lo) / lo <= LOSS_TOL["fp32"]
+    for k, v in errs.items():
+        assert v <= GRAD_TOL_FP32, k
+    d.close()
