@@ -121,3 +121,21 @@ def test_bf16_rounding_helper_matches_torch():
                         [0.0, -0.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8]]).astype(np.float32)
     ref = torch.from_numpy(x).to(torch.bfloat16).double().numpy()
     assert np.array_equal(round_to_bf16(x), ref)
+
+
+def test_lista_entry_points_reject_bad_arguments(lib):
+    """The coupled-LISTA entry points validate on the host, before any launch."""
+    vp = ctypes.c_void_p
+    size = ctypes.c_size_t()
+    assert lib.slista_lista_workspace_size(None, 4, 3, 0, 1, ctypes.byref(size)) == -1
+    assert b"dict" in lib.slista_last_error()
+    st = lib.slista_lista_forward(None, vp(16), 4, ctypes.c_float(0.1), vp(16), vp(16), vp(16), 3, 0, vp(16), None,
+                                  None, 1, vp(256), ctypes.c_size_t(1 << 20), None)
+    assert st == -1
+    st = lib.slista_lista_backward(None, 4, ctypes.c_float(0.1), vp(16), vp(16), 3, 0, None, None, None, vp(16),
+                                   vp(16), vp(256), ctypes.c_size_t(1 << 20), None)
+    assert st == -1
+    st = lib.slista_lista_forward_backward(None, vp(16), 4, ctypes.c_float(0.1), vp(16), vp(16), vp(16), 3, 0,
+                                           vp(16), None, None, None, vp(16), vp(16), vp(256),
+                                           ctypes.c_size_t(1 << 20), None)
+    assert st == -1
