@@ -185,7 +185,9 @@ struct Layout {
 Layout make_layout(const slista::Dict& d, int N, int T, int k) {
   Layout L;
   L.k = k;
-  L.zbytes = (size_t)N * d.m_pad * sizeof(float);
+  // N rounded up to whole 4-row groups: the persistent kernels keep the
+  // iterates in the accumulator's row order (four rows of a column together)
+  L.zbytes = (size_t)((N + 3) / 4 * 4) * d.m_pad * sizeof(float);
   const int row_tiles = (N + kTileRows - 1) / kTileRows;
   L.col_tiles = (d.m_pad + kTileCols - 1) / kTileCols;
   int P = row_tiles * L.col_tiles;

@@ -70,6 +70,23 @@ __device__ __forceinline__ void bstore(float v, Rsrc r, int voff, int soff) {
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, kCachePolicy);
 }
 
+// The kept iterates (checkpoint and segment slots) are stored in the
+// accumulator's row order: rows 4q .. 4q+3 of one column are 16 contiguous
+// bytes, element (i, j) at float ((i / 4) m_pad + j) 4 + i % 4, so each lane
+// moves the four rows it owns of a column with one 16-byte access. A slot
+// holds N rounded up to a multiple of 4 rows; a tile's slot descriptor starts
+// at row0 (a multiple of 16), the lane's offset is (lg m_pad + col) 16 bytes,
+// the row block's (16 fm + rbase) m_pad 4 bytes goes into soffset.
+__device__ __forceinline__ float4 bload4(Rsrc r, int voff, int soff) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, kCachePolicy));
+}
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void bstore4(float4 v, Rsrc r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, kCachePolicy);
+}
+// Bytes of a tile's slot range: its rows rounded up to whole 4-row groups.
+__device__ __forceinline__ size_t tape_bytes(int nrows, int m_pad) { return (size_t)((nrows + 3) / 4) * m_pad * 16; }
+
 __device__ __forceinline__ float* slot_ptr(const PersistArgs& g, int t) {
   const int k = g.k;
   if (t % k == 0 || t == g.T) return (float*)(g.ckpt + (size_t)((t + k - 1) / k - 1) * g.zbytes);
@@ -272,6 +289,37 @@ __device__ __forceinline__ void load_master(float (&zm)[NP][FM][FB][4], const fl
   }
 }
 
+// Loads this wave's FM row blocks (from row0) of a kept iterate (tape order)
+// into the master registers; 4-row groups past N read as 0 (and the rows
+// past N inside the last group hold 0 on the tape).
+template <int FM, int FB, int NP, int WC>
+__device__ __forceinline__ void load_master_tape(float (&zm)[NP][FM][FB][4], const float* src, int row0, int N,
+                                                 int m_pad, int npass, int wave, int lane) {
+  const int lr = lane & 15, lg = lane >> 4;
+  constexpr int R = FM * 16;
+  const int nrows = (N - row0) < R ? (N - row0) : R;
+  const Rsrc rs = make_rsrc(src + (size_t)row0 * m_pad, tape_bytes(nrows, m_pad));
+  const int rstride = m_pad * 4;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int slab = WC * p + wave;
+    const bool act = p < npass && slab * 16 * FB < m_pad;
+    const int lt = (lg * m_pad + 16 * FB * slab + lr) * 16;
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm) {
+      const bool ok = act && (16 * fm + 4 * lg) < nrows;
+#pragma unroll
+      for (int f = 0; f < FB; ++f) {
+        const float4 q = ok ? bload4(rs, lt + 256 * f, 16 * fm * rstride) : make_float4(0.f, 0.f, 0.f, 0.f);
+        zm[p][fm][f][0] = q.x;
+        zm[p][fm][f][1] = q.y;
+        zm[p][fm][f][2] = q.z;
+        zm[p][fm][f][3] = q.w;
+      }
+    }
+  }
+}
+
 // Forward over layers [t_begin, t_end): z^(t+1) = ST(z^t - a_t (G z^t - c), lam a_t),
 // keeping the tape; with TRACE also F(z^t) for each t. Then, if asked, one
 // more contraction G z^(t_end) for F(z^(t_end)) and the backward seed.
@@ -307,7 +355,7 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
 #pragma unroll
           for (int r4 = 0; r4 < 4; ++r4) zm[p][fm][f][r4] = 0.f;
   } else {
-    load_master<FM, FB, NP, WC>(zm, slot_ptr(g, g.t_begin), row0 + rbase, N, m_pad, npass, wave, lane);
+    load_master_tape<FM, FB, NP, WC>(zm, slot_ptr(g, g.t_begin), row0 + rbase, N, m_pad, npass, wave, lane);
   }
   master_to_lds<P, FM, FB, NP, WC>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
   __syncthreads();
@@ -317,7 +365,7 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
     const float lam = g.lam, th = lam * a;
     const bool store = g.k > 0 && (g.store_all || (t + 1) % g.k == 0 || t + 1 == g.T || t + 1 > g.a_last);
     const Rsrc rD = make_rsrc(store ? slot_ptr(g, t + 1) + (size_t)row0 * m_pad : nullptr,
-                              store ? (size_t)nrows * rstride : 0);
+                              store ? tape_bytes(nrows, m_pad) : 0);
     const bool copy_out = (t + 1 == g.T) && g.Zuser;
     float fs[FM][4];
     if constexpr (TRACE) {
@@ -342,8 +390,10 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
       const int colb = 16 * FB * slab + lr;            // column of block f = 0
       const int lo = (4 * lg * m_pad + colb) * 4;      // per-lane offset, [N][m_pad] buffers
       const int lou = (4 * lg * m + colb) * 4;         // per-lane offset, [N][m] buffers
+      const int lt = (lg * m_pad + colb) * 16;         // per-lane offset, tape order
 #pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
+      for (int fm = 0; fm < FM; ++fm) {
+        // rows past N keep z = 0: c reads as 0 there and so does G z
 #pragma unroll
         for (int r4 = 0; r4 < 4; ++r4) {
           if (rbase + 16 * fm + 4 * lg + r4 >= nrows) continue;
@@ -356,10 +406,16 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
             if constexpr (TRACE) fs[fm][r4] += 0.5f * z * pv - z * c + lam * fabsf(z);
             const float zn = soft_thresh(z - a * (pv - c), th);
             zm[p][fm][f][r4] = zn;
-            if (store) bstore(zn, rD, lo + 64 * f, so);
             if (copy_out && colb + 16 * f < m) bstore(zn, rZu, lou + 64 * f, sou);
           }
         }
+        if (store && rbase + 16 * fm + 4 * lg < nrows) {
+#pragma unroll
+          for (int f = 0; f < FB; ++f)
+            bstore4(make_float4(zm[p][fm][f][0], zm[p][fm][f][1], zm[p][fm][f][2], zm[p][fm][f][3]), rD,
+                    lt + 256 * f, (rbase + 16 * fm) * rstride);
+        }
+      }
     }
     if constexpr (TRACE)
       finish_rows<FM, R, WC>(fs, red, wave, rbase, lane, tid, row0, N, g.xsq, g.Ftrace + (size_t)t * N, nullptr);
@@ -443,21 +499,24 @@ __device__ __forceinline__ void bwd_body(const PersistArgs& g, int tile, char* l
   // For the first layer of the launch, s2 comes from one pass over z^{t_hi+1}.
   double s2 = 0.0;
   {
-    const Rsrc rz1 = make_rsrc(slot_ptr(g, g.t_hi + 1) + (size_t)row0 * m_pad, (size_t)nrows * rstride);
+    const Rsrc rz1 = make_rsrc(slot_ptr(g, g.t_hi + 1) + (size_t)row0 * m_pad, tape_bytes(nrows, m_pad));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       const int slab = WC * p + wave;
       if (!(p < npass && slab * 16 * FB < m_pad)) continue;
-      const int lo = (4 * lg * m_pad + 16 * FB * slab + lr) * 4;
+      const int lt = (lg * m_pad + 16 * FB * slab + lr) * 16;
 #pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
+      for (int fm = 0; fm < FM; ++fm) {
+        if (rbase + 16 * fm + 4 * lg >= nrows) continue;  // rows past N inside a group hold 0
 #pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          if (rbase + 16 * fm + 4 * lg + r4 >= nrows) continue;
-          const int so = (rbase + 16 * fm + r4) * rstride;
-#pragma unroll
-          for (int f = 0; f < FB; ++f) s2 += (double)vm[p][fm][f][r4] * (double)bload(rz1, lo + 64 * f, so);
+        for (int f = 0; f < FB; ++f) {
+          const float4 z1 = bload4(rz1, lt + 256 * f, (rbase + 16 * fm) * rstride);
+          s2 += (double)vm[p][fm][f][0] * (double)z1.x;
+          s2 += (double)vm[p][fm][f][1] * (double)z1.y;
+          s2 += (double)vm[p][fm][f][2] * (double)z1.z;
+          s2 += (double)vm[p][fm][f][3] * (double)z1.w;
         }
+      }
     }
   }
   __syncthreads();
@@ -465,7 +524,7 @@ __device__ __forceinline__ void bwd_body(const PersistArgs& g, int tile, char* l
   for (int t = g.t_hi; t >= g.t_lo; --t) {
     const float a = g.alpha[t];
     const Rsrc rz0 = make_rsrc(t >= 1 ? slot_ptr(g, t) + (size_t)row0 * m_pad : nullptr,
-                               t >= 1 ? (size_t)nrows * rstride : 0);
+                               t >= 1 ? tape_bytes(nrows, m_pad) : 0);
     double dsum = -s2;
     s2 = 0.0;
 #pragma unroll
@@ -474,18 +533,20 @@ __device__ __forceinline__ void bwd_body(const PersistArgs& g, int tile, char* l
       if (!(p < npass && slab * 16 * FB < m_pad)) continue;
       f32x4 acc[FM][FB];
       if (t >= 1) contract<P, FM, FB, PF>(g, lds + rbase * rowb, rowb, slab, lane, acc);
-      const int lo = (4 * lg * m_pad + 16 * FB * slab + lr) * 4;
+      const int lt = (lg * m_pad + 16 * FB * slab + lr) * 16;
+      if (t >= 1) {
 #pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          if (rbase + 16 * fm + 4 * lg + r4 >= nrows) continue;
-          const int so = (rbase + 16 * fm + r4) * rstride;
+        for (int fm = 0; fm < FM; ++fm) {
+          // rows past N: v = 0 and z^t = 0 (on the tape), so they add nothing
+          if (rbase + 16 * fm + 4 * lg >= nrows) continue;
 #pragma unroll
           for (int f = 0; f < FB; ++f) {
-            if (t >= 1) {
+            const float4 z4 = bload4(rz0, lt + 256 * f, (rbase + 16 * fm) * rstride);
+            const float zz[4] = {z4.x, z4.y, z4.z, z4.w};
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
               const float v = vm[p][fm][f][r4];
-              const float z0 = bload(rz0, lo + 64 * f, so);
+              const float z0 = zz[r4];
               dsum += (double)v * (double)z0;
               const float vn = (z0 != 0.f) ? v - a * acc[fm][f][r4] : 0.f;
               vm[p][fm][f][r4] = vn;
@@ -493,6 +554,7 @@ __device__ __forceinline__ void bwd_body(const PersistArgs& g, int tile, char* l
             }
           }
         }
+      }
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) dsum += __shfl_xor(dsum, o);
