@@ -51,16 +51,17 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "769722cf3e2d3691dd56c8fc19a42bab775dbde7c9c384f80bbff67a2639a6c9",
+    "sources_sha256": "416d14b0aea8f4b6452d70f36161d7bfd517dfbcadd1ca4c407ac4dec56eefb8",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {
-        ("bf16", "forward_layer"): (9872745 * 2 + 13751376) * 1024,
-        ("bf16", "backward_layer"): (8114900 * 2 + 622442) * 1024,
-        ("fp32", "forward_layer"): (17608741 * 2 + 13654236) * 1024,
-        ("fp32", "backward_layer"): (14002478 * 2 + 3675) * 1024,
+        ("bf16", "forward_layer"): (9463482 * 2 + 13648651) * 1024,
+        ("bf16", "backward_layer"): (7754830 * 2 + 10011) * 1024,
+        ("fp32", "forward_layer"): (21577470 * 2 + 13635754) * 1024,
+        ("fp32", "backward_layer"): (13324739 * 2 + 3251) * 1024,
     },
 }
+
 KERNEL_SOURCES = ["common.hpp", "persist.hpp", "persist_body.hpp", "kernels_persist.hip",
                   "kernels_persist_bf16.hip", "kernels_persist_f32.hip"]
 
