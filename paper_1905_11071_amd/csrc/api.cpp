@@ -176,13 +176,14 @@ constexpr int kTileCols = 128;  // columns of the fused kernel's workgroup tile
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t C = 0, xsq = 0, Fd = 0, fpart = 0, dpart = 0, pp = 0, ckpt = 0, seg = 0, vbuf = 0;
+  size_t C = 0, Cg = 0, xsq = 0, Fd = 0, fpart = 0, dpart = 0, pp = 0, ckpt = 0, seg = 0, vbuf = 0;
   size_t total = 0;
   size_t zbytes = 0;
   int k = 0, nckpt = 0, nseg = 0, col_tiles = 0, P = 0;
+  bool groups = false;  // Cg is there
 };
 
-Layout make_layout(const slista::Dict& d, int N, int T, int k) {
+Layout make_layout(const slista::Dict& d, int N, int T, int k, bool groups = true) {
   Layout L;
   L.k = k;
   // N rounded up to whole 4-row groups: the persistent kernels keep the
@@ -202,6 +203,8 @@ Layout make_layout(const slista::Dict& d, int N, int T, int k) {
     return o;
   };
   L.C = take(L.zbytes);
+  L.groups = groups;
+  if (groups) L.Cg = take(L.zbytes);  // c in the same row-group order, read by the persistent forward
   L.xsq = take((size_t)N * sizeof(double));
   L.Fd = take((size_t)N * sizeof(double));
   L.fpart = take((size_t)L.col_tiles * N * sizeof(double));
@@ -227,6 +230,7 @@ struct Run {
   hipStream_t s;
 
   float* C() const { return (float*)(ws + L.C); }
+  float* Cg() const { return L.groups ? (float*)(ws + L.Cg) : nullptr; }
   double* xsq() const { return (double*)(ws + L.xsq); }
   double* Fd() const { return (double*)(ws + L.Fd); }
   double* fpart() const { return (double*)(ws + L.fpart); }
@@ -275,6 +279,7 @@ slista::PersistArgs persist_args(const Run& r, int prec, const float* alpha, flo
   a.N = r.N;
   a.m = r.d->m;
   a.C = r.C();
+  a.Cg = r.Cg();
   a.alpha = alpha;
   a.lam = lam;
   a.ckpt = r.ws + r.L.ckpt;
@@ -301,6 +306,8 @@ int fwd_layer(const Run& r, int prec, const float* alpha, float lam, int t, doub
   return SLISTA_OK;
 }
 
+// c = D^T x for every sample (row-major), its norms, and, where the layout
+// has room for it, the row-group copy of c that the persistent forward reads.
 int prep(const Run& r, const float* X) {
   slista::GemmArgs g;
   std::memset(&g, 0, sizeof g);
@@ -315,6 +322,7 @@ int prep(const Run& r, const float* X) {
   g.ldz = r.d->m_pad;
   slista::gemm_grid(r.N, r.d->m_pad, g);
   LAUNCH(kKCorr, r.s, slista::launch_gemm(slista::kF32, slista::kEpiCorr, true, g, r.s));
+  if (r.L.groups) LAUNCH(kKOther, r.s, slista::launch_row_groups(r.C(), r.N, r.d->m_pad, r.Cg(), r.s));
   LAUNCH(kKOther, r.s, slista::launch_xsq(X, r.N, r.d->n, r.xsq(), r.s));
   return SLISTA_OK;
 }
@@ -1148,7 +1156,7 @@ int slista_forward_backward(const slista_dict* dict, const float* X, int N, floa
 // Workspace of slista_fista: the forward workspace without a tape (C, norms,
 // objective partials, two z buffers), two y buffers and the momentum weights.
 static size_t fista_offsets(const slista::Dict& d, int N, int T, size_t off[2]) {
-  const Layout L = make_layout(d, N, T, 0);
+  const Layout L = make_layout(d, N, T, 0, false);
   size_t o = align256(L.total);
   off[0] = o;  // y buffers
   o += 2 * align256(L.zbytes);
@@ -1180,7 +1188,7 @@ int slista_fista(const slista_dict* dict, const float* X, int N, float lambda, c
     if (loss) LAUNCH(kKOther, s, slista::launch_fill(loss, 1, 0.f, s));
     return SLISTA_OK;
   }
-  const Run r{&dict->d, make_layout(dict->d, N, T, 0), (char*)ws, N, T, s};
+  const Run r{&dict->d, make_layout(dict->d, N, T, 0, false), (char*)ws, N, T, s};
   const int mp = dict->d.m_pad;
   if (T == 0) return run_forward(r, X, lambda, alpha, prec, Z, F, 0, loss, true);  // Z = 0, F = |x|^2 / 2
   if ((st = prep(r, X)) != SLISTA_OK) return st;
@@ -1223,7 +1231,7 @@ int slista_fista(const slista_dict* dict, const float* X, int N, float lambda, c
 // objective partials reused as violation counts, two z buffers), the
 // gradient R [N, m_pad], the warm-start vectors V [N, m_pad], the steps [N].
 static size_t oista_offsets(const slista::Dict& d, int N, int T, size_t off[3]) {
-  const Layout L = make_layout(d, N, T, 0);
+  const Layout L = make_layout(d, N, T, 0, false);
   size_t o = align256(L.total);
   off[0] = o;  // R
   o += align256(L.zbytes);
@@ -1264,7 +1272,7 @@ int slista_oista(const slista_dict* dict, const float* X, int N, float lambda, d
     if (loss) LAUNCH(kKOther, s, slista::launch_fill(loss, 1, 0.f, s));
     return SLISTA_OK;
   }
-  const Run r{&dict->d, make_layout(dict->d, N, T, 0), (char*)ws, N, T, s};
+  const Run r{&dict->d, make_layout(dict->d, N, T, 0, false), (char*)ws, N, T, s};
   if (T == 0) return run_forward(r, X, lambda, nullptr, prec, Z, F, 0, loss, true);
   const int mp = dict->d.m_pad;
   float* R = (float*)((char*)ws + off[0]);

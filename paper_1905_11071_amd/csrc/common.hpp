@@ -96,6 +96,9 @@ hipError_t launch_layer0(const float* C, int N, int ldz, const float* alpha, flo
                          hipStream_t s);
 hipError_t launch_copy_out(const float* Zs, int N, int ldz, int m, float* Z, hipStream_t s);
 hipError_t launch_fill(float* p, size_t count, float v, hipStream_t s);
+// out[((i/4) ld + j) 4 + i%4] = A[i ld + j] for i < 4 ceil(N/4) (0 past N);
+// out holds ceil(N/4) 4 ld floats, 16-byte aligned.
+hipError_t launch_row_groups(const float* A, int N, int ld, float* out, hipStream_t s);
 hipError_t launch_reduce_f(const double* xsq, const double* fpart, int col_tiles, int N, float* F,
                            double* Fd, hipStream_t s);
 hipError_t launch_reduce_loss(const double* Fd, int N, float* loss, hipStream_t s);

@@ -178,6 +178,25 @@ __global__ void k_fill(float* __restrict__ p, size_t count, float v) {
     p[e] = v;
 }
 
+// Row-group copy of a [N][ld] matrix: the four rows 4q..4q+3 of column j go
+// to the 16 bytes at float (q ld + j) 4, rows past N as 0 (the order of the
+// persistent kernels' accumulator, so a lane reads its four rows at once).
+// One thread per (group, column): coalesced reads of four rows, coalesced
+// 16-byte writes.
+__global__ void k_row_groups(const float* __restrict__ A, int N, int ld, float4* __restrict__ out) {
+  const size_t ng = (size_t)(N + 3) / 4, total = ng * ld;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t q = e / ld;
+    const int j = (int)(e - q * ld), i = (int)(4 * q);
+    float4 v;
+    v.x = A[(size_t)i * ld + j];
+    v.y = i + 1 < N ? A[(size_t)(i + 1) * ld + j] : 0.f;
+    v.z = i + 2 < N ? A[(size_t)(i + 2) * ld + j] : 0.f;
+    v.w = i + 3 < N ? A[(size_t)(i + 3) * ld + j] : 0.f;
+    out[e] = v;
+  }
+}
+
 // F_i = 1/2 ||x_i||^2 + sum over column tiles of the fused partials
 // (1/2 z.Gz - z.c + lam |z|), i.e. Eq. (1) in Gram form.
 __global__ void k_reduce_f(const double* __restrict__ xsq, const double* __restrict__ fpart,
@@ -517,6 +536,13 @@ hipError_t launch_copy_out(const float* Zs, int N, int ldz, int m, float* Z, hip
   const size_t total = (size_t)N * m;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_out, dim3(grid_for(total, 256 * 8)), dim3(256), 0, s, Zs, N, ldz, m, Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_groups(const float* A, int N, int ld, float* out, hipStream_t s) {
+  const size_t total = (size_t)(N + 3) / 4 * ld;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_groups, dim3(grid_for(total, 256 * 4)), dim3(256), 0, s, A, N, ld, (float4*)out);
   return hipGetLastError();
 }
 

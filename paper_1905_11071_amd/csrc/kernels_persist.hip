@@ -90,6 +90,7 @@ int persist_rows(int prec, int m_pad, int variant) {
 // prefetch depth, waves per SIMD bound, row waves, column waves.
 
 hipError_t launch_persist(bool fwd, int prec, const PersistArgs& a, hipStream_t s, int variant) {
+  if (fwd && a.N > 0 && !a.Cg) return hipErrorInvalidValue;  // the forward reads c in row-group order
   const int np = np_of(a.m_pad);
   variant = persist_resolve_variant(prec, a.m_pad, variant);
   return prec == kBF16 ? launch_persist_bf16(fwd, np, variant, a, s) : launch_persist_f32(fwd, np, variant, a, s);

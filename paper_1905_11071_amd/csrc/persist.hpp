@@ -16,6 +16,7 @@ struct PersistArgs {
   int m_pad, KC;      // KC = number of 64-byte K steps per row
   int N, m;
   const float* C;     // [N][m_pad]
+  const float* Cg;    // the same c in row-group order (as the tape), read every layer
   const float* alpha;
   float lam;
   // where z^t lives (see the workspace layout in api.cpp)

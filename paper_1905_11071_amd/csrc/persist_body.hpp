@@ -342,6 +342,7 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
   const int ustride = m * 4;          // bytes per row of the caller's [N][m] buffers
   float* red = (float*)(lds + R * rowb);
   const Rsrc rC = make_rsrc(g.C + (size_t)row0 * m_pad, (size_t)nrows * rstride);
+  const Rsrc rCg = make_rsrc(g.Cg + (size_t)row0 * m_pad, tape_bytes(nrows, m_pad));
   const Rsrc rZu = make_rsrc(g.Zuser ? g.Zuser + (size_t)row0 * m : nullptr, g.Zuser ? (size_t)nrows * ustride : 0);
 
   float zm[NP][FM][FB][4];
@@ -388,20 +389,30 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
           for (int f = 0; f < FB; ++f) acc[fm][f] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
       const int colb = 16 * FB * slab + lr;            // column of block f = 0
-      const int lo = (4 * lg * m_pad + colb) * 4;      // per-lane offset, [N][m_pad] buffers
       const int lou = (4 * lg * m + colb) * 4;         // per-lane offset, [N][m] buffers
       const int lt = (lg * m_pad + colb) * 16;         // per-lane offset, tape order
 #pragma unroll
       for (int fm = 0; fm < FM; ++fm) {
-        // rows past N keep z = 0: c reads as 0 there and so does G z
+        // c of this lane's four rows, one 16-byte load per column block;
+        // rows past N keep z = 0 (their c is stored as 0, and G z is 0)
+        const bool grp = rbase + 16 * fm + 4 * lg < nrows;
+        float cg[FB][4];
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+          const float4 q = grp ? bload4(rCg, lt + 256 * f, (rbase + 16 * fm) * rstride) : make_float4(0.f, 0.f, 0.f, 0.f);
+          cg[f][0] = q.x;
+          cg[f][1] = q.y;
+          cg[f][2] = q.z;
+          cg[f][3] = q.w;
+        }
 #pragma unroll
         for (int r4 = 0; r4 < 4; ++r4) {
           if (rbase + 16 * fm + 4 * lg + r4 >= nrows) continue;
-          const int so = (rbase + 16 * fm + r4) * rstride, sou = (rbase + 16 * fm + r4) * ustride;
+          const int sou = (rbase + 16 * fm + r4) * ustride;
 #pragma unroll
           for (int f = 0; f < FB; ++f) {
             const float z = zm[p][fm][f][r4];
-            const float c = bload(rC, lo + 64 * f, so);
+            const float c = cg[f][r4];
             const float pv = acc[fm][f][r4];
             if constexpr (TRACE) fs[fm][r4] += 0.5f * z * pv - z * c + lam * fabsf(z);
             const float zn = soft_thresh(z - a * (pv - c), th);
