@@ -51,14 +51,14 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "416d14b0aea8f4b6452d70f36161d7bfd517dfbcadd1ca4c407ac4dec56eefb8",
+    "sources_sha256": "74d78683f8c8e3d19dc123d91440b38415468f1b137e1705f3bddac8a3c5674f",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {
-        ("bf16", "forward_layer"): (9463482 * 2 + 13648651) * 1024,
-        ("bf16", "backward_layer"): (7754830 * 2 + 10011) * 1024,
-        ("fp32", "forward_layer"): (21577470 * 2 + 13635754) * 1024,
-        ("fp32", "backward_layer"): (13324739 * 2 + 3251) * 1024,
+        ("bf16", "forward_layer"): (8332217 * 2 + 13648640) * 1024,
+        ("bf16", "backward_layer"): (7704534 * 2 + 10057) * 1024,
+        ("fp32", "forward_layer"): (14918036 * 2 + 13634021) * 1024,
+        ("fp32", "backward_layer"): (13366940 * 2 + 3257) * 1024,
     },
 }
 
