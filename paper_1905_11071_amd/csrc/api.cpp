@@ -278,7 +278,6 @@ slista::PersistArgs persist_args(const Run& r, int prec, const float* alpha, flo
   a.KC = r.d->m_pad * (prec == slista::kF32 ? 4 : 2) / 64;
   a.N = r.N;
   a.m = r.d->m;
-  a.C = r.C();
   a.Cg = r.Cg();
   a.alpha = alpha;
   a.lam = lam;

@@ -209,20 +209,37 @@ __global__ void k_reduce_f(const double* __restrict__ xsq, const double* __restr
   if (Fd) Fd[i] = s;
 }
 
-__global__ void k_reduce_loss(const double* __restrict__ Fd, int N, float* __restrict__ loss) {
-  __shared__ double sh[kRedThreads];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) s += Fd[i];
-  s = block_sum(s, sh);
+// Sum of Fd[0..N) by one workgroup of kSumThreads: each thread keeps eight
+// partial sums over a fixed stride pattern (eight loads in flight), then a
+// tree over the workgroup; the order depends on N alone.
+constexpr int kSumThreads = 1024;
+__device__ double sum_fixed(const double* __restrict__ Fd, int N, double* sh) {
+  double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int i = threadIdx.x;
+  for (; i + 7 * kSumThreads < N; i += 8 * kSumThreads) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) p[u] += Fd[i + u * kSumThreads];
+  }
+  // fewer than eight strides remain
+#pragma unroll
+  for (int u = 0; u < 7; ++u)
+    if (i + u * kSumThreads < N) p[u] += Fd[i + u * kSumThreads];
+  const double v = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+  return block_sum(v, sh);
+}
+
+__global__ __launch_bounds__(kSumThreads) void k_reduce_loss(const double* __restrict__ Fd, int N,
+                                                             float* __restrict__ loss) {
+  __shared__ double sh[kSumThreads];
+  const double s = sum_fixed(Fd, N, sh);
   if (threadIdx.x == 0) *loss = N > 0 ? (float)(s / N) : 0.f;
 }
 
 // Mean of the per-sample objectives in FP64 (the training loop's loss).
-__global__ void k_mean_d(const double* __restrict__ Fd, int N, double* __restrict__ out) {
-  __shared__ double sh[kRedThreads];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) s += Fd[i];
-  s = block_sum(s, sh);
+__global__ __launch_bounds__(kSumThreads) void k_mean_d(const double* __restrict__ Fd, int N,
+                                                        double* __restrict__ out) {
+  __shared__ double sh[kSumThreads];
+  const double s = sum_fixed(Fd, N, sh);
   if (threadIdx.x == 0) *out = N > 0 ? s / N : 0.0;
 }
 
@@ -560,12 +577,12 @@ hipError_t launch_reduce_f(const double* xsq, const double* fpart, int col_tiles
 }
 
 hipError_t launch_reduce_loss(const double* Fd, int N, float* loss, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(kRedThreads), 0, s, Fd, N, loss);
+  hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(kSumThreads), 0, s, Fd, N, loss);
   return hipGetLastError();
 }
 
 hipError_t launch_mean_d(const double* Fd, int N, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_mean_d, dim3(1), dim3(kRedThreads), 0, s, Fd, N, out);
+  hipLaunchKernelGGL(k_mean_d, dim3(1), dim3(kSumThreads), 0, s, Fd, N, out);
   return hipGetLastError();
 }
 

@@ -15,8 +15,7 @@ struct PersistArgs {
   const void* Gsw;    // fragment-ordered G (BF16 or FP32)
   int m_pad, KC;      // KC = number of 64-byte K steps per row
   int N, m;
-  const float* C;     // [N][m_pad]
-  const float* Cg;    // the same c in row-group order (as the tape), read every layer
+  const float* Cg;    // c = D^T x in row-group order (as the tape), read every layer
   const float* alpha;
   float lam;
   // where z^t lives (see the workspace layout in api.cpp)

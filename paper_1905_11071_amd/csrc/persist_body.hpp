@@ -341,7 +341,6 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
   const int rstride = m_pad * 4;      // bytes per row of the [N][m_pad] buffers
   const int ustride = m * 4;          // bytes per row of the caller's [N][m] buffers
   float* red = (float*)(lds + R * rowb);
-  const Rsrc rC = make_rsrc(g.C + (size_t)row0 * m_pad, (size_t)nrows * rstride);
   const Rsrc rCg = make_rsrc(g.Cg + (size_t)row0 * m_pad, tape_bytes(nrows, m_pad));
   const Rsrc rZu = make_rsrc(g.Zuser ? g.Zuser + (size_t)row0 * m : nullptr, g.Zuser ? (size_t)nrows * ustride : 0);
 
@@ -456,8 +455,19 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
     const int colb = 16 * FB * slab + lr;
     const int lo = (4 * lg * m_pad + colb) * 4;
     const int lou = (4 * lg * m + colb) * 4;
+    const int lt = (lg * m_pad + colb) * 16;
 #pragma unroll
-    for (int fm = 0; fm < FM; ++fm)
+    for (int fm = 0; fm < FM; ++fm) {
+      const bool grp = rbase + 16 * fm + 4 * lg < nrows;
+      float cg[FB][4];
+#pragma unroll
+      for (int f = 0; f < FB; ++f) {
+        const float4 q = grp ? bload4(rCg, lt + 256 * f, (rbase + 16 * fm) * rstride) : make_float4(0.f, 0.f, 0.f, 0.f);
+        cg[f][0] = q.x;
+        cg[f][1] = q.y;
+        cg[f][2] = q.z;
+        cg[f][3] = q.w;
+      }
 #pragma unroll
       for (int r4 = 0; r4 < 4; ++r4) {
         const int rl = rbase + 16 * fm + 4 * lg + r4;
@@ -467,7 +477,7 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
 #pragma unroll
         for (int f = 0; f < FB; ++f) {
           const float z = zm[p][fm][f][r4];
-          const float c = bload(rC, lo + 64 * f, so);
+          const float c = cg[f][r4];
           const float pv = acc[fm][f][r4];
           if (want_f) fs[fm][r4] += 0.5f * z * pv - z * c + lam * fabsf(z);
           if (seed) {
@@ -477,6 +487,7 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
           }
         }
       }
+    }
   }
   if (want_f) finish_rows<FM, R, WC>(fs, red, wave, rbase, lane, tid, row0, N, g.xsq, g.F, g.Fd);
 }
