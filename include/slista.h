@@ -248,7 +248,10 @@ SLISTA_API int slista_batch_destroy(slista_batch* batch);
  *     per-layer kernels (one fused contraction launch per layer);
  *   1 always the per-layer kernels;
  *   2 the persistent kernels where they apply.
- * Both families compute bitwise-identical iterates and step-size gradients.
+ * Both families compute bitwise-identical iterates and step-size gradients,
+ * but keep the forward's tape in different layouts (per-layer: row-major;
+ * persistent: four rows of a column together), so a slista_backward call
+ * must run under the family of the slista_forward call that left its tape.
  * ------------------------------------------------------------------------- */
 #define SLISTA_OPT_KERNEL_FAMILY 1
 /* SLISTA_OPT_PERSIST_VARIANT: tile configuration of the persistent kernels.
