@@ -51,14 +51,14 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "74d78683f8c8e3d19dc123d91440b38415468f1b137e1705f3bddac8a3c5674f",
+    "sources_sha256": "59d03b0176f71ec9ab964964fd1c0da5a58ec42b0220f5768edafb259088ea32",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {
-        ("bf16", "forward_layer"): (8332217 * 2 + 13648640) * 1024,
-        ("bf16", "backward_layer"): (7704534 * 2 + 10057) * 1024,
-        ("fp32", "forward_layer"): (14918036 * 2 + 13634021) * 1024,
-        ("fp32", "backward_layer"): (13366940 * 2 + 3257) * 1024,
+        ("bf16", "forward_layer"): (8398386 * 2 + 13650688) * 1024,
+        ("bf16", "backward_layer"): (7841569 * 2 + 10088) * 1024,
+        ("fp32", "forward_layer"): (14609746 * 2 + 13634196) * 1024,
+        ("fp32", "backward_layer"): (13592609 * 2 + 3251) * 1024,
     },
 }
 
