@@ -155,6 +155,25 @@ SLISTA_API int slista_forward(const slista_dict* dict, const float* X, int N, fl
                               const float* alpha, int T, int prec, float* Z, float* F, int f_trace,
                               float* loss, int ckpt_every, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the forward
+ * pass of slista_forward with ckpt_every = 0 (no tape), whose workspace is a
+ * static array of 64 MiB (67108864 bytes) inside the library instead of a
+ * caller buffer. The caller still passes X, alpha and the outputs Z, F, loss
+ * (as for slista_forward). Each GPU the library runs on holds its own copy of
+ * that array from the first call on it until the process ends; the call
+ * neither allocates nor frees device memory. Sizes whose forward workspace
+ * (slista_workspace_size with ckpt_every = 0) exceeds 64 MiB are rejected
+ * with SLISTA_EINVAL (e.g. m = 1024 allows N up to about 4000; m = 256 about
+ * 16000). The current device must be the dictionary's, and kernel timing
+ * (slista_profile_begin) must be off. Every call on a GPU shares that GPU's
+ * array, so calls that overlap on one GPU (on different streams or threads)
+ * race; calls ordered on one stream do not. Nothing in the array needs to
+ * start at zero: the pass overwrites everything it reads. */
+SLISTA_API int slista_forward_scratch(const slista_dict* dict, const float* X, int N, float lambda,
+                                      const float* alpha, int T, int prec, float* Z, float* F, int f_trace,
+                                      float* loss, void* stream);
+
 /* Lasso cost of given codes, Eq. (1): F[i] = 1/2 ||x_i - D z_i||^2 + lambda ||z_i||_1
  * for Z (device FP32 [N, m]), written to F (device FP32 [N]). The residual is
  * formed in FP32 from the non-zero coordinates of z_i (one wave per sample,

@@ -35,6 +35,8 @@ SIGNATURES = {
     "slista_forward": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _vp, _vp, _c_int, _vp,
                                 _c_int, _vp, _size_t, _vp]),
     "slista_objective": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _vp, _vp]),
+    "slista_forward_scratch": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _vp, _vp, _c_int, _vp,
+                                        _vp]),
     "slista_backward": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _vp, _vp, _vp, _c_int,
                                  _vp, _size_t, _vp]),
     "slista_forward_backward": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _c_int, _c_int, _vp, _vp, _vp,
@@ -84,7 +86,7 @@ class Problem(ctypes.Structure):
 
 
 STATUS = {0: "SLISTA_OK", -1: "SLISTA_EINVAL", -2: "SLISTA_ENOMEM", -3: "SLISTA_EHIP",
-          -4: "SLISTA_ENOTSUP", -5: "SLISTA_ENOTCONV"}
+          -4: "SLISTA_ENOTSUP", -5: "SLISTA_ENOTCONV", -6: "SLISTA_ENONFINITE"}
 
 
 class SlistaError(RuntimeError):

@@ -881,6 +881,39 @@ int lista_backward_run(const ListaRun& r, float lam, const float* alpha, const f
 
 }  // namespace
 
+// Static per-device scratch of slista_forward_scratch (for callers that cannot
+// allocate device memory): the workspace of a forward pass without a tape.
+// Each GPU the library runs on holds one copy of this array until the process
+// ends. Host code never passes the array's name to a kernel (on the host it is
+// only a stand-in for the symbol): it uses the device address obtained with
+// hipGetSymbolAddress once per device, with that device current.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device).
+int scratch_ptr(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(SLISTA_EINVAL, "device %d outside [0, %d)", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SLISTA_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SLISTA_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int slista_abi_version(void) { return SLISTA_ABI_VERSION; }
@@ -1092,6 +1125,25 @@ int slista_forward(const slista_dict* dict, const float* X, int N, float lambda,
   if (N == 0) return SLISTA_OK;
   Run r{&dict->d, make_layout(dict->d, N, T, ckpt_every), (char*)ws, N, T, (hipStream_t)stream};
   return run_forward(r, X, lambda, alpha, prec, Z, F, f_trace, loss, true);
+}
+
+int slista_forward_scratch(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha,
+                           int T, int prec, float* Z, float* F, int f_trace, float* loss, void* stream) {
+  if (!dict) return fail(SLISTA_EINVAL, "dict is NULL");
+  if (g_prof.on) return fail(SLISTA_EINVAL, "kernel timing creates HIP events; switch it off for this entry point");
+  if (N < 0 || N > kMaxN || T < 0 || T > kMaxT) return fail(SLISTA_EINVAL, "N=%d or T=%d out of range", N, T);
+  const size_t need = make_layout(dict->d, N, T, 0).total;
+  if (need > kScratchBytes)
+    return fail(SLISTA_EINVAL, "N=%d, m_pad=%d needs %zu bytes of scratch; the static scratch holds %zu bytes", N,
+                dict->d.m_pad, need, kScratchBytes);
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != dict->d.device)
+    return fail(SLISTA_EINVAL, "the current device (%d) is not the dictionary's (%d)", dev, dict->d.device);
+  void* ws = nullptr;
+  const int st = scratch_ptr(dev, &ws);
+  if (st != SLISTA_OK) return st;
+  return slista_forward(dict, X, N, lambda, alpha, T, prec, Z, F, f_trace, loss, 0, ws, kScratchBytes, stream);
 }
 
 int slista_objective(const slista_dict* dict, const float* X, int N, float lambda, const float* Z, float* F,
