@@ -11,6 +11,7 @@ from .slista import (  # noqa: F401
     objective,
     forward,
     forward_backward,
+    adjoint,
     kkt_residual,
     lasso_solution,
     brute_force_lasso,

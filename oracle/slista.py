@@ -29,6 +29,7 @@ __all__ = [
     "objective",
     "forward",
     "forward_backward",
+    "adjoint",
     "kkt_residual",
     "lasso_solution",
     "brute_force_lasso",
@@ -124,7 +125,7 @@ def forward(D, X, lam, alpha, return_iterates: bool = False):
     return Z, F
 
 
-def forward_backward(D, X, lam, alpha, dZ=None, dF=None) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+def forward_backward(D, X, lam, alpha, dZ=None, dF=None, return_adjoints: bool = False):
     """Forward pass plus the reverse-mode derivative with respect to the steps.
 
     The scalar differentiated is J = sum_i dF_i F_{x_i}(z_i^(T)) + <dZ, Z^(T)>.
@@ -141,13 +142,34 @@ def forward_backward(D, X, lam, alpha, dZ=None, dF=None) -> Tuple[np.ndarray, np
         dJ/dalpha_t = - sum v * (D^T (D z^(t) - x) + lam sign u)
         g        = v - alpha_t D^T D v       (back through the linear step)
 
-    Returns (Z^(T), F [T+1, N], dalpha [T]). Pinned against central finite
-    differences of `forward` and against the closed form for T = 1.
+    Returns (Z^(T), F [T+1, N], dalpha [T]); with return_adjoints also the
+    iterates [z^(0) .. z^(T)] and the masked adjoints [v^(0) .. v^(T-1)]
+    (v^(t) = g * M at layer t). Pinned against central finite differences of
+    `forward` and against the closed form for T = 1.
     """
     D, X = _f64(D), _f64(X)
     alpha = _f64(alpha).reshape(-1)
-    N, m = X.shape[0], D.shape[1]
     Z, F, iterates = forward(D, X, lam, alpha, return_iterates=True)
+    dalpha, adjoints = adjoint(D, X, lam, alpha, iterates, dZ=dZ, dF=dF)
+    if return_adjoints:
+        return Z, F, dalpha, iterates, adjoints
+    return Z, F, dalpha
+
+
+def adjoint(D, X, lam, alpha, iterates, dZ=None, dF=None):
+    """The reverse pass of `forward_backward` along given iterates
+    z^(0) .. z^(T) (each [N, m]): the same recursion, with z^(t) taken from
+    `iterates` instead of recomputed. Along the oracle's own iterates it is
+    forward_backward's derivative; along iterates computed elsewhere (in
+    another precision) it is the exact derivative of J at that trajectory's
+    layers, which separates the error of a reverse pass from the error of
+    the forward pass that fed it. Returns (dalpha [T], the masked adjoints
+    [v^(0) .. v^(T-1)])."""
+    D, X = _f64(D), _f64(X)
+    alpha = _f64(alpha).reshape(-1)
+    iterates = [_f64(z) for z in iterates]
+    N, m = X.shape[0], D.shape[1]
+    Z = iterates[len(alpha)]
     if dZ is None and dF is None:
         raise ValueError("forward_backward needs dZ and/or dF")
     g = np.zeros((N, m)) if dZ is None else _f64(dZ).copy()
@@ -156,6 +178,7 @@ def forward_backward(D, X, lam, alpha, dZ=None, dF=None) -> Tuple[np.ndarray, np
         grad_T = (Z @ D.T - X) @ D
         g = g + dF[:, None] * (grad_T + lam * np.sign(Z))
     dalpha = np.zeros_like(alpha)
+    adjoints = [None] * len(alpha)
     for t in range(len(alpha) - 1, -1, -1):
         a = alpha[t]
         Zt = iterates[t]
@@ -164,8 +187,9 @@ def forward_backward(D, X, lam, alpha, dZ=None, dF=None) -> Tuple[np.ndarray, np
         M = np.abs(U) > lam * a
         v = np.where(M, g, 0.0)
         dalpha[t] = -np.sum(v * (grad + lam * np.sign(U)))
+        adjoints[t] = v
         g = v - a * ((v @ D.T) @ D)
-    return Z, F, dalpha
+    return dalpha, adjoints
 
 
 def kkt_residual(D, X, Z, lam) -> np.ndarray:

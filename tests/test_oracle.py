@@ -391,3 +391,23 @@ def test_lista_fixed_point_iff_aligned_lemma43():
     W = D.copy()
     W[:, j] += 0.5 * rng.standard_normal(D.shape[0])
     assert np.max(np.abs(oracle.lista_layer(D, X, lam, Z, W, 0.3, 0.3) - Z)) > 1e-3
+
+
+def test_adjoint_along_its_own_iterates_is_forward_backward():
+    """The reverse pass along given iterates reproduces forward_backward's
+    derivative along the oracle's own trajectory (whose finite-difference and
+    closed-form pins above then pin it), and its adjoints are the masked
+    vectors the recursion multiplies by the layers' Jacobians."""
+    pb = pins.small_problem(N=40)
+    alpha = synth.perturbed_steps(oracle.lipschitz(pb.D), 7, seed=3)
+    dF = np.full(pb.N, 1.0 / pb.N)
+    _, _, da, its, adj = oracle.forward_backward(pb.D, pb.X, pb.lam, alpha, dF=dF, return_adjoints=True)
+    da2, adj2 = oracle.adjoint(pb.D, pb.X, pb.lam, alpha, its, dF=dF)
+    assert np.array_equal(da, da2)
+    assert all(np.array_equal(a, b) for a, b in zip(adj, adj2))
+    # the last adjoint is the seed restricted to the last layer's mask
+    Z = its[-1]
+    seed = dF[:, None] * ((Z @ pb.D.T - pb.X) @ pb.D + pb.lam * np.sign(Z))
+    a = alpha[-1]
+    U = its[-2] - a * ((its[-2] @ pb.D.T - pb.X) @ pb.D)
+    np.testing.assert_array_equal(adj[-1], np.where(np.abs(U) > pb.lam * a, seed, 0.0))
