@@ -87,7 +87,7 @@ def objective(D, X, Z, lam) -> np.ndarray:
     return 0.5 * np.sum(R * R, axis=1) + lam * np.sum(np.abs(Z), axis=1)
 
 
-def forward(D, X, lam, alpha, return_iterates: bool = False):
+def forward(D, X, lam, alpha, return_iterates: bool = False, dtype=np.float64):
     """T layers of Step-LISTA / proximal gradient with a step sequence.
 
     z^(0) = 0 and z^(t+1) = ST(z^(t) - alpha_t D^T (D z^(t) - x), lam alpha_t)
@@ -106,17 +106,22 @@ def forward(D, X, lam, alpha, return_iterates: bool = False):
     exact zeros when lam >= lambda_max (Section 2), one-step convergence for
     an orthogonal dictionary (Section 3, after Prop. 3.2), KKT at
     convergence (Lemma 2.1) and the Lemma 4.2 closed-form solution.
+
+    dtype: the type every array of the recursion is held in. float64 is the
+    oracle; float32 runs the same recursion with 32-bit rounding (the
+    objective trace is still evaluated in float64), which the tests use as a
+    measured rounding floor for 32-bit results, never as a reference.
     """
-    D, X = _f64(D), _f64(X)
-    alpha = _f64(alpha).reshape(-1)
+    D, X = np.asarray(D, dtype), np.asarray(X, dtype)
+    alpha = np.asarray(alpha, dtype).reshape(-1)
     N, m = X.shape[0], D.shape[1]
-    Z = np.zeros((N, m))
+    Z = np.zeros((N, m), dtype)
     iterates = [Z]
     trace = [objective(D, X, Z, lam)]
     for a in alpha:
         R = Z @ D.T - X                      # D z - x, per sample
         U = Z - a * (R @ D)                  # z - alpha D^T (D z - x)
-        Z = soft_threshold(U, lam * a)
+        Z = soft_threshold(U, a * dtype(lam)).astype(dtype)
         iterates.append(Z)
         trace.append(objective(D, X, Z, lam))
     F = np.stack(trace)
@@ -125,7 +130,7 @@ def forward(D, X, lam, alpha, return_iterates: bool = False):
     return Z, F
 
 
-def forward_backward(D, X, lam, alpha, dZ=None, dF=None, return_adjoints: bool = False):
+def forward_backward(D, X, lam, alpha, dZ=None, dF=None, return_adjoints: bool = False, dtype=np.float64):
     """Forward pass plus the reverse-mode derivative with respect to the steps.
 
     The scalar differentiated is J = sum_i dF_i F_{x_i}(z_i^(T)) + <dZ, Z^(T)>.
@@ -145,18 +150,17 @@ def forward_backward(D, X, lam, alpha, dZ=None, dF=None, return_adjoints: bool =
     Returns (Z^(T), F [T+1, N], dalpha [T]); with return_adjoints also the
     iterates [z^(0) .. z^(T)] and the masked adjoints [v^(0) .. v^(T-1)]
     (v^(t) = g * M at layer t). Pinned against central finite differences of
-    `forward` and against the closed form for T = 1.
+    `forward` and against the closed form for T = 1. dtype as in `forward`
+    (dalpha is summed in float64 either way).
     """
-    D, X = _f64(D), _f64(X)
-    alpha = _f64(alpha).reshape(-1)
-    Z, F, iterates = forward(D, X, lam, alpha, return_iterates=True)
-    dalpha, adjoints = adjoint(D, X, lam, alpha, iterates, dZ=dZ, dF=dF)
+    Z, F, iterates = forward(D, X, lam, alpha, return_iterates=True, dtype=dtype)
+    dalpha, adjoints = adjoint(D, X, lam, alpha, iterates, dZ=dZ, dF=dF, dtype=dtype)
     if return_adjoints:
         return Z, F, dalpha, iterates, adjoints
     return Z, F, dalpha
 
 
-def adjoint(D, X, lam, alpha, iterates, dZ=None, dF=None):
+def adjoint(D, X, lam, alpha, iterates, dZ=None, dF=None, dtype=np.float64):
     """The reverse pass of `forward_backward` along given iterates
     z^(0) .. z^(T) (each [N, m]): the same recursion, with z^(t) taken from
     `iterates` instead of recomputed. Along the oracle's own iterates it is
@@ -164,20 +168,21 @@ def adjoint(D, X, lam, alpha, iterates, dZ=None, dF=None):
     another precision) it is the exact derivative of J at that trajectory's
     layers, which separates the error of a reverse pass from the error of
     the forward pass that fed it. Returns (dalpha [T], the masked adjoints
-    [v^(0) .. v^(T-1)])."""
-    D, X = _f64(D), _f64(X)
-    alpha = _f64(alpha).reshape(-1)
-    iterates = [_f64(z) for z in iterates]
+    [v^(0) .. v^(T-1)]). dtype as in `forward`."""
+    D, X = np.asarray(D, dtype), np.asarray(X, dtype)
+    alpha = np.asarray(alpha, dtype).reshape(-1)
+    lam = dtype(lam)
+    iterates = [np.asarray(z, dtype) for z in iterates]
     N, m = X.shape[0], D.shape[1]
     Z = iterates[len(alpha)]
     if dZ is None and dF is None:
         raise ValueError("forward_backward needs dZ and/or dF")
-    g = np.zeros((N, m)) if dZ is None else _f64(dZ).copy()
+    g = np.zeros((N, m), dtype) if dZ is None else np.array(dZ, dtype)
     if dF is not None:
-        dF = _f64(dF).reshape(-1)
+        dF = np.asarray(dF, dtype).reshape(-1)
         grad_T = (Z @ D.T - X) @ D
         g = g + dF[:, None] * (grad_T + lam * np.sign(Z))
-    dalpha = np.zeros_like(alpha)
+    dalpha = np.zeros(len(alpha))
     adjoints = [None] * len(alpha)
     for t in range(len(alpha) - 1, -1, -1):
         a = alpha[t]
@@ -185,8 +190,8 @@ def adjoint(D, X, lam, alpha, iterates, dZ=None, dF=None):
         grad = (Zt @ D.T - X) @ D            # D^T (D z^(t) - x)
         U = Zt - a * grad
         M = np.abs(U) > lam * a
-        v = np.where(M, g, 0.0)
-        dalpha[t] = -np.sum(v * (grad + lam * np.sign(U)))
+        v = np.where(M, g, dtype(0))
+        dalpha[t] = -np.sum(v * (grad + lam * np.sign(U)), dtype=np.float64)
         adjoints[t] = v
         g = v - a * ((v @ D.T) @ D)
     return dalpha, adjoints

@@ -411,3 +411,20 @@ def test_adjoint_along_its_own_iterates_is_forward_backward():
     a = alpha[-1]
     U = its[-2] - a * ((its[-2] @ pb.D.T - pb.X) @ pb.D)
     np.testing.assert_array_equal(adj[-1], np.where(np.abs(U) > pb.lam * a, seed, 0.0))
+
+
+def test_float32_evaluation_runs_in_float32_and_stays_near_float64():
+    """dtype=float32 evaluates the same recursion with 32-bit arrays (the
+    tests' measured rounding floor for 32-bit results): the iterates are
+    float32, and z^T and dalpha stay within a few thousand unit roundoffs of
+    the float64 oracle on a small problem."""
+    pb = pins.small_problem(N=40)
+    alpha = synth.perturbed_steps(oracle.lipschitz(pb.D), 12, seed=5)
+    dF = np.full(pb.N, 1.0 / pb.N)
+    Z64, _, da64, its64, _ = oracle.forward_backward(pb.D, pb.X, pb.lam, alpha, dF=dF, return_adjoints=True)
+    Z32, _, da32, its32, adj32 = oracle.forward_backward(pb.D, pb.X, pb.lam, alpha, dF=dF, return_adjoints=True,
+                                                         dtype=np.float32)
+    assert all(z.dtype == np.float32 for z in its32) and all(v.dtype == np.float32 for v in adj32)
+    assert np.max(np.abs(Z32 - Z64)) <= 1e-4 * np.max(np.abs(Z64))
+    assert np.max(np.abs(da32 - da64)) <= 1e-4 * np.max(np.abs(da64))
+    assert np.max(np.abs(da32 - da64)) > 0.0   # it did round
