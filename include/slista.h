@@ -39,7 +39,11 @@
  *    text of the last failure on the calling thread is slista_last_error().
  *  - Device values are not inspected: alpha_t > 0 (Section 4, parameters in
  *    R+*) and finite inputs are preconditions. Non-finite inputs propagate
- *    as IEEE NaN/Inf.
+ *    by IEEE arithmetic (into F and the loss; the soft-threshold maps a NaN
+ *    argument to 0, so codes may stay finite), unless the finite-value check
+ *    (SLISTA_OPT_CHECK_FINITE) is on: then the dictionary, forward and backward entry points count
+ *    NaN/Inf in their inputs and outputs on the device, synchronise, and
+ *    return SLISTA_ENONFINITE if there are any.
  *  - Calls that overlap on the same workspace race; calls on distinct
  *    workspaces may run concurrently on different streams.
  */
@@ -61,7 +65,8 @@ typedef enum {
   SLISTA_ENOMEM = -2,     /* device allocation failed (slista_dict_create only) */
   SLISTA_EHIP = -3,       /* a HIP runtime call or kernel launch failed */
   SLISTA_ENOTSUP = -4,    /* valid request this build does not support (e.g. no gfx950 device) */
-  SLISTA_ENOTCONV = -5    /* power iteration reached max_iter before rtol */
+  SLISTA_ENOTCONV = -5,   /* power iteration reached max_iter before rtol */
+  SLISTA_ENONFINITE = -6  /* the finite-value check found NaN or Inf (SLISTA_OPT_CHECK_FINITE) */
 } slista_status;
 
 /* Arithmetic of the contraction P = Z G. The step, threshold and objective
@@ -71,6 +76,19 @@ typedef enum {
   SLISTA_BF16 = 1   /* BF16 operands on MFMA (v_mfma_f32_16x16x32_bf16), FP32 accumulate;
                        z is rounded to BF16 only as the operand of the product */
 } slista_prec;
+
+/* A precision schedule for the forward / backward entry points and batches:
+ * BF16 contractions in layers 0 .. T-tail-1 and FP32 contractions in the last
+ * `tail` layers (and in the adjoint of those layers). BF16 operands leave
+ * the iterates at a rounding floor that FP32 layers then contract away, so a
+ * short FP32 tail recovers FP32 objective-gap accuracy on converged problems
+ * at a fraction of the FP32 cost. 0 <= tail <= T; with layer checkpointing
+ * (ckpt_every > 1) T - tail must be a multiple of ckpt_every (the first FP32
+ * layer starts from a checkpoint). Pass it wherever an `int prec` is taken
+ * by slista_forward, slista_backward, slista_forward_backward,
+ * slista_forward_scratch, slista_batch_create and slista_batched_*; other
+ * entry points take SLISTA_FP32 or SLISTA_BF16 only. */
+#define SLISTA_BF16_FP32_TAIL(tail) (SLISTA_BF16 | ((tail) << 8))
 
 typedef struct slista_dict slista_dict;
 
@@ -191,9 +209,15 @@ SLISTA_API int slista_objective(const slista_dict* dict, const float* X, int N, 
  * dF_i = 1/N and dZ = 0, J is the loss of Eq. (15). The derivative of ST is
  * taken as 1 where |u| > lambda alpha_t and 0 elsewhere, and sign(0) = 0 in
  * the sub-gradient of |z| (a valid sub-gradient at the kinks).
- * Precondition: ws holds the tape of a slista_forward call with the same
- * dict, X, N, lambda, alpha, T, prec and ckpt_every >= 1, and nothing has
- * written to ws since. */
+ * ckpt_every >= 1. The call does not depend on an earlier slista_forward:
+ * the library records on the host which workspace holds the tape of which
+ * forward pass (slista_forward or slista_forward_backward with ckpt_every >=
+ * 1: same dict, X and alpha pointers, N, lambda, T, prec, ckpt_every, kernel
+ * family and tile variants). If ws holds such a tape it is used; otherwise
+ * the backward first runs the forward pass into ws itself (and records it).
+ * Calls of this library that write ws for anything else drop the record;
+ * the caller must not modify ws, X or alpha's values in between (the record
+ * cannot see writes from outside the library). */
 SLISTA_API int slista_backward(const slista_dict* dict, const float* X, int N, float lambda,
                                const float* alpha, int T, int prec, const float* dZ, const float* dF,
                                float* dalpha, int ckpt_every, void* ws, size_t ws_bytes, void* stream);
@@ -207,19 +231,51 @@ SLISTA_API int slista_forward_backward(const slista_dict* dict, const float* X, 
                                        size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Checks of a result
+ *
+ * slista_kkt: per sample, in FP64 on the device, the optimality conditions of
+ * the Lasso (Lemma 2.1, Eq. (3)): with r_j = D_j^T (x_i - D z_i),
+ *     kkt[i] = max_j ( |r_j - lambda sign z_ij|   if z_ij != 0,
+ *                      max(|r_j| - lambda, 0)     if z_ij == 0 ),
+ * zero exactly at the Lasso solution, and F[i] = F_{x_i}(z_i) (Eq. (1)),
+ * both from the FP32 values of D, X and Z with every product and sum in FP64.
+ * X device FP32 [N, n], Z device FP32 [N, m], kkt device FP64 [N], F device
+ * FP64 [N] or NULL. n <= 8192 (SLISTA_ENOTSUP above). No workspace.
+ *
+ * slista_lambda_max: lambda_max (Section 2): below it the Lasso solution of a
+ * sample is non-zero, at or above it exactly zero. Writes
+ *     lam_max_rows[i] = ||D^T x_i||_inf  (device FP32 [N], or NULL),
+ *     *lam_max = max_i lam_max_rows[i]   (device FP32 [1]),
+ * from the same FP32 correlation product c = D^T x (same kernel and order)
+ * that the forward pass uses, so that any lambda >= *lam_max gives
+ * z^(t) = 0 exactly in every layer. Workspace of
+ * slista_lambda_max_workspace_size bytes, 256-byte aligned.
+ * ------------------------------------------------------------------------- */
+SLISTA_API int slista_kkt(const slista_dict* dict, const float* X, int N, float lambda, const float* Z, double* kkt,
+                          double* F, void* stream);
+SLISTA_API int slista_lambda_max_workspace_size(const slista_dict* dict, int N, size_t* bytes);
+SLISTA_API int slista_lambda_max(const slista_dict* dict, const float* X, int N, float* lam_max, float* lam_max_rows,
+                                 void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Uneven batches: many independent Lasso problems (each its own dictionary,
  * n, m, N, lambda and steps; one common T) run forward + backward of their
  * mean losses together. Problems are grouped by column-pass bucket (m_pad up
  * to 256, 512, 1024, 2048); each bucket runs as one persistent launch per
- * phase over a work list of (problem, tile) pairs ordered longest first.
+ * phase over a work list of (problem, tile) pairs ordered longest first, and
+ * the buckets run concurrently: each on a stream of the batch's own, forked
+ * from the caller's stream and joined back into it with events (a captured
+ * graph has one branch per bucket). `prec` may carry an FP32 tail
+ * (SLISTA_BF16_FP32_TAIL).
  *
  * Usage: slista_batch_create -> slista_batch_workspace_size -> allocate ->
- * slista_batch_bind (builds the device argument tables, synchronises) ->
- * slista_batch_run (enqueue) or slista_batch_capture once and then
- * slista_batch_replay (HIP graph) -> slista_batch_destroy.
- * A batch owns small device tables (argument records and work lists) and
- * the captured graph; the problems' buffers and the workspace stay the
- * caller's and must outlive the batch's use of them.
+ * slista_batch_bind (builds the device argument tables and the bucket
+ * streams, synchronises) -> slista_batch_run (enqueue) or
+ * slista_batch_capture once and then slista_batch_replay (HIP graph) ->
+ * slista_batch_destroy. A batch owns small device tables (argument records
+ * and work lists), its streams and events and the captured graph; the
+ * problems' buffers and the workspace stay the caller's and must outlive the
+ * batch's use of them.
  * ------------------------------------------------------------------------- */
 typedef struct {
   const slista_dict* dict;   /* dictionary of this problem (m_pad <= 2048) */
@@ -258,6 +314,24 @@ SLISTA_API int slista_batch_replay(slista_batch* batch, void* stream);
 SLISTA_API int slista_batch_autotune(slista_batch* batch, void* stream, int* variants);
 SLISTA_API int slista_batch_destroy(slista_batch* batch);
 
+/* One call for a whole batch: forward + backward of every problem (as
+ * slista_batch_run). On the first call with a given problem array (its
+ * contents), T, prec, ckpt_every and workspace the library plans the batch
+ * (argument tables, work lists: device allocations and a synchronisation)
+ * and, with use_graph != 0, records it into a HIP graph on a stream of its
+ * own; later calls with the same key only launch that graph (use_graph) or
+ * the batch's kernels on `stream`. Up to 8 plans are kept, least recently
+ * used dropped first; slista_batched_release drops all of them (and
+ * synchronises the device). The workspace must hold
+ * slista_batched_workspace_size bytes (256-byte aligned) and must not be
+ * used for anything else while its plan is kept. Thread-safe; calls that
+ * share a workspace must not overlap. */
+SLISTA_API int slista_batched_workspace_size(const slista_problem* problems, int P, int T, int prec, int ckpt_every,
+                                             size_t* bytes);
+SLISTA_API int slista_batched_fwd_bwd(const slista_problem* problems, int P, int T, int prec, int ckpt_every,
+                                      void* ws, size_t ws_bytes, void* stream, int use_graph);
+SLISTA_API int slista_batched_release(void);
+
 /* ---------------------------------------------------------------------------
  * Options (process-wide, not thread-safe; set before enqueuing work)
  *
@@ -286,6 +360,14 @@ SLISTA_API int slista_batch_destroy(slista_batch* batch);
  * by the grouping of their partial sums. A variant that does not exist for
  * the dictionary's m_pad falls back to the default. */
 #define SLISTA_OPT_PERSIST_VARIANT 2
+/* SLISTA_OPT_CHECK_FINITE: 1 = count NaN/Inf in the inputs (D, X, alpha,
+ * dZ, dF) and outputs (Z, F, loss, dalpha) of slista_dict_create,
+ * slista_forward, slista_backward and slista_forward_backward on the device;
+ * each such call then synchronises its stream and returns
+ * SLISTA_ENONFINITE if any was found (outputs are written regardless).
+ * 0 (default) = no checks, no synchronisation. Not for use during stream
+ * capture. */
+#define SLISTA_OPT_CHECK_FINITE 3
 
 /* Options are process-wide: set them before other threads call the library.
  * The autotuners use per-thread overrides while timing, and the tuning table

@@ -6,6 +6,12 @@ include/slista.h); this package is its thin PyTorch binding.
 from .ops import (  # noqa: F401
     PRECISIONS,
     Batch,
+    BatchedCall,
+    batched_release,
+    bf16_fp32_tail,
+    kkt,
+    lambda_max,
+    set_check_finite,
     Dictionary,
     SlistaError,
     autotune,

@@ -72,6 +72,12 @@ SIGNATURES = {
     "slista_batch_capture": (_c_int, [_vp, _vp]),
     "slista_batch_replay": (_c_int, [_vp, _vp]),
     "slista_batch_destroy": (_c_int, [_vp]),
+    "slista_kkt": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _vp, _vp, _vp]),
+    "slista_lambda_max_workspace_size": (_c_int, [_vp, _c_int, ctypes.POINTER(_size_t)]),
+    "slista_lambda_max": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _size_t, _vp]),
+    "slista_batched_workspace_size": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_size_t)]),
+    "slista_batched_fwd_bwd": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, _vp, _size_t, _vp, _c_int]),
+    "slista_batched_release": (_c_int, []),
     "slista_profile_begin": (_c_int, []),
     "slista_profile_end": (_c_int, [ctypes.POINTER(_c_int), ctypes.POINTER(_c_double), ctypes.POINTER(_c_int)]),
 }

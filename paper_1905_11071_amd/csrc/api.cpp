@@ -38,26 +38,38 @@ struct slista_dict {
 };
 
 struct slista_batch {
-  int P = 0, T = 0, prec = 0, k = 1, variant = 0;
+  int P = 0, T = 0, prec = 0, k = 1;
+  int base = 0, tail = 0;              // precision schedule (see parse_sched)
   std::vector<slista_problem> probs;
   std::vector<size_t> offset;          // workspace offset of each problem
   size_t total = 0;
-  // buckets of the persistent kernels
+  // buckets of the persistent kernels; per contraction precision (index
+  // slista::kF32 / kBF16) a tile variant and a work list
   struct Bucket {
-    int np = 0, max_m_pad = 0, nwork = 0, variant = 0, rows_total = 0;
+    int np = 0, max_m_pad = 0, rows_total = 0;
+    int variant[2] = {0, 0}, nwork[2] = {0, 0};
     std::vector<int> problems;
-    size_t work_off = 0;                // index of the bucket's first work item
+    size_t work_off[2] = {0, 0};        // index of the bucket's first work item
+    size_t small_off = 0;               // index of its first entry in d_small
+    int max_N = 0;                      // largest N of its problems
+    size_t max_group_elems = 0;         // largest row-group copy of c (float4 count)
   };
   std::vector<Bucket> buckets;
-  std::vector<int> rows;                // tile rows per problem
+  std::vector<int> rows[2];             // tile rows per problem
+  bool uses[2] = {false, false};        // precisions the schedule runs
   // device tables (owned)
-  slista::PersistArgs* d_args = nullptr;
+  slista::PersistArgs* d_args[2] = {nullptr, nullptr};
   int2* d_work = nullptr;
   size_t work_cap = 0;                  // entries d_work holds
+  slista::BatchSmall* d_small = nullptr;  // [P] small-kernel table, bucket by bucket
   char* ws = nullptr;
   size_t ws_bytes = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // one stream per bucket (default priority), forked from and joined into
+  // the caller's stream with events, so that the buckets run concurrently
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev;  // [0]: fork; [1 + bi]: bucket bi done
 };
 
 namespace {
@@ -131,6 +143,8 @@ struct ProfScope {
 int g_kernel_family = 0;
 // Tile variant of the persistent kernels (0 = default; see persist_rows).
 int g_persist_variant = 0;
+// Finite-value checks of inputs and outputs (SLISTA_OPT_CHECK_FINITE).
+int g_check_finite = 0;
 // Autotuned variants: (precision, column-pass bucket, floor(log2 N)) -> variant,
 // shared by all threads (g_tuned_mu guards it).
 std::map<std::tuple<int, int, int>, int> g_tuned;
@@ -270,6 +284,153 @@ bool use_persist(const Run& r, int prec) {
   return slista::persist_rows(prec, r.d->m_pad, variant_for(prec, r.d->m_pad, r.N)) > 0;
 }
 
+// ---------------------------------------------------------------- precision schedule
+// The `prec` argument of the forward/backward entry points: its low byte is
+// the contraction precision (SLISTA_FP32 or SLISTA_BF16); with SLISTA_BF16,
+// bits 8 and up may give an FP32 tail: the last `tail` layers contract in FP32.
+struct Sched {
+  int base = 0, tail = 0, T = 0;
+  // contraction precision of layer t (z^t -> z^{t+1})
+  int at(int t) const { return (tail > 0 && t >= T - tail) ? (int)slista::kF32 : base; }
+  int split() const { return tail > 0 && tail < T ? T - tail : 1 << 30; }
+};
+
+int parse_sched(int prec, int T, int ckpt_every, Sched* sc) {
+  if (prec < 0) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
+  const int base = prec & 0xff, tail = prec >> 8;
+  if (base != SLISTA_FP32 && base != SLISTA_BF16) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
+  if (tail > 0 && base != SLISTA_BF16) return fail(SLISTA_EINVAL, "an FP32 tail needs SLISTA_BF16 layers before it");
+  if (tail > T) return fail(SLISTA_EINVAL, "FP32 tail of %d layers is longer than T=%d", tail, T);
+  if (tail > 0 && tail < T && ckpt_every > 1 && (T - tail) % ckpt_every != 0)
+    return fail(SLISTA_EINVAL, "the first FP32 layer (T - tail = %d) must be a checkpoint (ckpt_every=%d)", T - tail,
+                ckpt_every);
+  sc->base = base;
+  sc->tail = tail;
+  sc->T = T;
+  return SLISTA_OK;
+}
+
+// Layer ranges that run in one precision: one span, or a BF16 span and the FP32 tail.
+struct Span {
+  int t0, t1, prec;
+};
+int spans_of(const Sched& sc, Span out[2]) {
+  if (sc.tail == 0 || sc.tail >= sc.T) {
+    out[0] = Span{0, sc.T, sc.tail > 0 ? (int)slista::kF32 : sc.base};
+    return 1;
+  }
+  out[0] = Span{0, sc.T - sc.tail, sc.base};
+  out[1] = Span{sc.T - sc.tail, sc.T, (int)slista::kF32};
+  return 2;
+}
+
+bool use_persist(const Run& r, const Sched& sc) {
+  Span sp[2];
+  const int ns = spans_of(sc, sp);
+  for (int i = 0; i < ns; ++i)
+    if (!use_persist(r, sp[i].prec)) return false;
+  return true;
+}
+
+// Tiles of the persistent kernels for precision p on this run.
+int persist_tiles(const Run& r, int p) {
+  const int rows = slista::persist_rows(p, r.d->m_pad, variant_for(p, r.d->m_pad, r.N));
+  return (r.N + rows - 1) / rows;
+}
+
+// ---------------------------------------------------------------- tape registry
+// What a forward pass left in a workspace, recorded on the host, keyed by the
+// workspace's address range: a backward call uses the tape only if it was
+// kept for the same arguments, kernel family and tile variants, and
+// recomputes it otherwise. Every entry point that writes a caller workspace
+// drops the records its range overlaps.
+struct TapeTag {
+  const slista::Dict* d;
+  const float* X;
+  const float* alpha;
+  int N, T, prec, k, family, variant0, variant1;
+  float lam;
+  // Which of the tape's slots hold the forward's iterates: the checkpoints
+  // always; the interior of the last segment (which the forward keeps) only
+  // until a backward pass with several segments has recomputed the earlier
+  // segments into the same slots.
+  bool operator==(const TapeTag& o) const {
+    return d == o.d && X == o.X && alpha == o.alpha && N == o.N && T == o.T && prec == o.prec && k == o.k &&
+           family == o.family && variant0 == o.variant0 && variant1 == o.variant1 &&
+           std::memcmp(&lam, &o.lam, sizeof lam) == 0;
+  }
+};
+struct TapeRec {
+  uintptr_t lo, hi;
+  TapeTag tag;
+  bool last_interior;
+};
+std::mutex g_tape_mu;
+std::vector<TapeRec> g_tapes;
+constexpr size_t kMaxTapes = 4096;
+
+TapeTag tape_tag(const Run& r, const float* X, float lam, const float* alpha, int prec) {
+  TapeTag t;
+  std::memset(&t, 0, sizeof t);
+  t.d = r.d;
+  t.X = X;
+  t.alpha = alpha;
+  t.N = r.N;
+  t.T = r.T;
+  t.prec = prec;
+  t.k = r.L.k;
+  t.family = kernel_family();
+  t.variant0 = variant_for(slista::kF32, r.d->m_pad, r.N);
+  t.variant1 = variant_for(slista::kBF16, r.d->m_pad, r.N);
+  t.lam = lam;
+  return t;
+}
+
+void tape_forget(const void* ws, size_t bytes) {
+  const uintptr_t lo = (uintptr_t)ws, hi = lo + (bytes > 0 ? bytes : 1);
+  std::lock_guard<std::mutex> lock(g_tape_mu);
+  g_tapes.erase(std::remove_if(g_tapes.begin(), g_tapes.end(),
+                               [&](const TapeRec& t) { return t.lo < hi && lo < t.hi; }),
+                g_tapes.end());
+}
+
+void tape_record(const void* ws, size_t bytes, const TapeTag& tag, bool last_interior) {
+  tape_forget(ws, bytes);
+  std::lock_guard<std::mutex> lock(g_tape_mu);
+  if (g_tapes.size() >= kMaxTapes) g_tapes.erase(g_tapes.begin());
+  g_tapes.push_back(TapeRec{(uintptr_t)ws, (uintptr_t)ws + bytes, tag, last_interior});
+}
+
+// 0: no tape of this forward in ws; 1: checkpoints only; 2: the whole tape.
+int tape_state(const void* ws, const TapeTag& tag) {
+  std::lock_guard<std::mutex> lock(g_tape_mu);
+  for (const auto& t : g_tapes)
+    if (t.lo == (uintptr_t)ws && t.tag == tag) return t.last_interior ? 2 : 1;
+  return 0;
+}
+
+// Whether a backward pass over this layout leaves the last segment's interior
+// in place (it recomputes the earlier segments into the same slots).
+bool backward_keeps_interior(const Layout& L, int T) { return L.k <= 1 || (T + L.k - 1) / L.k <= 1; }
+
+// ---------------------------------------------------------------- finite-value checks
+// With SLISTA_OPT_CHECK_FINITE on: count NaN / Inf entries of the given
+// buffers on the device and synchronise; SLISTA_ENONFINITE if any.
+struct Buf {
+  const float* p;
+  size_t n;
+};
+int check_finite(const slista::Dict& d, hipStream_t s, std::initializer_list<Buf> bufs, const char* what) {
+  if (!g_check_finite) return SLISTA_OK;
+  LAUNCH(kKOther, s, slista::launch_zero_u32(d.flag, s));
+  for (const Buf& b : bufs) LAUNCH(kKOther, s, slista::launch_count_nonfinite(b.p, b.n, d.flag, s));
+  unsigned int cnt = 0;
+  HIP_TRY(hipMemcpyAsync(&cnt, d.flag, sizeof cnt, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (cnt) return fail(SLISTA_ENONFINITE, "%u non-finite values in %s", cnt, what);
+  return SLISTA_OK;
+}
+
 slista::PersistArgs persist_args(const Run& r, int prec, const float* alpha, float lam) {
   slista::PersistArgs a;
   std::memset(&a, 0, sizeof a);
@@ -305,9 +466,8 @@ int fwd_layer(const Run& r, int prec, const float* alpha, float lam, int t, doub
   return SLISTA_OK;
 }
 
-// c = D^T x for every sample (row-major), its norms, and, where the layout
-// has room for it, the row-group copy of c that the persistent forward reads.
-int prep(const Run& r, const float* X) {
+// c = D^T x for every sample (row-major).
+int prep_corr(const Run& r, const float* X) {
   slista::GemmArgs g;
   std::memset(&g, 0, sizeof g);
   g.A = X;
@@ -321,21 +481,34 @@ int prep(const Run& r, const float* X) {
   g.ldz = r.d->m_pad;
   slista::gemm_grid(r.N, r.d->m_pad, g);
   LAUNCH(kKCorr, r.s, slista::launch_gemm(slista::kF32, slista::kEpiCorr, true, g, r.s));
+  return SLISTA_OK;
+}
+
+// c, the norms ||x_i||^2, and, where the layout has room for it, the
+// row-group copy of c that the persistent forward reads.
+int prep(const Run& r, const float* X) {
+  int st = prep_corr(r, X);
+  if (st != SLISTA_OK) return st;
   if (r.L.groups) LAUNCH(kKOther, r.s, slista::launch_row_groups(r.C(), r.N, r.d->m_pad, r.Cg(), r.s));
   LAUNCH(kKOther, r.s, slista::launch_xsq(X, r.N, r.d->n, r.xsq(), r.s));
   return SLISTA_OK;
 }
 
 int check_common(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha, int T,
-                 int prec, int ckpt_every, void* ws, size_t ws_bytes, size_t* need) {
+                 int prec, int ckpt_every, void* ws, size_t ws_bytes, size_t* need, Sched* sc = nullptr) {
   if (!dict) return fail(SLISTA_EINVAL, "dict is NULL");
   if (N < 0 || N > kMaxN) return fail(SLISTA_EINVAL, "N=%d outside [0, %d]", N, kMaxN);
   if (T < 0 || T > kMaxT) return fail(SLISTA_EINVAL, "T=%d outside [0, %d]", T, kMaxT);
   if (!(lambda > 0.f) || !std::isfinite(lambda))
     return fail(SLISTA_EINVAL, "lambda=%g must be finite and > 0", (double)lambda);
-  if (prec != SLISTA_FP32 && prec != SLISTA_BF16) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
   if (ckpt_every < 0 || ckpt_every > kMaxT)
     return fail(SLISTA_EINVAL, "ckpt_every=%d outside [0, %d]", ckpt_every, kMaxT);
+  if (sc) {
+    const int st = parse_sched(prec, T, ckpt_every, sc);
+    if (st != SLISTA_OK) return st;
+  } else if (prec != SLISTA_FP32 && prec != SLISTA_BF16) {
+    return fail(SLISTA_EINVAL, "unknown precision %d (FP32 tails are not taken here)", prec);
+  }
   if (N > 0 && !X) return fail(SLISTA_EINVAL, "X is NULL");
   if (T > 0 && !alpha) return fail(SLISTA_EINVAL, "alpha is NULL");
   const Layout L = make_layout(dict->d, N, T, ckpt_every);
@@ -350,41 +523,55 @@ int check_common(const slista_dict* dict, const float* X, int N, float lambda, c
 }
 
 // Forward pass into the workspace. want_final: evaluate F(z^T) here (else
-// the caller's seed contraction does it).
-int run_forward(const Run& r, const float* X, float lam, const float* alpha, int prec, float* Z, float* F,
+// the caller's seed contraction does it). Z may be NULL (the tape only).
+int run_forward(const Run& r, const float* X, float lam, const float* alpha, const Sched& sc, float* Z, float* F,
                 int f_trace, float* loss, bool want_final, float* seed_vout = nullptr, float seed_dF = 0.f) {
   const int N = r.N, T = r.T, mp = r.d->m_pad;
   int st;
   if ((st = prep(r, X)) != SLISTA_OK) return st;
   const bool want_f = (F != nullptr) || (loss != nullptr);
   if (T == 0) {
-    LAUNCH(kKOther, r.s, slista::launch_fill(Z, (size_t)N * r.d->m, 0.f, r.s));
+    if (Z) LAUNCH(kKOther, r.s, slista::launch_fill(Z, (size_t)N * r.d->m, 0.f, r.s));
     if (want_f) {
       LAUNCH(kKOther, r.s, slista::launch_reduce_f(r.xsq(), r.fpart(), 0, N, F, r.Fd(), r.s));
       if (loss) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
     }
     return SLISTA_OK;
   }
-  if (use_persist(r, prec)) {
-    slista::PersistArgs a = persist_args(r, prec, alpha, lam);
-    a.t_begin = 0;
-    a.t_end = T;
-    if (want_f && want_final) {
-      a.mode |= slista::kModeF;
-      a.F = F ? (f_trace ? F + (size_t)T * N : F) : nullptr;
-      a.Fd = r.Fd();
+  if (use_persist(r, sc)) {
+    Span sp[2];
+    const int ns = spans_of(sc, sp);
+    // without a tape, the iterate where the precision changes goes through
+    // the (otherwise unused) iterate buffers of the layout
+    float* handoff = (r.L.k == 0 && ns == 2) ? (float*)(r.ws + r.L.pp) : nullptr;
+    for (int i = 0; i < ns; ++i) {
+      const bool last = i == ns - 1;
+      slista::PersistArgs a = persist_args(r, sp[i].prec, alpha, lam);
+      a.t_begin = sp[i].t0;
+      a.t_end = sp[i].t1;
+      if (F && f_trace) {
+        a.mode |= slista::kModeTrace;
+        a.Ftrace = F;
+      }
+      if (last) {
+        if (want_f && want_final) {
+          a.mode |= slista::kModeF;
+          a.F = F ? (f_trace ? F + (size_t)T * N : F) : nullptr;
+          a.Fd = r.Fd();
+        }
+        a.Zuser = Z;
+        if (seed_vout) {
+          a.mode |= slista::kModeSeed;
+          a.dF_scalar = seed_dF;
+          a.Vout = seed_vout;
+        }
+        a.zload = i > 0 ? handoff : nullptr;
+      } else {
+        a.zsave = handoff;
+      }
+      LAUNCH(kKFwd, r.s,
+             slista::launch_persist(true, sp[i].prec, a, r.s, variant_for(sp[i].prec, r.d->m_pad, r.N)));
     }
-    if (F && f_trace) {
-      a.mode |= slista::kModeTrace;
-      a.Ftrace = F;
-    }
-    a.Zuser = Z;
-    if (seed_vout) {
-      a.mode |= slista::kModeSeed;
-      a.dF_scalar = seed_dF;
-      a.Vout = seed_vout;
-    }
-    LAUNCH(kKFwd, r.s, slista::launch_persist(true, prec, a, r.s, variant_for(prec, r.d->m_pad, r.N)));
     if (loss && want_final) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
     return SLISTA_OK;
   }
@@ -392,18 +579,18 @@ int run_forward(const Run& r, const float* X, float lam, const float* alpha, int
   LAUNCH(kKOther, r.s, slista::launch_layer0(r.C(), N, mp, alpha, lam, r.slot(1), r.s));
   for (int t = 1; t < T; ++t) {
     const bool tr = F && f_trace;
-    if ((st = fwd_layer(r, prec, alpha, lam, t, tr ? r.fpart() : nullptr)) != SLISTA_OK) return st;
+    if ((st = fwd_layer(r, sc.at(t), alpha, lam, t, tr ? r.fpart() : nullptr)) != SLISTA_OK) return st;
     if (tr) LAUNCH(kKOther, r.s, slista::launch_reduce_f(r.xsq(), r.fpart(), r.L.col_tiles, N, F + (size_t)t * N, nullptr, r.s));
   }
-  LAUNCH(kKOther, r.s, slista::launch_copy_out(r.slot(T), N, mp, r.d->m, Z, r.s));
+  if (Z) LAUNCH(kKOther, r.s, slista::launch_copy_out(r.slot(T), N, mp, r.d->m, Z, r.s));
   if (want_f && want_final) {
     slista::GemmArgs g = base_args(r, alpha, lam);
     g.A = r.slot(T);
-    g.Bt = gram_for(*r.d, prec);
+    g.Bt = gram_for(*r.d, sc.at(T - 1));
     g.t = T - 1;
     g.Zt = r.slot(T);
     g.fpart = r.fpart();
-    LAUNCH(kKFinal, r.s, slista::launch_gemm(prec, slista::kEpiFinal, false, g, r.s));
+    LAUNCH(kKFinal, r.s, slista::launch_gemm(sc.at(T - 1), slista::kEpiFinal, false, g, r.s));
     float* Fout = F ? (f_trace ? F + (size_t)T * N : F) : nullptr;
     LAUNCH(kKOther, r.s, slista::launch_reduce_f(r.xsq(), r.fpart(), r.L.col_tiles, N, Fout, r.Fd(), r.s));
     if (loss) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
@@ -412,15 +599,18 @@ int run_forward(const Run& r, const float* X, float lam, const float* alpha, int
 }
 
 // Reverse pass over a workspace holding the forward tape. If seed_fpart, the
-// seed contraction also produces F(z^T) (into F / loss).
-int run_backward(const Run& r, float lam, const float* alpha, int prec, const float* dZ, const float* dF,
-                 float dF_scalar, float* dalpha, bool seed_fpart, float* F, float* loss, bool seeded = false) {
+// seed contraction also produces F(z^T) (into F / loss). Layer t of the
+// adjoint contracts in the precision of forward layer t.
+int run_backward(const Run& r, float lam, const float* alpha, const Sched& sc, const float* dZ, const float* dF,
+                 float dF_scalar, float* dalpha, bool seed_fpart, float* F, float* loss, bool seeded = false,
+                 bool last_interior = true) {
   const int N = r.N, T = r.T, k = r.L.k;
   if (T == 0) return SLISTA_OK;
   int st;
-  if (use_persist(r, prec)) {
-    slista::PersistArgs a = persist_args(r, prec, alpha, lam);
+  if (use_persist(r, sc)) {
+    const int pT = sc.at(T - 1);
     if (!seeded) {
+      slista::PersistArgs a = persist_args(r, pT, alpha, lam);
       a.t_begin = a.t_end = T;
       a.mode = slista::kModeSeed;
       a.dF = dF;
@@ -432,39 +622,52 @@ int run_backward(const Run& r, float lam, const float* alpha, int prec, const fl
         a.F = F;
         a.Fd = r.Fd();
       }
-      LAUNCH(kKSeed, r.s, slista::launch_persist(true, prec, a, r.s, variant_for(prec, r.d->m_pad, r.N)));
+      LAUNCH(kKSeed, r.s, slista::launch_persist(true, pT, a, r.s, variant_for(pT, r.d->m_pad, r.N)));
       if (seed_fpart && loss) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
     }
-    // With every iterate kept (k = 1) nothing is recomputed: one launch walks
-    // all layers; otherwise one recompute + one backward launch per segment.
-    const int seg_len = k == 1 ? T : k;
-    const int nseg = (T + seg_len - 1) / seg_len;
-    for (int sgi = nseg - 1; sgi >= 0; --sgi) {
-      const int a0 = sgi * seg_len;
-      const int b = (a0 + seg_len < T) ? a0 + seg_len : T;
-      if (k > 1 && sgi != nseg - 1 && b - 1 > a0) {
-        slista::PersistArgs f = persist_args(r, prec, alpha, lam);
-        f.t_begin = a0;
-        f.t_end = b - 1;
-        f.store_all = 1;
-        LAUNCH(kKFwd, r.s, slista::launch_persist(true, prec, f, r.s, variant_for(prec, r.d->m_pad, r.N)));
-      }
+    auto bwd = [&](int prec, int t_hi, int t_lo) -> int {
       slista::PersistArgs bw = persist_args(r, prec, alpha, lam);
-      bw.t_hi = b - 1;
-      bw.t_lo = a0;
+      bw.t_hi = t_hi;
+      bw.t_lo = t_lo;
       bw.Vio = r.vbuf(0);
       bw.dpart = r.dpart();
       LAUNCH(kKBwd, r.s, slista::launch_persist(false, prec, bw, r.s, variant_for(prec, r.d->m_pad, r.N)));
+      return SLISTA_OK;
+    };
+    if (k == 1) {
+      // every iterate kept: nothing is recomputed; one launch per precision span
+      Span sp[2];
+      const int ns = spans_of(sc, sp);
+      for (int i = ns - 1; i >= 0; --i)
+        if ((st = bwd(sp[i].prec, sp[i].t1 - 1, sp[i].t0)) != SLISTA_OK) return st;
+    } else {
+      // one recompute + one backward launch per segment (a segment never
+      // straddles the first FP32 layer, which is a checkpoint)
+      const int nseg = (T + k - 1) / k;
+      for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+        const int a0 = sgi * k;
+        const int b = (a0 + k < T) ? a0 + k : T;
+        const int prec = sc.at(a0);
+        if ((sgi != nseg - 1 || !last_interior) && b - 1 > a0) {
+          slista::PersistArgs f = persist_args(r, prec, alpha, lam);
+          f.t_begin = a0;
+          f.t_end = b - 1;
+          f.store_all = 1;
+          LAUNCH(kKFwd, r.s, slista::launch_persist(true, prec, f, r.s, variant_for(prec, r.d->m_pad, r.N)));
+        }
+        if ((st = bwd(prec, b - 1, a0)) != SLISTA_OK) return st;
+      }
     }
-    const int rows = slista::persist_rows(prec, r.d->m_pad, variant_for(prec, r.d->m_pad, r.N));
-    const int tiles = (N + rows - 1) / rows;
-    LAUNCH(kKOther, r.s, slista::launch_reduce_dalpha(r.dpart(), T, r.L.P, tiles, tiles, alpha, dalpha, r.s));
+    const int tiles_lo = persist_tiles(r, sc.at(0)), tiles_hi = persist_tiles(r, pT);
+    LAUNCH(kKOther, r.s, slista::launch_reduce_dalpha(r.dpart(), T, r.L.P, tiles_lo, tiles_lo, alpha, dalpha, r.s,
+                                                      sc.split(), tiles_hi));
     return SLISTA_OK;
   }
   {
+    const int pT = sc.at(T - 1);
     slista::GemmArgs g = base_args(r, alpha, lam);
     g.A = r.slot(T);
-    g.Bt = gram_for(*r.d, prec);
+    g.Bt = gram_for(*r.d, pT);
     g.t = T - 1;
     g.Zt = r.slot(T);
     g.Out = r.vbuf(T - 1);
@@ -472,7 +675,7 @@ int run_backward(const Run& r, float lam, const float* alpha, int prec, const fl
     g.dF_scalar = dF_scalar;
     g.dZ = dZ;
     g.fpart = seed_fpart ? r.fpart() : nullptr;
-    LAUNCH(kKSeed, r.s, slista::launch_gemm(prec, slista::kEpiSeed, false, g, r.s));
+    LAUNCH(kKSeed, r.s, slista::launch_gemm(pT, slista::kEpiSeed, false, g, r.s));
     if (seed_fpart) {
       LAUNCH(kKOther, r.s, slista::launch_reduce_f(r.xsq(), r.fpart(), r.L.col_tiles, N, F, r.Fd(), r.s));
       if (loss) LAUNCH(kKOther, r.s, slista::launch_reduce_loss(r.Fd(), N, loss, r.s));
@@ -483,11 +686,11 @@ int run_backward(const Run& r, float lam, const float* alpha, int prec, const fl
     const int a = sgi * k;
     const int b = (a + k < T) ? a + k : T;
     // Recompute the interior z^(a+1) .. z^(b-1) unless the forward left it.
-    if (sgi != nseg - 1) {
+    if (sgi != nseg - 1 || !last_interior) {
       for (int t = a + 1; t < b; ++t) {
         if (t == 1)
           LAUNCH(kKOther, r.s, slista::launch_layer0(r.C(), N, r.d->m_pad, alpha, lam, r.slot(1), r.s));
-        else if ((st = fwd_layer(r, prec, alpha, lam, t - 1, nullptr)) != SLISTA_OK)
+        else if ((st = fwd_layer(r, sc.at(t - 1), alpha, lam, t - 1, nullptr)) != SLISTA_OK)
           return st;
       }
     }
@@ -499,13 +702,13 @@ int run_backward(const Run& r, float lam, const float* alpha, int prec, const fl
         slista::GemmArgs g = base_args(r, alpha, lam);
         g.A = r.vbuf(t);
         g.Vin = r.vbuf(t);
-        g.Bt = gram_for(*r.d, prec);
+        g.Bt = gram_for(*r.d, sc.at(t));
         g.t = t;
         g.Zt = r.slot(t);
         g.Zt1 = r.slot(t + 1);
         g.Out = r.vbuf(t - 1);
         g.dpart = dp;
-        LAUNCH(kKBwd, r.s, slista::launch_gemm(prec, slista::kEpiBwd, false, g, r.s));
+        LAUNCH(kKBwd, r.s, slista::launch_gemm(sc.at(t), slista::kEpiBwd, false, g, r.s));
       }
     }
   }
@@ -930,6 +1133,11 @@ int slista_set_option(int option, int value) {
     g_persist_variant = value;
     return SLISTA_OK;
   }
+  if (option == SLISTA_OPT_CHECK_FINITE) {
+    if (value < 0 || value > 1) return fail(SLISTA_EINVAL, "check-finite flag %d outside [0, 1]", value);
+    g_check_finite = value;
+    return SLISTA_OK;
+  }
   return fail(SLISTA_EINVAL, "unknown option %d", option);
 }
 
@@ -967,6 +1175,7 @@ const char* slista_status_string(int status) {
     case SLISTA_EHIP: return "HIP runtime error";
     case SLISTA_ENOTSUP: return "not supported";
     case SLISTA_ENOTCONV: return "power iteration did not converge";
+    case SLISTA_ENONFINITE: return "non-finite values (NaN or Inf) found by the finite-value check";
     default: return "unknown status";
   }
 }
@@ -999,13 +1208,15 @@ int slista_dict_create(const float* D, int n, int m, void* stream, slista_dict**
   d.pwork = nullptr;
   d.Gsb = nullptr;
   d.Gsf = nullptr;
+  d.flag = nullptr;
   const size_t mp = d.m_pad;
   bool ok = hipMalloc(&d.G32, mp * mp * sizeof(float)) == hipSuccess &&
             hipMalloc(&d.Gb, mp * mp * sizeof(uint16_t)) == hipSuccess &&
             hipMalloc(&d.Dt, mp * (size_t)n * sizeof(float)) == hipSuccess &&
             hipMalloc(&d.pwork, (2 * mp + 8) * sizeof(double)) == hipSuccess &&
             hipMalloc(&d.Gsb, mp * mp * sizeof(uint16_t)) == hipSuccess &&
-            hipMalloc(&d.Gsf, mp * mp * sizeof(float)) == hipSuccess;
+            hipMalloc(&d.Gsf, mp * mp * sizeof(float)) == hipSuccess &&
+            hipMalloc(&d.flag, 256) == hipSuccess;
   if (!ok) {
     (void)hipFree(d.G32);
     (void)hipFree(d.Gb);
@@ -1013,6 +1224,7 @@ int slista_dict_create(const float* D, int n, int m, void* stream, slista_dict**
     (void)hipFree(d.pwork);
     (void)hipFree(d.Gsb);
     (void)hipFree(d.Gsf);
+    (void)hipFree(d.flag);
     delete h;
     (void)hipGetLastError();
     return fail(SLISTA_ENOMEM, "hipMalloc of the Gram matrices (m_pad=%d) failed", d.m_pad);
@@ -1023,6 +1235,11 @@ int slista_dict_create(const float* D, int n, int m, void* stream, slista_dict**
   if (e != hipSuccess) {
     slista_dict_destroy(h);
     return fail(SLISTA_EHIP, "Gram matrix: %s", hipGetErrorString(e));
+  }
+  const int cst = check_finite(d, s, {{D, (size_t)n * m}}, "D");
+  if (cst != SLISTA_OK) {
+    slista_dict_destroy(h);
+    return cst;
   }
   *out = h;
   return SLISTA_OK;
@@ -1037,6 +1254,7 @@ int slista_dict_destroy(slista_dict* dict) {
   (void)hipFree(dict->d.pwork);
   (void)hipFree(dict->d.Gsb);
   (void)hipFree(dict->d.Gsf);
+  (void)hipFree(dict->d.flag);
   delete dict;
   return SLISTA_OK;
 }
@@ -1085,7 +1303,9 @@ int slista_workspace_size(const slista_dict* dict, int N, int T, int prec, int c
   if (!dict || !bytes) return fail(SLISTA_EINVAL, "dict or bytes is NULL");
   if (N < 0 || N > kMaxN || T < 0 || T > kMaxT || ckpt_every < 0 || ckpt_every > kMaxT)
     return fail(SLISTA_EINVAL, "sizes out of range");
-  if (prec != SLISTA_FP32 && prec != SLISTA_BF16) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
+  Sched sc;
+  const int st = parse_sched(prec, T, ckpt_every, &sc);
+  if (st != SLISTA_OK) return st;
   *bytes = make_layout(dict->d, N, T, ckpt_every).total;
   return SLISTA_OK;
 }
@@ -1094,7 +1314,9 @@ int slista_ckpt_for_budget(const slista_dict* dict, int N, int T, int prec, size
                            size_t* bytes) {
   if (!dict || !ckpt_every) return fail(SLISTA_EINVAL, "dict or ckpt_every is NULL");
   if (N < 0 || N > kMaxN || T < 1 || T > kMaxT) return fail(SLISTA_EINVAL, "sizes out of range");
-  if (prec != SLISTA_FP32 && prec != SLISTA_BF16) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
+  Sched sc;
+  const int st = parse_sched(prec, T, 1, &sc);
+  if (st != SLISTA_OK) return st;
   // the workspace shrinks with k until the segment buffers outgrow the
   // checkpoints (around sqrt(T)); the smallest fitting k recomputes least
   size_t best_bytes = (size_t)-1;
@@ -1115,16 +1337,25 @@ int slista_forward(const slista_dict* dict, const float* X, int N, float lambda,
                    int prec, float* Z, float* F, int f_trace, float* loss, int ckpt_every, void* ws,
                    size_t ws_bytes, void* stream) {
   size_t need = 0;
-  int st = check_common(dict, X, N, lambda, alpha, T, prec, ckpt_every, ws, ws_bytes, &need);
+  Sched sc;
+  int st = check_common(dict, X, N, lambda, alpha, T, prec, ckpt_every, ws, ws_bytes, &need, &sc);
   if (st != SLISTA_OK) return st;
   if (N > 0 && !Z) return fail(SLISTA_EINVAL, "Z is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  tape_forget(ws, need);
   if (loss && N == 0) {
-    LAUNCH(kKOther, (hipStream_t)stream, slista::launch_fill(loss, 1, 0.f, (hipStream_t)stream));
+    LAUNCH(kKOther, s, slista::launch_fill(loss, 1, 0.f, s));
     return SLISTA_OK;
   }
   if (N == 0) return SLISTA_OK;
-  Run r{&dict->d, make_layout(dict->d, N, T, ckpt_every), (char*)ws, N, T, (hipStream_t)stream};
-  return run_forward(r, X, lambda, alpha, prec, Z, F, f_trace, loss, true);
+  const slista::Dict& d = dict->d;
+  if ((st = check_finite(d, s, {{X, (size_t)N * d.n}, {alpha, (size_t)T}}, "the inputs X, alpha")) != SLISTA_OK)
+    return st;
+  Run r{&d, make_layout(d, N, T, ckpt_every), (char*)ws, N, T, s};
+  if ((st = run_forward(r, X, lambda, alpha, sc, Z, F, f_trace, loss, true)) != SLISTA_OK) return st;
+  if (ckpt_every >= 1) tape_record(ws, need, tape_tag(r, X, lambda, alpha, prec), true);
+  const size_t nF = F ? (f_trace ? (size_t)(T + 1) * N : (size_t)N) : 0;
+  return check_finite(d, s, {{Z, (size_t)N * d.m}, {F, nF}, {loss, loss ? 1u : 0u}}, "the outputs Z, F, loss");
 }
 
 int slista_forward_scratch(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha,
@@ -1162,45 +1393,78 @@ int slista_backward(const slista_dict* dict, const float* X, int N, float lambda
                     int prec, const float* dZ, const float* dF, float* dalpha, int ckpt_every, void* ws,
                     size_t ws_bytes, void* stream) {
   size_t need = 0;
-  int st = check_common(dict, X, N, lambda, alpha, T, prec, ckpt_every, ws, ws_bytes, &need);
+  Sched sc;
+  int st = check_common(dict, X, N, lambda, alpha, T, prec, ckpt_every, ws, ws_bytes, &need, &sc);
   if (st != SLISTA_OK) return st;
-  if (ckpt_every < 1) return fail(SLISTA_EINVAL, "backward needs the tape of a forward with ckpt_every >= 1");
+  if (ckpt_every < 1) return fail(SLISTA_EINVAL, "backward needs ckpt_every >= 1 (its tape)");
   if (!dZ && !dF) return fail(SLISTA_EINVAL, "dZ and dF are both NULL");
   if (T > 0 && !dalpha) return fail(SLISTA_EINVAL, "dalpha is NULL");
   if (T == 0) return SLISTA_OK;
+  hipStream_t s = (hipStream_t)stream;
   if (N == 0) {
-    LAUNCH(kKOther, (hipStream_t)stream, slista::launch_fill(dalpha, T, 0.f, (hipStream_t)stream));
+    LAUNCH(kKOther, s, slista::launch_fill(dalpha, T, 0.f, s));
     return SLISTA_OK;
   }
-  Run r{&dict->d, make_layout(dict->d, N, T, ckpt_every), (char*)ws, N, T, (hipStream_t)stream};
-  return run_backward(r, lambda, alpha, prec, dZ, dF, 0.f, dalpha, false, nullptr, nullptr);
+  const slista::Dict& d = dict->d;
+  if ((st = check_finite(d, s, {{X, (size_t)N * d.n}, {alpha, (size_t)T}, {dZ, dZ ? (size_t)N * d.m : 0},
+                                {dF, dF ? (size_t)N : 0}},
+                         "the inputs X, alpha, dZ, dF")) != SLISTA_OK)
+    return st;
+  Run r{&d, make_layout(d, N, T, ckpt_every), (char*)ws, N, T, s};
+  const TapeTag tag = tape_tag(r, X, lambda, alpha, prec);
+  int state = tape_state(ws, tag);
+  if (state == 0) {
+    // no tape of a forward with these arguments in ws: keep one now
+    if ((st = run_forward(r, X, lambda, alpha, sc, nullptr, nullptr, 0, nullptr, false)) != SLISTA_OK) return st;
+    state = 2;
+  }
+  if ((st = run_backward(r, lambda, alpha, sc, dZ, dF, 0.f, dalpha, false, nullptr, nullptr, false, state == 2)) !=
+      SLISTA_OK)
+    return st;
+  tape_record(ws, need, tag, state == 2 && backward_keeps_interior(r.L, T));
+  return check_finite(d, s, {{dalpha, (size_t)T}}, "the output dalpha");
 }
 
 int slista_forward_backward(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha,
                             int T, int prec, float* Z, float* F, float* loss, float* dalpha, int ckpt_every,
                             void* ws, size_t ws_bytes, void* stream) {
   size_t need = 0;
-  int st = check_common(dict, X, N, lambda, alpha, T, prec, ckpt_every, ws, ws_bytes, &need);
+  Sched sc;
+  int st = check_common(dict, X, N, lambda, alpha, T, prec, ckpt_every, ws, ws_bytes, &need, &sc);
   if (st != SLISTA_OK) return st;
   if (ckpt_every < 1) return fail(SLISTA_EINVAL, "forward_backward needs ckpt_every >= 1");
   if (N > 0 && !Z) return fail(SLISTA_EINVAL, "Z is NULL");
   if (T > 0 && !dalpha) return fail(SLISTA_EINVAL, "dalpha is NULL");
   hipStream_t s = (hipStream_t)stream;
+  tape_forget(ws, need);
   if (N == 0) {
     if (T > 0) LAUNCH(kKOther, s, slista::launch_fill(dalpha, T, 0.f, s));
     if (loss) LAUNCH(kKOther, s, slista::launch_fill(loss, 1, 0.f, s));
     return SLISTA_OK;
   }
-  Run r{&dict->d, make_layout(dict->d, N, T, ckpt_every), (char*)ws, N, T, s};
-  if (T == 0) return run_forward(r, X, lambda, alpha, prec, Z, F, 0, loss, true);
-  if (use_persist(r, prec)) {
+  const slista::Dict& d = dict->d;
+  if ((st = check_finite(d, s, {{X, (size_t)N * d.n}, {alpha, (size_t)T}}, "the inputs X, alpha")) != SLISTA_OK)
+    return st;
+  Run r{&d, make_layout(d, N, T, ckpt_every), (char*)ws, N, T, s};
+  if (T == 0) {
+    if ((st = run_forward(r, X, lambda, alpha, sc, Z, F, 0, loss, true)) != SLISTA_OK) return st;
+  } else if (use_persist(r, sc)) {
     // one persistent launch runs the forward, F(z^T) and the seed of the mean loss
-    if ((st = run_forward(r, X, lambda, alpha, prec, Z, F, 0, loss, true, r.vbuf(0), (float)(1.0 / N))) != SLISTA_OK)
+    if ((st = run_forward(r, X, lambda, alpha, sc, Z, F, 0, loss, true, r.vbuf(0), (float)(1.0 / N))) != SLISTA_OK)
       return st;
-    return run_backward(r, lambda, alpha, prec, nullptr, nullptr, 0.f, dalpha, false, nullptr, nullptr, true);
+    if ((st = run_backward(r, lambda, alpha, sc, nullptr, nullptr, 0.f, dalpha, false, nullptr, nullptr, true)) !=
+        SLISTA_OK)
+      return st;
+  } else {
+    if ((st = run_forward(r, X, lambda, alpha, sc, Z, nullptr, 0, nullptr, false)) != SLISTA_OK) return st;
+    if ((st = run_backward(r, lambda, alpha, sc, nullptr, nullptr, (float)(1.0 / N), dalpha, F || loss, F, loss)) !=
+        SLISTA_OK)
+      return st;
   }
-  if ((st = run_forward(r, X, lambda, alpha, prec, Z, nullptr, 0, nullptr, false)) != SLISTA_OK) return st;
-  return run_backward(r, lambda, alpha, prec, nullptr, nullptr, (float)(1.0 / N), dalpha, F || loss, F, loss);
+  tape_record(ws, need, tape_tag(r, X, lambda, alpha, prec), backward_keeps_interior(r.L, T));
+  return check_finite(d, s, {{Z, (size_t)N * d.m}, {F, F ? (size_t)N : 0}, {loss, loss ? 1u : 0u},
+                             {dalpha, (size_t)T}},
+                      "the outputs Z, F, loss, dalpha");
 }
 
 // ------------------------------------------------------------- FISTA
@@ -1233,6 +1497,7 @@ int slista_fista(const slista_dict* dict, const float* X, int N, float lambda, c
   size_t off[2];
   const size_t need = fista_offsets(dict->d, N, T, off);
   if (ws_bytes < need) return fail(SLISTA_EINVAL, "workspace must hold %zu bytes", need);
+  tape_forget(ws, need);
   if (N > 0 && !Z) return fail(SLISTA_EINVAL, "Z is NULL");
   hipStream_t s = (hipStream_t)stream;
   if (N == 0) {
@@ -1241,7 +1506,7 @@ int slista_fista(const slista_dict* dict, const float* X, int N, float lambda, c
   }
   const Run r{&dict->d, make_layout(dict->d, N, T, 0, false), (char*)ws, N, T, s};
   const int mp = dict->d.m_pad;
-  if (T == 0) return run_forward(r, X, lambda, alpha, prec, Z, F, 0, loss, true);  // Z = 0, F = |x|^2 / 2
+  if (T == 0) return run_forward(r, X, lambda, alpha, Sched{prec, 0, 0}, Z, F, 0, loss, true);  // Z = 0, F = |x|^2 / 2
   if ((st = prep(r, X)) != SLISTA_OK) return st;
   float* ybuf[2] = {(float*)((char*)ws + off[0]), (float*)((char*)ws + off[0] + align256(r.L.zbytes))};
   float* beta = (float*)((char*)ws + off[1]);
@@ -1317,6 +1582,7 @@ int slista_oista(const slista_dict* dict, const float* X, int N, float lambda, d
   size_t off[3];
   const size_t need = oista_offsets(dict->d, N, T, off);
   if (ws_bytes < need) return fail(SLISTA_EINVAL, "workspace must hold %zu bytes", need);
+  tape_forget(ws, need);
   if (N > 0 && !Z) return fail(SLISTA_EINVAL, "Z is NULL");
   hipStream_t s = (hipStream_t)stream;
   if (N == 0) {
@@ -1324,7 +1590,7 @@ int slista_oista(const slista_dict* dict, const float* X, int N, float lambda, d
     return SLISTA_OK;
   }
   const Run r{&dict->d, make_layout(dict->d, N, T, 0, false), (char*)ws, N, T, s};
-  if (T == 0) return run_forward(r, X, lambda, nullptr, prec, Z, F, 0, loss, true);
+  if (T == 0) return run_forward(r, X, lambda, nullptr, Sched{prec, 0, 0}, Z, F, 0, loss, true);
   const int mp = dict->d.m_pad;
   float* R = (float*)((char*)ws + off[0]);
   float* V = (float*)((char*)ws + off[1]);
@@ -1378,6 +1644,7 @@ int slista_lista_forward(const slista_dict* dict, const float* X, int N, float l
   if (T > 0 && (!W || !alpha || !beta)) return fail(SLISTA_EINVAL, "W, alpha or beta is NULL");
   const ListaLayout L = lista_layout(dict->d, N, T, prec, tape != 0);
   if ((st = lista_check_ws(L, ws, ws_bytes)) != SLISTA_OK) return st;
+  tape_forget(ws, L.total);
   hipStream_t s = (hipStream_t)stream;
   if (N == 0) {
     if (loss) LAUNCH(kKOther, s, slista::launch_fill(loss, 1, 0.f, s));
@@ -1396,6 +1663,7 @@ int slista_lista_backward(const slista_dict* dict, int N, float lambda, const fl
   if (T > 0 && (!alpha || !beta || !dalpha || !dbeta)) return fail(SLISTA_EINVAL, "alpha, beta, dalpha or dbeta is NULL");
   const ListaLayout L = lista_layout(dict->d, N, T, prec, true);
   if ((st = lista_check_ws(L, ws, ws_bytes)) != SLISTA_OK) return st;
+  tape_forget(ws, L.total);
   hipStream_t s = (hipStream_t)stream;
   if (N == 0 || T == 0) {
     if (T > 0) {
@@ -1420,6 +1688,7 @@ int slista_lista_forward_backward(const slista_dict* dict, const float* X, int N
     return fail(SLISTA_EINVAL, "W, alpha, beta, dalpha or dbeta is NULL");
   const ListaLayout L = lista_layout(dict->d, N, T, prec, true);
   if ((st = lista_check_ws(L, ws, ws_bytes)) != SLISTA_OK) return st;
+  tape_forget(ws, L.total);
   hipStream_t s = (hipStream_t)stream;
   if (N == 0) {
     if (loss) LAUNCH(kKOther, s, slista::launch_fill(loss, 1, 0.f, s));
@@ -1474,6 +1743,8 @@ int slista_train(const slista_dict* dict, const float* X, int N, float lambda, f
   const size_t need = train_extra_offsets(dict->d, N, T, off);
   if (((uintptr_t)ws & 255) || ws_bytes < need)
     return fail(SLISTA_EINVAL, "workspace must be 256-byte aligned with %zu bytes", need);
+  if (prec != SLISTA_FP32 && prec != SLISTA_BF16) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
+  tape_forget(ws, need);
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
   const size_t main_bytes = off[0];
@@ -1516,7 +1787,8 @@ int slista_train(const slista_dict* dict, const float* X, int N, float lambda, f
       }
       HIP_TRY(hipMemcpyAsync(alpha, cand, (size_t)T * sizeof(float), hipMemcpyDeviceToDevice, s));
       J = Jc;
-      if ((st = slista_backward(dict, X, N, lambda, alpha, T, prec, nullptr, dF, g, 1, ws, main_bytes, stream)) !=
+      // the gradient from the tape the candidate's forward kept (same step pointer, so the tape is used)
+      if ((st = slista_backward(dict, X, N, lambda, cand, T, prec, nullptr, dF, g, 1, ws, main_bytes, stream)) !=
           SLISTA_OK)
         return st;
       eta *= 2.0;
@@ -1538,6 +1810,7 @@ int slista_autotune(const slista_dict* dict, const float* X, int N, float lambda
                     double* ms) {
   if (!best) return fail(SLISTA_EINVAL, "best is NULL");
   if (!dict || N < 1 || T < 1 || ckpt_every < 1) return fail(SLISTA_EINVAL, "autotune needs N, T, ckpt_every >= 1");
+  if (prec != SLISTA_FP32 && prec != SLISTA_BF16) return fail(SLISTA_EINVAL, "autotune takes SLISTA_FP32 or SLISTA_BF16");
   if (g_prof.on) return fail(SLISTA_EINVAL, "kernel timing must be off while tuning");
   int nv = 0;
   for (int v = 1; v <= slista::kPersistMaxVariant; ++v) nv += slista::persist_has_variant(dict->d.m_pad, v);
@@ -1624,36 +1897,43 @@ static void batch_release_graph(slista_batch* b) {
   b->graph = nullptr;
 }
 
-// Tile rows and work count of bucket `bi` for tile variant v.
-static void batch_set_variant(slista_batch* b, size_t bi, int v) {
+// Tile rows and work count of bucket `bi` in precision pr for tile variant v.
+static void batch_set_variant(slista_batch* b, size_t bi, int pr, int v) {
   slista_batch::Bucket& bk = b->buckets[bi];
-  bk.variant = slista::persist_resolve_variant(b->prec, bk.max_m_pad, v);
-  bk.nwork = 0;
+  bk.variant[pr] = slista::persist_resolve_variant(pr, bk.max_m_pad, v);
+  bk.nwork[pr] = 0;
   for (int p : bk.problems) {
-    b->rows[p] = slista::persist_rows(b->prec, b->probs[p].dict->d.m_pad, v);
-    bk.nwork += (b->probs[p].N + b->rows[p] - 1) / b->rows[p];
+    b->rows[pr][p] = slista::persist_rows(pr, b->probs[p].dict->d.m_pad, v);
+    bk.nwork[pr] += (b->probs[p].N + b->rows[pr][p] - 1) / b->rows[pr][p];
   }
 }
 
-// (problem, tile) work lists of all buckets, uploaded to d_work; synchronises.
+static Run batch_run_of(const slista_batch* b, int p, hipStream_t s);
+
+// (problem, tile) work lists of all buckets and precisions, uploaded to
+// d_work, and, once a workspace is bound, the small kernels' table, uploaded
+// to d_small; synchronises.
 static int batch_upload_work(slista_batch* b, hipStream_t s) {
   std::vector<int2> work;
   for (auto& bk : b->buckets) {
-    bk.work_off = work.size();
     // longest tiles first: larger m_pad, then problem order
     std::vector<int> order = bk.problems;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
       return b->probs[x].dict->d.m_pad > b->probs[y].dict->d.m_pad;
     });
-    for (int p : order) {
-      const int tiles = (b->probs[p].N + b->rows[p] - 1) / b->rows[p];
-      for (int t = 0; t < tiles; ++t) work.push_back(make_int2(p, t));
+    for (int pr = 0; pr < 2; ++pr) {
+      bk.work_off[pr] = work.size();
+      if (!b->uses[pr]) continue;
+      for (int p : order) {
+        const int tiles = (b->probs[p].N + b->rows[pr][p] - 1) / b->rows[pr][p];
+        for (int t = 0; t < tiles; ++t) work.push_back(make_int2(p, t));
+      }
     }
   }
   if (work.size() > b->work_cap) {
-    // capacity for the smallest tile any variant uses (16 rows)
+    // capacity for the smallest tile any variant uses (16 rows), in both precisions
     size_t cap = 0;
-    for (const auto& q : b->probs) cap += (q.N + 15) / 16;
+    for (const auto& q : b->probs) cap += 2 * (size_t)((q.N + 15) / 16);
     cap = std::max(cap, work.size());
     HIP_TRY(hipStreamSynchronize(s));
     if (b->d_work) HIP_TRY(hipFree(b->d_work));
@@ -1663,6 +1943,48 @@ static int batch_upload_work(slista_batch* b, hipStream_t s) {
     b->work_cap = cap;
   }
   HIP_TRY(hipMemcpyAsync(b->d_work, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, s));
+  std::vector<slista::BatchSmall> small;
+  if (b->ws) {
+    // the small kernels' table: buffers of the bound workspace and the
+    // step-gradient partial counts of the current tile rows
+    const Sched sc{b->base, b->tail, b->T};
+    const int p_lo = sc.at(0), p_hi = sc.at(b->T > 0 ? b->T - 1 : 0);
+    for (auto& bk : b->buckets) {
+      bk.small_off = small.size();
+      bk.max_N = 0;
+      bk.max_group_elems = 0;
+      for (int p : bk.problems) {
+        const slista_problem& q = b->probs[p];
+        Run r = batch_run_of(b, p, s);
+        const int tiles_lo = (q.N + b->rows[p_lo][p] - 1) / b->rows[p_lo][p];
+        const int tiles_hi = (q.N + b->rows[p_hi][p] - 1) / b->rows[p_hi][p];
+        slista::BatchSmall e;
+        e.X = q.X;
+        e.N = q.N;
+        e.n = q.dict->d.n;
+        e.mp = q.dict->d.m_pad;
+        e.xsq = r.xsq();
+        e.C = r.C();
+        e.Cg = r.L.groups ? r.Cg() : nullptr;
+        e.Fd = r.Fd();
+        e.loss = q.loss;
+        e.dpart = r.dpart();
+        e.P = r.L.P;
+        e.count0 = tiles_lo;
+        e.count = tiles_lo;
+        e.t_split = sc.split();
+        e.count_hi = tiles_hi;
+        e.alpha = q.alpha;
+        e.dalpha = q.dalpha;
+        small.push_back(e);
+        bk.max_N = std::max(bk.max_N, q.N);
+        if (e.Cg) bk.max_group_elems = std::max(bk.max_group_elems, (size_t)(q.N + 3) / 4 * e.mp);
+      }
+    }
+    if (!b->d_small) HIP_TRY(hipMalloc(&b->d_small, sizeof(slista::BatchSmall) * std::max(b->P, 1)));
+    HIP_TRY(hipMemcpyAsync(b->d_small, small.data(), sizeof(slista::BatchSmall) * small.size(),
+                           hipMemcpyHostToDevice, s));
+  }
   HIP_TRY(hipStreamSynchronize(s));
   return SLISTA_OK;
 }
@@ -1672,8 +1994,10 @@ int slista_batch_create(const slista_problem* problems, int P, int T, int prec, 
   *out = nullptr;
   if (!problems || P < 1 || P > 1 << 20) return fail(SLISTA_EINVAL, "need 1 <= P problems");
   if (T < 1 || T > kMaxT) return fail(SLISTA_EINVAL, "T=%d outside [1, %d]", T, kMaxT);
-  if (prec != SLISTA_FP32 && prec != SLISTA_BF16) return fail(SLISTA_EINVAL, "unknown precision %d", prec);
   if (ckpt_every < 1 || ckpt_every > kMaxT) return fail(SLISTA_EINVAL, "ckpt_every=%d must be >= 1", ckpt_every);
+  Sched sc;
+  int st = parse_sched(prec, T, ckpt_every, &sc);
+  if (st != SLISTA_OK) return st;
   for (int p = 0; p < P; ++p) {
     const slista_problem& q = problems[p];
     if (!q.dict || !q.X || !q.alpha || !q.Z || !q.dalpha)
@@ -1688,8 +2012,12 @@ int slista_batch_create(const slista_problem* problems, int P, int T, int prec, 
   b->P = P;
   b->T = T;
   b->prec = prec;
+  b->base = sc.base;
+  b->tail = sc.tail;
   b->k = ckpt_every;
-  b->variant = g_persist_variant;
+  Span sp[2];
+  const int ns = spans_of(sc, sp);
+  for (int i = 0; i < ns; ++i) b->uses[sp[i].prec] = true;
   b->probs.assign(problems, problems + P);
   size_t off = 0;
   for (int p = 0; p < P; ++p) {
@@ -1697,7 +2025,8 @@ int slista_batch_create(const slista_problem* problems, int P, int T, int prec, 
     off += align256(make_layout(problems[p].dict->d, problems[p].N, T, ckpt_every).total);
   }
   b->total = off;
-  b->rows.assign(P, 0);
+  b->rows[0].assign(P, 0);
+  b->rows[1].assign(P, 0);
   for (int np : {8, 4, 2, 1}) {
     slista_batch::Bucket bk;
     bk.np = np;
@@ -1712,7 +2041,8 @@ int slista_batch_create(const slista_problem* problems, int P, int T, int prec, 
     bk.rows_total = (int)std::min<long long>(rows_total, kMaxN);
     b->buckets.push_back(bk);
     // one tile variant per bucket launch: forced, tuned for the bucket's rows, or default
-    batch_set_variant(b, b->buckets.size() - 1, variant_for(prec, bk.max_m_pad, bk.rows_total));
+    for (int pr = 0; pr < 2; ++pr)
+      if (b->uses[pr]) batch_set_variant(b, b->buckets.size() - 1, pr, variant_for(pr, bk.max_m_pad, bk.rows_total));
   }
   *out = b;
   return SLISTA_OK;
@@ -1734,64 +2064,103 @@ int slista_batch_bind(slista_batch* b, void* ws, size_t ws_bytes, void* stream) 
   if (!ws || ((uintptr_t)ws & 255) || ws_bytes < b->total)
     return fail(SLISTA_EINVAL, "workspace must be 256-byte aligned with %zu bytes", b->total);
   hipStream_t s = (hipStream_t)stream;
+  tape_forget(ws, ws_bytes);
   b->ws = (char*)ws;
   b->ws_bytes = ws_bytes;
   batch_release_graph(b);
-  std::vector<slista::PersistArgs> args(b->P);
-  for (int p = 0; p < b->P; ++p) {
-    const slista_problem& q = b->probs[p];
-    Run r = batch_run_of(b, p, s);
-    slista::PersistArgs a = persist_args(r, b->prec, q.alpha, q.lambda);
-    a.F = q.F;
-    a.Fd = r.Fd();
-    a.Zuser = q.Z;
-    a.Vout = r.vbuf(0);
-    a.Vio = r.vbuf(0);
-    a.dpart = r.dpart();
-    a.dF_scalar = (float)(1.0 / q.N);
-    a.mode_mask = slista::kModeF | slista::kModeSeed;
-    args[p] = a;
+  while (b->side.size() < b->buckets.size()) {
+    hipStream_t q = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    b->side.push_back(q);
   }
-  if (!b->d_args) HIP_TRY(hipMalloc(&b->d_args, sizeof(slista::PersistArgs) * b->P));
-  HIP_TRY(hipMemcpyAsync(b->d_args, args.data(), sizeof(slista::PersistArgs) * b->P, hipMemcpyHostToDevice, s));
+  while (b->ev.size() < b->buckets.size() + 1) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    b->ev.push_back(e);
+  }
+  for (int pr = 0; pr < 2; ++pr) {
+    if (!b->uses[pr]) continue;
+    std::vector<slista::PersistArgs> args(b->P);
+    for (int p = 0; p < b->P; ++p) {
+      const slista_problem& q = b->probs[p];
+      Run r = batch_run_of(b, p, s);
+      slista::PersistArgs a = persist_args(r, pr, q.alpha, q.lambda);
+      a.F = q.F;
+      a.Fd = r.Fd();
+      a.Zuser = q.Z;
+      a.Vout = r.vbuf(0);
+      a.Vio = r.vbuf(0);
+      a.dpart = r.dpart();
+      a.dF_scalar = (float)(1.0 / q.N);
+      a.mode_mask = slista::kModeF | slista::kModeSeed;
+      args[p] = a;
+    }
+    if (!b->d_args[pr]) HIP_TRY(hipMalloc(&b->d_args[pr], sizeof(slista::PersistArgs) * b->P));
+    HIP_TRY(hipMemcpyAsync(b->d_args[pr], args.data(), sizeof(slista::PersistArgs) * b->P, hipMemcpyHostToDevice, s));
+  }
   return batch_upload_work(b, s);
+}
+
+// Every launch of bucket bi (its problems' preparation, the forward and
+// backward phases, the losses and step gradients) in stream order on s.
+static int batch_run_bucket(slista_batch* b, size_t bi, hipStream_t s) {
+  const slista_batch::Bucket& bk = b->buckets[bi];
+  const int T = b->T, k = b->k;
+  const Sched sc{b->base, b->tail, T};
+  int st;
+  const slista::BatchSmall* small = b->d_small + bk.small_off;
+  const int nprob = (int)bk.problems.size();
+  // c per problem (one correlation product each), then the norms and the
+  // row-group copies of every problem in one launch
+  for (int p : bk.problems)
+    if ((st = prep_corr(batch_run_of(b, p, s), b->probs[p].X)) != SLISTA_OK) return st;
+  LAUNCH(kKOther, s, slista::launch_batch_prep(small, nprob, bk.max_N, bk.max_group_elems, s));
+  auto phase = [&](bool fwd, int pr, slista::PersistPhase ph) -> int {
+    LAUNCH(fwd ? kKFwd : kKBwd, s,
+           slista::launch_persist_batched(fwd, pr, bk.np, bk.variant[pr], b->d_args[pr], b->d_work + bk.work_off[pr],
+                                          bk.nwork[pr], bk.max_m_pad, ph, s));
+    return SLISTA_OK;
+  };
+  Span sp[2];
+  const int ns = spans_of(sc, sp);
+  for (int i = 0; i < ns; ++i) {
+    const int mode = i == ns - 1 ? (slista::kModeF | slista::kModeSeed) : 0;
+    if ((st = phase(true, sp[i].prec, slista::PersistPhase{sp[i].t0, sp[i].t1, mode, 0, 0, 0})) != SLISTA_OK)
+      return st;
+  }
+  LAUNCH(kKOther, s, slista::launch_batch_loss(small, nprob, s));
+  if (k == 1) {
+    for (int i = ns - 1; i >= 0; --i)
+      if ((st = phase(false, sp[i].prec, slista::PersistPhase{0, 0, 0, 0, sp[i].t1 - 1, sp[i].t0})) != SLISTA_OK)
+        return st;
+  } else {
+    const int nseg = (T + k - 1) / k;
+    for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+      const int a0 = sgi * k;
+      const int e = (a0 + k < T) ? a0 + k : T;
+      const int pr = sc.at(a0);
+      if (sgi != nseg - 1 && e - 1 > a0)
+        if ((st = phase(true, pr, slista::PersistPhase{a0, e - 1, 0, 1, 0, 0})) != SLISTA_OK) return st;
+      if ((st = phase(false, pr, slista::PersistPhase{0, 0, 0, 0, e - 1, a0})) != SLISTA_OK) return st;
+    }
+  }
+  LAUNCH(kKOther, s, slista::launch_batch_dalpha(small, nprob, T, s));
+  return SLISTA_OK;
 }
 
 int slista_batch_run(slista_batch* b, void* stream) {
   if (!b || !b->ws) return fail(SLISTA_EINVAL, "batch is NULL or not bound to a workspace");
   hipStream_t s = (hipStream_t)stream;
-  const int T = b->T, k = b->k, prec = b->prec;
   int st;
-  for (int p = 0; p < b->P; ++p)
-    if ((st = prep(batch_run_of(b, p, s), b->probs[p].X)) != SLISTA_OK) return st;
-  auto phase = [&](bool fwd, slista::PersistPhase ph) -> int {
-    for (const auto& bk : b->buckets)
-      LAUNCH(fwd ? kKFwd : kKBwd, s,
-             slista::launch_persist_batched(fwd, prec, bk.np, bk.variant, b->d_args, b->d_work + bk.work_off,
-                                            bk.nwork, bk.max_m_pad, ph, s));
-    return SLISTA_OK;
-  };
-  if ((st = phase(true, slista::PersistPhase{0, T, slista::kModeF | slista::kModeSeed, 0, 0, 0})) != SLISTA_OK)
-    return st;
-  for (int p = 0; p < b->P; ++p)
-    if (b->probs[p].loss) {
-      Run r = batch_run_of(b, p, s);
-      LAUNCH(kKOther, s, slista::launch_reduce_loss(r.Fd(), r.N, b->probs[p].loss, s));
-    }
-  const int seg_len = k == 1 ? T : k;
-  const int nseg = (T + seg_len - 1) / seg_len;
-  for (int sgi = nseg - 1; sgi >= 0; --sgi) {
-    const int a0 = sgi * seg_len;
-    const int e = (a0 + seg_len < T) ? a0 + seg_len : T;
-    if (k > 1 && sgi != nseg - 1 && e - 1 > a0)
-      if ((st = phase(true, slista::PersistPhase{a0, e - 1, 0, 1, 0, 0})) != SLISTA_OK) return st;
-    if ((st = phase(false, slista::PersistPhase{0, 0, 0, 0, e - 1, a0})) != SLISTA_OK) return st;
-  }
-  for (int p = 0; p < b->P; ++p) {
-    Run r = batch_run_of(b, p, s);
-    const int tiles = (r.N + b->rows[p] - 1) / b->rows[p];
-    LAUNCH(kKOther, s, slista::launch_reduce_dalpha(r.dpart(), T, r.L.P, tiles, tiles, b->probs[p].alpha,
-                                                    b->probs[p].dalpha, s));
+  const size_t nb = b->buckets.size();
+  if (nb == 1) return batch_run_bucket(b, 0, s);
+  // the buckets share nothing: fork one stream per bucket from s and join them back
+  HIP_TRY(hipEventRecord(b->ev[0], s));
+  for (size_t bi = 0; bi < nb; ++bi) {
+    HIP_TRY(hipStreamWaitEvent(b->side[bi], b->ev[0], 0));
+    if ((st = batch_run_bucket(b, bi, b->side[bi])) != SLISTA_OK) return st;
+    HIP_TRY(hipEventRecord(b->ev[1 + bi], b->side[bi]));
+    HIP_TRY(hipStreamWaitEvent(s, b->ev[1 + bi], 0));
   }
   return SLISTA_OK;
 }
@@ -1807,36 +2176,39 @@ int slista_batch_autotune(slista_batch* b, void* stream, int* variants) {
     return fail(SLISTA_EHIP, "hipEventCreate failed");
   }
   int st = SLISTA_OK;
-  // one bucket at a time, the others at their current variant
+  // one (bucket, precision) pair at a time, the others at their current variant
   for (size_t bi = 0; bi < b->buckets.size() && st == SLISTA_OK; ++bi) {
-    const int mp = b->buckets[bi].max_m_pad;
-    int nv = 0;
-    for (int v = 1; v <= slista::kPersistMaxVariant; ++v) nv += slista::persist_has_variant(mp, v);
-    if (nv < 2) continue;
-    int bestv = b->buckets[bi].variant;
-    double bestms = 1e300;
-    for (int v = 1; v <= slista::kPersistMaxVariant && st == SLISTA_OK; ++v) {
-      if (!slista::persist_has_variant(mp, v)) continue;
-      batch_set_variant(b, bi, v);
-      if ((st = batch_upload_work(b, s)) != SLISTA_OK) break;
-      if ((st = slista_batch_run(b, stream)) != SLISTA_OK) break;  // warm-up
-      if (hipEventRecord(e0, s) != hipSuccess) { st = fail(SLISTA_EHIP, "hipEventRecord failed"); break; }
-      if ((st = slista_batch_run(b, stream)) != SLISTA_OK) break;
-      float t = 0.f;
-      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
-        st = fail(SLISTA_EHIP, "event timing failed");
-        break;
+    for (int pr = 0; pr < 2 && st == SLISTA_OK; ++pr) {
+      if (!b->uses[pr]) continue;
+      const int mp = b->buckets[bi].max_m_pad;
+      int nv = 0;
+      for (int v = 1; v <= slista::kPersistMaxVariant; ++v) nv += slista::persist_has_variant(mp, v);
+      if (nv < 2) continue;
+      int bestv = b->buckets[bi].variant[pr];
+      double bestms = 1e300;
+      for (int v = 1; v <= slista::kPersistMaxVariant && st == SLISTA_OK; ++v) {
+        if (!slista::persist_has_variant(mp, v)) continue;
+        batch_set_variant(b, bi, pr, v);
+        if ((st = batch_upload_work(b, s)) != SLISTA_OK) break;
+        if ((st = slista_batch_run(b, stream)) != SLISTA_OK) break;  // warm-up
+        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(SLISTA_EHIP, "hipEventRecord failed"); break; }
+        if ((st = slista_batch_run(b, stream)) != SLISTA_OK) break;
+        float t = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+          st = fail(SLISTA_EHIP, "event timing failed");
+          break;
+        }
+        if (t < bestms) {
+          bestms = t;
+          bestv = v;
+        }
       }
-      if (t < bestms) {
-        bestms = t;
-        bestv = v;
+      batch_set_variant(b, bi, pr, bestv);
+      if (st == SLISTA_OK) {
+        const auto& bk = b->buckets[bi];
+        record_tuned(pr, bk.np, log2_bucket(bk.rows_total), bestv);
       }
-    }
-    batch_set_variant(b, bi, bestv);
-    if (st == SLISTA_OK) {
-      const auto& bk = b->buckets[bi];
-      record_tuned(b->prec, bk.np, log2_bucket(bk.rows_total), bestv);
     }
   }
   (void)hipEventDestroy(e0);
@@ -1845,8 +2217,10 @@ int slista_batch_autotune(slista_batch* b, void* stream, int* variants) {
   if (st != SLISTA_OK) return st;
   if (st2 != SLISTA_OK) return st2;
   if (variants) {
+    // the variants of the schedule's first precision (the only one without an FP32 tail)
+    const int pr = b->uses[b->base] ? b->base : (int)slista::kF32;
     for (int i = 0; i < 4; ++i) variants[i] = 0;
-    for (const auto& bk : b->buckets) variants[bk.np == 1 ? 0 : bk.np == 2 ? 1 : bk.np == 4 ? 2 : 3] = bk.variant;
+    for (const auto& bk : b->buckets) variants[bk.np == 1 ? 0 : bk.np == 2 ? 1 : bk.np == 4 ? 2 : 3] = bk.variant[pr];
   }
   return SLISTA_OK;
 }
@@ -1880,9 +2254,171 @@ int slista_batch_destroy(slista_batch* b) {
   if (!b) return SLISTA_OK;
   (void)hipDeviceSynchronize();
   batch_release_graph(b);
-  (void)hipFree(b->d_args);
+  (void)hipFree(b->d_args[0]);
+  (void)hipFree(b->d_args[1]);
   (void)hipFree(b->d_work);
+  (void)hipFree(b->d_small);
+  for (hipStream_t q : b->side) (void)hipStreamDestroy(q);
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
   delete b;
+  return SLISTA_OK;
+}
+
+// ------------------------------------------------------------- checks
+int slista_kkt(const slista_dict* dict, const float* X, int N, float lambda, const float* Z, double* kkt, double* F,
+               void* stream) {
+  if (!dict) return fail(SLISTA_EINVAL, "dict is NULL");
+  if (N < 0 || N > kMaxN) return fail(SLISTA_EINVAL, "N=%d outside [0, %d]", N, kMaxN);
+  if (!(lambda >= 0.f) || !std::isfinite(lambda)) return fail(SLISTA_EINVAL, "lambda must be finite and >= 0");
+  if (N > 0 && (!X || !Z || !kkt)) return fail(SLISTA_EINVAL, "X, Z or kkt is NULL");
+  if (dict->d.n > slista::kkt_max_n())
+    return fail(SLISTA_ENOTSUP, "slista_kkt supports n <= %d (n=%d)", slista::kkt_max_n(), dict->d.n);
+  hipStream_t s = (hipStream_t)stream;
+  LAUNCH(kKOther, s, slista::launch_kkt(X, dict->d.Dt, N, dict->d.n, dict->d.m, (double)lambda, Z, kkt, F, s));
+  return SLISTA_OK;
+}
+
+int slista_lambda_max_workspace_size(const slista_dict* dict, int N, size_t* bytes) {
+  if (!dict || !bytes) return fail(SLISTA_EINVAL, "dict or bytes is NULL");
+  if (N < 0 || N > kMaxN) return fail(SLISTA_EINVAL, "N=%d outside [0, %d]", N, kMaxN);
+  *bytes = align256((size_t)N * dict->d.m_pad * sizeof(float)) + align256((size_t)(N > 0 ? N : 1) * sizeof(float));
+  return SLISTA_OK;
+}
+
+int slista_lambda_max(const slista_dict* dict, const float* X, int N, float* lam_max, float* lam_max_rows, void* ws,
+                      size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  int st = slista_lambda_max_workspace_size(dict, N, &need);
+  if (st != SLISTA_OK) return st;
+  if (!lam_max) return fail(SLISTA_EINVAL, "lam_max is NULL");
+  if (N > 0 && !X) return fail(SLISTA_EINVAL, "X is NULL");
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need)
+    return fail(SLISTA_EINVAL, "workspace must be 256-byte aligned with %zu bytes", need);
+  tape_forget(ws, need);
+  hipStream_t s = (hipStream_t)stream;
+  const slista::Dict& d = dict->d;
+  float* C = (float*)ws;
+  float* rows = lam_max_rows ? lam_max_rows : (float*)((char*)ws + align256((size_t)N * d.m_pad * sizeof(float)));
+  if (N > 0) {
+    // the correlation product of the forward pass, same kernel and launch shape
+    slista::GemmArgs g;
+    std::memset(&g, 0, sizeof g);
+    g.A = X;
+    g.lda = d.n;
+    g.Bt = d.Dt;
+    g.ldb = d.n;
+    g.rows = N;
+    g.ncols = d.m_pad;
+    g.K = d.n;
+    g.Out = C;
+    g.ldz = d.m_pad;
+    slista::gemm_grid(N, d.m_pad, g);
+    LAUNCH(kKCorr, s, slista::launch_gemm(slista::kF32, slista::kEpiCorr, true, g, s));
+    LAUNCH(kKOther, s, slista::launch_row_absmax(C, N, d.m_pad, d.m, rows, s));
+  }
+  LAUNCH(kKOther, s, slista::launch_absmax(rows, N, 1, 1, lam_max, s));
+  return SLISTA_OK;
+}
+
+// ------------------------------------------------------------- one-call batches
+// Plans (a bound slista_batch, its captured graph and a capture stream) kept
+// per (problem array contents, T, prec, ckpt_every, workspace), least recently
+// used first out.
+namespace {
+struct Plan {
+  std::vector<unsigned char> key;
+  slista_batch* b = nullptr;
+  hipStream_t cap = nullptr;
+  bool captured = false;
+};
+std::mutex g_plan_mu;
+std::vector<Plan> g_plans;
+constexpr size_t kMaxPlans = 8;
+
+void plan_release(Plan& pl) {
+  if (pl.b) slista_batch_destroy(pl.b);
+  if (pl.cap) (void)hipStreamDestroy(pl.cap);
+  pl.b = nullptr;
+  pl.cap = nullptr;
+}
+
+std::vector<unsigned char> plan_key(const slista_problem* problems, int P, int T, int prec, int k, void* ws,
+                                    size_t ws_bytes) {
+  std::vector<unsigned char> key(sizeof(slista_problem) * (size_t)P + 3 * sizeof(int) + sizeof(void*) +
+                                 sizeof(size_t));
+  unsigned char* q = key.data();
+  std::memcpy(q, problems, sizeof(slista_problem) * (size_t)P);
+  q += sizeof(slista_problem) * (size_t)P;
+  const int v[3] = {T, prec, k};
+  std::memcpy(q, v, sizeof v);
+  q += sizeof v;
+  std::memcpy(q, &ws, sizeof ws);
+  q += sizeof ws;
+  std::memcpy(q, &ws_bytes, sizeof ws_bytes);
+  return key;
+}
+}  // namespace
+
+int slista_batched_workspace_size(const slista_problem* problems, int P, int T, int prec, int ckpt_every,
+                                  size_t* bytes) {
+  if (!bytes) return fail(SLISTA_EINVAL, "bytes is NULL");
+  slista_batch* b = nullptr;
+  const int st = slista_batch_create(problems, P, T, prec, ckpt_every, &b);
+  if (st != SLISTA_OK) return st;
+  *bytes = b->total;
+  slista_batch_destroy(b);
+  return SLISTA_OK;
+}
+
+int slista_batched_fwd_bwd(const slista_problem* problems, int P, int T, int prec, int ckpt_every, void* ws,
+                           size_t ws_bytes, void* stream, int use_graph) {
+  if (!problems || P < 1 || P > 1 << 20) return fail(SLISTA_EINVAL, "need 1 <= P problems");
+  if (use_graph && g_prof.on) return fail(SLISTA_EINVAL, "kernel timing must be off with use_graph");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<unsigned char> key = plan_key(problems, P, T, prec, ckpt_every, ws, ws_bytes);
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  size_t idx = g_plans.size();
+  for (size_t i = 0; i < g_plans.size(); ++i)
+    if (g_plans[i].key == key) idx = i;
+  if (idx == g_plans.size()) {
+    Plan pl;
+    pl.key = std::move(key);
+    int st = slista_batch_create(problems, P, T, prec, ckpt_every, &pl.b);
+    if (st == SLISTA_OK) st = slista_batch_bind(pl.b, ws, ws_bytes, stream);
+    if (st != SLISTA_OK) {
+      plan_release(pl);
+      return st;
+    }
+    if (g_plans.size() >= kMaxPlans) {
+      plan_release(g_plans.front());
+      g_plans.erase(g_plans.begin());
+    }
+    g_plans.push_back(std::move(pl));
+    idx = g_plans.size() - 1;
+  } else if (idx + 1 != g_plans.size()) {
+    // most recently used last
+    Plan pl = std::move(g_plans[idx]);
+    g_plans.erase(g_plans.begin() + (long)idx);
+    g_plans.push_back(std::move(pl));
+    idx = g_plans.size() - 1;
+  }
+  Plan& pl = g_plans[idx];
+  if (!use_graph) return slista_batch_run(pl.b, stream);
+  if (!pl.captured) {
+    // capture on a stream of the plan's own (a legacy default stream cannot
+    // be captured); the graph is then launched on the caller's stream
+    if (!pl.cap) HIP_TRY(hipStreamCreateWithFlags(&pl.cap, hipStreamNonBlocking));
+    const int st = slista_batch_capture(pl.b, pl.cap);
+    if (st != SLISTA_OK) return st;
+    pl.captured = true;
+  }
+  return slista_batch_replay(pl.b, s);
+}
+
+int slista_batched_release(void) {
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  for (auto& pl : g_plans) plan_release(pl);
+  g_plans.clear();
   return SLISTA_OK;
 }
 

@@ -41,6 +41,7 @@ struct Dict {
   uint16_t* Gb;    // [m_pad][m_pad] BF16 copy (bit pattern), zero padded
   float* Dt;       // [m_pad][n]     D^T, zero rows for j >= m
   double* pwork;   // power iteration scratch: [2 * m_pad + 4]
+  unsigned int* flag;  // non-finite counter of the finite-value checks
   uint16_t* Gsb;   // BF16 G in MFMA fragment order (persistent kernels)
   float* Gsf;      // FP32 G in MFMA fragment order (persistent kernels)
 };
@@ -142,10 +143,47 @@ hipError_t launch_lista_reduce_w(const float* part, int S, size_t count, const f
                                  hipStream_t s);
 hipError_t launch_bwd0(const float* V0, const float* Z1, int N, int ldz, double* dpart, int nblocks,
                        hipStream_t s);
+// dalpha_t = -(1/alpha_t) sum of the first n_t partials of row t of dpart
+// [T][P]: n_0 = count0, n_t = count for 0 < t < t_split, count_hi for
+// t >= t_split (layers run with different tile sizes).
 hipError_t launch_reduce_dalpha(const double* dpart, int T, int P, int count0, int count, const float* alpha,
-                                float* dalpha, hipStream_t s);
+                                float* dalpha, hipStream_t s, int t_split = 1 << 30, int count_hi = 0);
 int bwd0_blocks(int N, int ldz);
 hipError_t launch_objective(const float* X, const float* Dt, int N, int n, int m, float lam, const float* Z,
                             float* F, hipStream_t s);
+// The small per-problem steps of an uneven batch in one launch each over a
+// table of problems (device memory): the norms ||x_i||^2 and the row-group
+// copy of c before the forward; the mean loss and the step gradients after
+// the backward. Per problem the arithmetic and its order are those of
+// launch_xsq / launch_row_groups / launch_reduce_loss / launch_reduce_dalpha.
+struct BatchSmall {
+  const float* X;            // [N, n]
+  int N, n, mp;
+  double* xsq;               // [N]
+  const float* C;            // [N, mp] row-major c
+  float* Cg;                 // its row-group copy, or NULL
+  const double* Fd;          // [N] per-sample objectives
+  float* loss;               // mean objective, or NULL
+  const double* dpart;       // [T][P] step-gradient partials
+  int P, count0, count, t_split, count_hi;
+  const float* alpha;        // [T]
+  float* dalpha;             // [T]
+};
+hipError_t launch_batch_prep(const BatchSmall* tab, int nprob, int max_N, size_t max_group_elems, hipStream_t s);
+hipError_t launch_batch_loss(const BatchSmall* tab, int nprob, hipStream_t s);
+hipError_t launch_batch_dalpha(const BatchSmall* tab, int nprob, int T, hipStream_t s);
+// Checks (kernels_check.hip).
+// Per sample, in FP64: the largest violation of the Lasso optimality
+// conditions (Lemma 2.1) by z_i, and F(z_i) (Eq. (1)); n <= kkt_max_n().
+int kkt_max_n();
+hipError_t launch_kkt(const float* X, const float* Dt, int N, int n, int m, double lam, const float* Z, double* kkt,
+                      double* F, hipStream_t s);
+// *out = max over i < N, j < m of |C[i][ld * i + j]| (out zeroed first).
+hipError_t launch_absmax(const float* C, int N, int ld, int m, float* out, hipStream_t s);
+// out[i] = max over j < m of |C[i ld + j]| for i < N.
+hipError_t launch_row_absmax(const float* C, int N, int ld, int m, float* out, hipStream_t s);
+hipError_t launch_zero_u32(unsigned int* p, hipStream_t s);
+// *out += number of NaN / Inf entries of p[0..count).
+hipError_t launch_count_nonfinite(const float* p, size_t count, unsigned int* out, hipStream_t s);
 
 }  // namespace slista

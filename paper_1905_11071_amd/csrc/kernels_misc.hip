@@ -131,9 +131,9 @@ __global__ __launch_bounds__(1024) void k_power_norm(int m, int mp, int max_iter
 }
 
 // ||x_i||^2 in FP64, one wave per sample.
-__global__ void k_xsq(const float* __restrict__ X, int N, int n, double* __restrict__ xsq) {
+__device__ void xsq_rows(const float* __restrict__ X, int N, int n, double* __restrict__ xsq, int block) {
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int i = block * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= N) return;
   double s = 0.0;
   for (int k = lane; k < n; k += 64) {
@@ -142,6 +142,10 @@ __global__ void k_xsq(const float* __restrict__ X, int N, int n, double* __restr
   }
   for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
   if (lane == 0) xsq[i] = s;
+}
+
+__global__ void k_xsq(const float* __restrict__ X, int N, int n, double* __restrict__ xsq) {
+  xsq_rows(X, N, n, xsq, blockIdx.x);
 }
 
 // First layer from z^(0) = 0: the product vanishes, so
@@ -183,7 +187,7 @@ __global__ void k_fill(float* __restrict__ p, size_t count, float v) {
 // persistent kernels' accumulator, so a lane reads its four rows at once).
 // One thread per (group, column): coalesced reads of four rows, coalesced
 // 16-byte writes.
-__global__ void k_row_groups(const float* __restrict__ A, int N, int ld, float4* __restrict__ out) {
+__device__ void row_groups(const float* __restrict__ A, int N, int ld, float4* __restrict__ out) {
   const size_t ng = (size_t)(N + 3) / 4, total = ng * ld;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
     const size_t q = e / ld;
@@ -195,6 +199,10 @@ __global__ void k_row_groups(const float* __restrict__ A, int N, int ld, float4*
     v.w = i + 3 < N ? A[(size_t)(i + 3) * ld + j] : 0.f;
     out[e] = v;
   }
+}
+
+__global__ void k_row_groups(const float* __restrict__ A, int N, int ld, float4* __restrict__ out) {
+  row_groups(A, N, ld, out);
 }
 
 // F_i = 1/2 ||x_i||^2 + sum over column tiles of the fused partials
@@ -276,7 +284,11 @@ __global__ void k_fista_beta(int T, float* __restrict__ beta) {
 // exhausted. Supports of at most kLsCache atoms read G_SS from LDS (gathered
 // once), larger ones read G from L2. step[i] = 1/L_S, 1/L for an empty
 // support. One 64-lane workgroup per sample: reductions are fixed-order
-// shuffles and the barriers cost one wave. V is not used.
+// shuffles and the barriers cost one wave. L_S depends on the support alone
+// (and the run is deterministic), so a sample whose support has not changed
+// since the last call keeps step[i]: row i of V holds that support as a
+// bitmask (one 64-bit word per 64 columns) and, in its last word, a flag
+// that step[i] is valid (V zero-filled before the first layer).
 constexpr int kLsLanes = 64;
 constexpr int kLsCache = 64;
 constexpr int kLsMaxSteps = 128;  // Krylov dimension cap
@@ -340,7 +352,6 @@ __global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __r
                                                                const float* __restrict__ Z, float* __restrict__ V,
                                                                double L, int max_iter, double tol,
                                                                float* __restrict__ step) {
-  (void)V;
   extern __shared__ __attribute__((aligned(16))) char sm[];
   double* q = (double*)sm;                  // [mp] q_j
   double* qp = q + mp;                      // [mp] q_{j-1}
@@ -351,6 +362,9 @@ __global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __r
   int* idx = (int*)(gs + kLsCache * (kLsCache + 1)); // [mp]
   const int i = blockIdx.x, lane = threadIdx.x;
   const float* z = Z + (size_t)i * mp;
+  unsigned long long* memo = (unsigned long long*)(V + (size_t)i * mp);  // [mp / 2] words
+  const int valid_word = mp / 2 - 1;
+  bool same = memo[valid_word] != 0ull;
   int ns = 0;
   for (int j0 = 0; j0 < m; j0 += kLsLanes) {
     const int j = j0 + lane;
@@ -358,8 +372,20 @@ __global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __r
     const unsigned long long ball = __ballot(nz);
     if (nz) idx[ns + __popcll(ball & ((1ull << lane) - 1ull))] = j;
     ns += __popcll(ball);
+    same = same && memo[j0 / kLsLanes] == ball;
   }
   __syncthreads();
+  if (same) return;  // the support of the last call: step[i] holds its 1/L_S
+  // record this support (every lane holds every ballot; lane 0 writes them)
+  {
+    int j0 = 0;
+    for (int c = 0; j0 < m; ++c, j0 += kLsLanes) {
+      const int j = j0 + lane;
+      const unsigned long long ball = __ballot(j < m && z[j] != 0.f);
+      if (lane == 0) memo[c] = ball;
+    }
+    if (lane == 0) memo[valid_word] = 1ull;
+  }
   if (ns == 0) {
     if (lane == 0) step[i] = (float)(1.0 / L);
     return;
@@ -457,15 +483,42 @@ __global__ void k_bwd0(const float* __restrict__ V0, const float* __restrict__ Z
 // dalpha_t = -(1/alpha_t) sum_p dpart[t][p]: on the active set,
 // z^t - z^{t+1} = alpha_t (G z^t - c + lam sign u), so this equals
 // -sum v (G z^t - c + lam sign u), the derivative of the layer output in a_t.
-__global__ void k_reduce_dalpha(const double* __restrict__ dpart, int P, int count0, int count,
-                                const float* __restrict__ alpha, float* __restrict__ dalpha) {
-  __shared__ double sh[kRedThreads];
-  const int t = blockIdx.x;
-  const int n = t == 0 ? count0 : count;
+__device__ void reduce_dalpha_layer(const double* __restrict__ dpart, int P, int count0, int count, int t_split,
+                                    int count_hi, const float* __restrict__ alpha, float* __restrict__ dalpha,
+                                    int t, double* sh) {
+  const int n = t == 0 ? count0 : (t >= t_split ? count_hi : count);
   double s = 0.0;
   for (int p = threadIdx.x; p < n; p += blockDim.x) s += dpart[(size_t)t * P + p];
   s = block_sum(s, sh);
   if (threadIdx.x == 0) dalpha[t] = (float)(-s / (double)alpha[t]);
+}
+
+__global__ void k_reduce_dalpha(const double* __restrict__ dpart, int P, int count0, int count, int t_split,
+                                int count_hi, const float* __restrict__ alpha, float* __restrict__ dalpha) {
+  __shared__ double sh[kRedThreads];
+  reduce_dalpha_layer(dpart, P, count0, count, t_split, count_hi, alpha, dalpha, blockIdx.x, sh);
+}
+
+// Uneven batches: blockIdx.y indexes the bucket's problem table.
+__global__ void k_batch_prep(const BatchSmall* __restrict__ tab) {
+  const BatchSmall& b = tab[blockIdx.y];
+  // the norms: the blocks of k_xsq's grid, then the rest of this grid idles
+  if ((int)blockIdx.x < (b.N + 3) / 4) xsq_rows(b.X, b.N, b.n, b.xsq, blockIdx.x);
+  if (b.Cg) row_groups(b.C, b.N, b.mp, (float4*)b.Cg);
+}
+
+__global__ void k_batch_reduce_dalpha(const BatchSmall* __restrict__ tab) {
+  __shared__ double sh[kRedThreads];
+  const BatchSmall& b = tab[blockIdx.y];
+  reduce_dalpha_layer(b.dpart, b.P, b.count0, b.count, b.t_split, b.count_hi, b.alpha, b.dalpha, blockIdx.x, sh);
+}
+
+__global__ __launch_bounds__(kSumThreads) void k_batch_reduce_loss(const BatchSmall* __restrict__ tab) {
+  __shared__ double sh[kSumThreads];
+  const BatchSmall& b = tab[blockIdx.x];
+  if (!b.loss) return;
+  const double s = sum_fixed(b.Fd, b.N, sh);
+  if (threadIdx.x == 0) *b.loss = b.N > 0 ? (float)(s / b.N) : 0.f;
 }
 
 // F_i = 1/2 ||x_i - D z_i||^2 + lam ||z_i||_1 (Eq. (1)), one wave per sample.
@@ -641,10 +694,33 @@ hipError_t launch_bwd0(const float* V0, const float* Z1, int N, int ldz, double*
   return hipGetLastError();
 }
 
+hipError_t launch_batch_prep(const BatchSmall* tab, int nprob, int max_N, size_t max_group_elems, hipStream_t s) {
+  if (nprob == 0 || max_N == 0) return hipSuccess;
+  // as many blocks as k_xsq needs for the largest problem, at least as many
+  // as k_row_groups' grid-stride loop would use
+  const size_t bx_xsq = (size_t)(max_N + 3) / 4, bx_grp = (size_t)grid_for(max_group_elems, 256 * 4);
+  const size_t bx = bx_xsq > bx_grp ? bx_xsq : bx_grp;
+  hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)bx, nprob), dim3(256), 0, s, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_loss(const BatchSmall* tab, int nprob, hipStream_t s) {
+  if (nprob == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_reduce_loss, dim3(nprob), dim3(kSumThreads), 0, s, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_dalpha(const BatchSmall* tab, int nprob, int T, hipStream_t s) {
+  if (nprob == 0 || T == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_reduce_dalpha, dim3(T, nprob), dim3(kRedThreads), 0, s, tab);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce_dalpha(const double* dpart, int T, int P, int count0, int count, const float* alpha,
-                                float* dalpha, hipStream_t s) {
+                                float* dalpha, hipStream_t s, int t_split, int count_hi) {
   if (T == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_dalpha, dim3(T), dim3(kRedThreads), 0, s, dpart, P, count0, count, alpha, dalpha);
+  hipLaunchKernelGGL(k_reduce_dalpha, dim3(T), dim3(kRedThreads), 0, s, dpart, P, count0, count, t_split, count_hi,
+                     alpha, dalpha);
   return hipGetLastError();
 }
 

@@ -24,6 +24,10 @@ struct PersistArgs {
   size_t zbytes;
   int k, T, a_last;
   int store_all;
+  // a launch that ends (starts) inside the network without a tape slot for
+  // that iterate writes (reads) it here instead, in tape order; else NULL
+  float* zsave;
+  const float* zload;
   // forward range and outputs
   int t_begin, t_end, mode;
   float* F;

@@ -355,7 +355,8 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
 #pragma unroll
           for (int r4 = 0; r4 < 4; ++r4) zm[p][fm][f][r4] = 0.f;
   } else {
-    load_master_tape<FM, FB, NP, WC>(zm, slot_ptr(g, g.t_begin), row0 + rbase, N, m_pad, npass, wave, lane);
+    load_master_tape<FM, FB, NP, WC>(zm, g.zload ? g.zload : slot_ptr(g, g.t_begin), row0 + rbase, N, m_pad, npass,
+                                     wave, lane);
   }
   master_to_lds<P, FM, FB, NP, WC>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
   __syncthreads();
@@ -434,6 +435,24 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
     __syncthreads();
   }
 
+  if (g.zsave) {
+    // z^(t_end) for a launch that continues the network (tape order)
+    const Rsrc rS = make_rsrc(g.zsave + (size_t)row0 * m_pad, tape_bytes(nrows, m_pad));
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int slab = WC * p + wave;
+      if (!(p < npass && slab * 16 * FB < m_pad)) continue;
+      const int lt = (lg * m_pad + 16 * FB * slab + lr) * 16;
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+        if (rbase + 16 * fm + 4 * lg < nrows) {
+#pragma unroll
+          for (int f = 0; f < FB; ++f)
+            bstore4(make_float4(zm[p][fm][f][0], zm[p][fm][f][1], zm[p][fm][f][2], zm[p][fm][f][3]), rS,
+                    lt + 256 * f, (rbase + 16 * fm) * rstride);
+        }
+    }
+  }
   if (!(g.mode & (kModeF | kModeSeed))) return;
   // final contraction: F(z^(t_end)) and / or the seed of the backward pass
   const bool want_f = (g.mode & kModeF) != 0;

@@ -15,6 +15,14 @@ from ._lib import SlistaError, check, lib  # noqa: F401
 PRECISIONS = {"fp32": 0, "bf16": 1}
 
 
+def bf16_fp32_tail(tail: int) -> int:
+    """Precision schedule: BF16 contractions, then FP32 in the last `tail`
+    layers (SLISTA_BF16_FP32_TAIL)."""
+    if tail < 0:
+        raise ValueError("tail must be >= 0")
+    return PRECISIONS["bf16"] | (int(tail) << 8)
+
+
 def _prec(prec) -> int:
     if isinstance(prec, int):
         return prec
@@ -148,6 +156,34 @@ def objective(d: Dictionary, X: torch.Tensor, lam: float, Z: torch.Tensor) -> to
     check(lib().slista_objective(d.handle, X.data_ptr(), int(X.shape[0]), float(lam), Z.data_ptr(), F.data_ptr(),
                                  _stream(d.device)))
     return F
+
+
+def kkt(d: Dictionary, X: torch.Tensor, lam: float, Z: torch.Tensor):
+    """(kkt, F): per sample, in FP64 on the device, the largest violation of
+    the Lasso optimality conditions (Lemma 2.1) by the codes Z, and F(z)."""
+    X = _dev_f32(X, "X")
+    Z = _dev_f32(Z, "Z", (X.shape[0], d.m))
+    N = int(X.shape[0])
+    k = torch.empty(N, device=d.device, dtype=torch.float64)
+    F = torch.empty(N, device=d.device, dtype=torch.float64)
+    check(lib().slista_kkt(d.handle, X.data_ptr(), N, float(lam), Z.data_ptr(), k.data_ptr(), F.data_ptr(),
+                           _stream(d.device)))
+    return k, F
+
+
+def lambda_max(d: Dictionary, X: torch.Tensor):
+    """(max_i ||D^T x_i||_inf as a Python float, the per-sample values [N])
+    from the forward pass's own correlation product."""
+    X = _dev_f32(X, "X")
+    N = int(X.shape[0])
+    nbytes = ctypes.c_size_t()
+    check(lib().slista_lambda_max_workspace_size(d.handle, N, ctypes.byref(nbytes)))
+    ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=d.device)
+    out = torch.empty(1, device=d.device, dtype=torch.float32)
+    rows = torch.empty(max(N, 1), device=d.device, dtype=torch.float32)
+    check(lib().slista_lambda_max(d.handle, X.data_ptr(), N, out.data_ptr(), rows.data_ptr(), ws.data_ptr(),
+                                  ws.numel(), _stream(d.device)))
+    return float(out.item()), rows[:N]
 
 
 def backward(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, ws: torch.Tensor,
@@ -348,7 +384,56 @@ class Batch:
             pass
 
 
+class BatchedCall:
+    """The one-call batch entry point (slista_batched_fwd_bwd): the library
+    plans the batch on the first call (and captures a HIP graph if asked) and
+    replays it on later calls. Same inputs and outputs as Batch."""
+
+    def __init__(self, problems, prec="fp32", ckpt_every: int = 1):
+        from ._lib import Problem
+        if not problems:
+            raise ValueError("empty batch")
+        self.T = int(problems[0][3].shape[0])
+        self.device = problems[0][0].device
+        self.prec, self.ckpt = _prec(prec), int(ckpt_every)
+        self._keep = []
+        self.Z, self.F, self.loss, self.dalpha = [], [], [], []
+        self._arr = (Problem * len(problems))()
+        for i, (d, X, lam, alpha) in enumerate(problems):
+            X, alpha = _check_inputs(d, X, alpha)
+            N = int(X.shape[0])
+            out = (torch.empty(N, d.m, device=d.device, dtype=torch.float32),
+                   torch.empty(N, device=d.device, dtype=torch.float32),
+                   torch.empty(1, device=d.device, dtype=torch.float32),
+                   torch.empty(self.T, device=d.device, dtype=torch.float32))
+            self._keep += [d, X, alpha]
+            for lst, t in zip((self.Z, self.F, self.loss, self.dalpha), out):
+                lst.append(t)
+            self._arr[i] = Problem(d.handle.value, X.data_ptr(), N, float(lam), alpha.data_ptr(),
+                                   out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), out[3].data_ptr())
+        nbytes = ctypes.c_size_t()
+        check(lib().slista_batched_workspace_size(ctypes.cast(self._arr, ctypes.c_void_p), len(problems), self.T,
+                                                  self.prec, self.ckpt, ctypes.byref(nbytes)))
+        self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
+
+    def __call__(self, use_graph: bool = True) -> None:
+        check(lib().slista_batched_fwd_bwd(ctypes.cast(self._arr, ctypes.c_void_p), len(self._arr), self.T,
+                                           self.prec, self.ckpt, self.ws.data_ptr(), self.ws.numel(),
+                                           _stream(self.device), int(bool(use_graph))))
+
+
+def batched_release() -> None:
+    """Drop every plan slista_batched_fwd_bwd keeps (synchronises the device)."""
+    check(lib().slista_batched_release())
+
+
 KERNEL_FAMILIES = {"auto": 0, "layer": 1, "persistent": 2}
+
+
+def set_check_finite(on: bool) -> None:
+    """Count NaN / Inf in the inputs and outputs of the dictionary, forward
+    and backward calls (synchronising); raise SLISTA_ENONFINITE if any."""
+    check(lib().slista_set_option(3, int(bool(on))))
 
 
 def set_kernel_family(name: str) -> None:
