@@ -56,15 +56,3 @@ def round_to_bf16(a):
     r = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
     return r.view(np.float32).astype(np.float64)
 
-
-def gap_tolerance(prec: str, T: int, gap_orc: float, gap_rounded: float) -> float:
-    """Tolerance on the relative error of the mean gap.
-
-    The nominal figure (GAP_TOL) assumes the gap is resolvable in the working
-    precision. Near convergence it is not: rounding the oracle's exact z^T to
-    the precision of the device iterate (FP32) or of its contraction operand
-    (BF16) already moves the mean gap by rho = |gap(rounded) - gap| / gap, and
-    each of the T layers rounds once more, so the tolerance is
-    max(GAP_TOL, T * rho)."""
-    rho = abs(gap_rounded - gap_orc) / gap_orc
-    return max(GAP_TOL[prec], T * rho)

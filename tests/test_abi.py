@@ -139,3 +139,40 @@ def test_lista_entry_points_reject_bad_arguments(lib):
                                            vp(16), None, None, None, vp(16), vp(16), vp(256),
                                            ctypes.c_size_t(1 << 20), None)
     assert st == -1
+
+
+def test_check_and_batched_entry_points_reject_bad_arguments(lib):
+    """The device checks, lambda_max, the one-call batch and the options
+    validate on the host, before any launch."""
+    vp = ctypes.c_void_p
+    size = ctypes.c_size_t()
+    assert lib.slista_kkt(None, vp(16), 4, ctypes.c_float(0.1), vp(16), vp(16), None, None) == -1
+    assert lib.slista_lambda_max_workspace_size(None, 4, ctypes.byref(size)) == -1
+    assert lib.slista_lambda_max(None, vp(16), 4, vp(16), None, vp(256), ctypes.c_size_t(1 << 20), None) == -1
+    assert lib.slista_batched_workspace_size(None, 1, 5, 0, 1, ctypes.byref(size)) == -1
+    assert lib.slista_batched_fwd_bwd(None, 1, 5, 0, 1, vp(256), ctypes.c_size_t(1 << 20), None, 0) == -1
+    assert lib.slista_batched_release() == 0
+    assert lib.slista_set_option(3, 2) == -1
+    assert lib.slista_set_option(3, 0) == 0
+    assert lib.slista_status_string(-6) == b"non-finite values (NaN or Inf) found by the finite-value check"
+
+
+def test_precision_schedule_is_checked_on_the_host(lib):
+    """SLISTA_BF16_FP32_TAIL(k) = 1 | k << 8: the tail must not exceed T, needs
+    BF16 layers before it, and with checkpoints its first layer must be a
+    checkpoint. A batch of problems takes the same encoding."""
+    import re
+    text = open(HEADER).read()
+    assert re.search(r"#define SLISTA_BF16_FP32_TAIL\(tail\) \(SLISTA_BF16 \| \(\(tail\) << 8\)\)", text)
+
+    class P(ctypes.Structure):
+        _fields_ = [("dict", ctypes.c_void_p), ("X", ctypes.c_void_p), ("N", ctypes.c_int),
+                    ("lam", ctypes.c_float), ("alpha", ctypes.c_void_p), ("Z", ctypes.c_void_p),
+                    ("F", ctypes.c_void_p), ("loss", ctypes.c_void_p), ("dalpha", ctypes.c_void_p)]
+    arr = (P * 1)()
+    out = ctypes.c_void_p()
+    for prec, T, k, frag in [((1 | (6 << 8)), 5, 1, b"longer than T"), ((0 | (2 << 8)), 5, 1, b"needs SLISTA_BF16"),
+                             ((1 | (3 << 8)), 10, 2, b"checkpoint"), (7, 5, 1, b"unknown precision")]:
+        # the schedule is parsed before the problems are looked at
+        assert lib.slista_batch_create(ctypes.cast(arr, ctypes.c_void_p), 1, T, prec, k, ctypes.byref(out)) == -1
+        assert frag in lib.slista_last_error(), (prec, lib.slista_last_error())

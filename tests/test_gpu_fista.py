@@ -1,8 +1,7 @@
 """FISTA (slista_fista, per-layer kernels) against the FP64 oracle's FISTA.
 The momentum makes the iteration non-contractive, so the codes are compared
-through the objective: the relative error of the mean gap (with the
-rounding-floor reading of tests.gpu_common.gap_tolerance) and per-sample
-objective values."""
+through the objective: the relative error of the mean gap (1e-5 FP32, 2e-2
+BF16) and per-sample objective values."""
 import sys
 
 import numpy as np
@@ -10,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_common import gap_tolerance, round_to_bf16
+from tests.gpu_common import GAP_TOL
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -49,10 +48,8 @@ def test_fista_vs_oracle(sl, prec, shape):
     Fs = oracle.objective(pb.D, pb.X, zs, pb.lam)
     g_gpu = float(np.mean(oracle.objective(pb.D, pb.X, Zg, pb.lam) - Fs))
     g_orc = float(np.mean(Fo[-1] - Fs))
-    rnd = (lambda z: z.astype(np.float32).astype(np.float64)) if prec == "fp32" else round_to_bf16
-    g_rnd = float(np.mean(oracle.objective(pb.D, pb.X, rnd(Zo), pb.lam) - Fs))
     rel = abs(g_gpu - g_orc) / g_orc
-    tol = gap_tolerance(prec, T, g_orc, g_rnd)
+    tol = GAP_TOL[prec]
     _say(f"[{prec}] {shape}: FISTA mean-gap rel err {rel:.2e} (tolerance {tol:.2e}), gap/F* {g_orc / np.mean(Fs):.2e}")
     assert rel <= tol
     np.testing.assert_allclose(F.cpu().numpy(), Fo[-1], rtol=1e-4 if prec == "fp32" else 2e-2)

@@ -18,11 +18,18 @@ DEV = "cuda:0"
 # FP32: every layer rounds z, the residual and W^T r once (unit roundoff
 # 6e-8); over 40 layers and through the adjoint's sums the relative error
 # measured on MI355X stays at or below 7e-7, so the FP32 bar of 1e-5 holds
-# for the iterates and the gradients as for the objective. BF16: the loss is
-# held to the BF16 objective bar; gradients to direction (cosine >= 0.99).
+# for the iterates and the gradients as for the objective. BF16: the loss,
+# z^T and the step gradients d alpha, d beta are held to the BF16 bar of 2e-2
+# (relative to their largest entry; measured <= 4.2e-3). dW is held to its
+# direction (cosine >= 0.995, measured >= 0.9989): an entry of dW sums
+# R_i v_j over the samples whose support holds atom j, and BF16 operands move
+# those supports, so single entries differ by up to 0.14 of the largest one
+# while the matrix keeps its direction and scale.
 Z_TOL_FP32 = 1e-5
 GRAD_TOL_FP32 = 1e-5
 LOSS_TOL = {"fp32": 1e-5, "bf16": 2e-2}
+BF16_TOL = 2e-2
+DW_COS_BF16 = 0.995
 
 
 def _say(*a):
@@ -108,11 +115,9 @@ def test_lista_forward_backward_vs_oracle(sl, name, prec):
         for k, v in errs.items():
             assert v <= GRAD_TOL_FP32, k
     else:
-        # BF16 operands move the iterates (and with them the active sets); the
-        # gradients keep their direction and scale
-        assert zerr <= 0.1
-        for k, v in coss.items():
-            assert v >= 0.99, k
+        assert zerr <= BF16_TOL
+        assert errs["dalpha"] <= BF16_TOL and errs["dbeta"] <= BF16_TOL
+        assert coss["dW"] >= DW_COS_BF16
     d.close()
 
 
@@ -247,9 +252,9 @@ def test_lista_wide_dictionaries(sl, shape, prec):
         for k, v in errs.items():
             assert v <= GRAD_TOL_FP32, k
     else:
-        assert errs["Z"] <= 0.1
-        for k, v in coss.items():
-            assert v >= 0.99, k
+        assert errs["Z"] <= BF16_TOL
+        assert errs["dalpha"] <= BF16_TOL and errs["dbeta"] <= BF16_TOL
+        assert coss["dW"] >= DW_COS_BF16
     d.close()
 
 
