@@ -30,17 +30,22 @@ PEAK = {"bf16_tflops": 2500.0, "fp32_tflops": 157.3, "hbm_gbs": 8000.0}
 def launch_work(kind: str, N: int, m: int, T: int):
     """Algorithmic flops and HBM bytes of one launch of a persistent kernel.
 
-    Units: one contraction of one sample costs 2 m^2 flops (P = Z G). One
-    forward layer of one sample moves 8 m bytes (read c, write the kept
-    iterate); one backward layer reads the kept iterate z^t once (4 m bytes).
+    Units: one contraction of one sample costs 2 m^2 flops (P = Z G). The
+    iterate and c = D^T x of a tile stay on chip across the layers, so a
+    sample's algorithmic HBM traffic is c read once (4 m bytes) plus what the
+    launch must store or read: each kept iterate of the tape is 4 m bytes.
       forward launch (all T layers + the final contraction for F and the
         seed): T contractions (layer 0 has none since z^0 = 0, the final one
-        is G z^T); bytes 4 m N (2T + 3): T reads of c and T iterate writes,
-        plus the final c read, the copy of z^T and the seed v^{T-1}.
+        is G z^T); bytes 4 m N (T + 3): c once, T kept iterates, the copy of
+        z^T and the seed v^{T-1}.
       backward launch (all T layers): T - 1 contractions; bytes 4 m N (T + 1):
-        the seed, z^T, and z^t for 1 <= t < T."""
+        the seed, z^T, and z^t for 1 <= t < T.
+    Both are m / 2 flop per byte: above the BF16 ridge (2.5 PFLOP/s over
+    8 TB/s = 312) for m = 1024, so their roofline is the MFMA peak. Bytes
+    the kernels move beyond these (the forward re-reads its rows of c every
+    layer) are excess, visible in the measured traffic."""
     if kind == "forward_layer":
-        return 2.0 * N * m * m * T, 4.0 * m * N * (2 * T + 3)
+        return 2.0 * N * m * m * T, 4.0 * m * N * (T + 3)
     if kind == "backward_layer":
         return 2.0 * N * m * m * (T - 1), 4.0 * m * N * (T + 1)
     raise ValueError(kind)
@@ -51,14 +56,14 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "59d03b0176f71ec9ab964964fd1c0da5a58ec42b0220f5768edafb259088ea32",
+    "sources_sha256": "74b583d40542c14e3782c7d7c46d8bcc5f16288fc97785552527be41e429587f",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {
-        ("bf16", "forward_layer"): (8398386 * 2 + 13650688) * 1024,
-        ("bf16", "backward_layer"): (7841569 * 2 + 10088) * 1024,
-        ("fp32", "forward_layer"): (14609746 * 2 + 13634196) * 1024,
-        ("fp32", "backward_layer"): (13592609 * 2 + 3251) * 1024,
+        ("bf16", "forward_layer"): (8333298.6875 * 2 + 13650688) * 1024,
+        ("bf16", "backward_layer"): (7728264.9375 * 2 + 10060.59375) * 1024,
+        ("fp32", "forward_layer"): (14679313.1875 * 2 + 13634496.9375) * 1024,
+        ("fp32", "backward_layer"): (13997890.0 * 2 + 3248.46875) * 1024,
     },
 }
 
@@ -94,6 +99,7 @@ def roofline(kind: str, avg_ms: float, N: int, m: int, T: int, prec: str, traffi
            "mfma_frac": round(tflops / peak_f, 4), "hbm_frac": round(gbs / PEAK["hbm_gbs"], 4), "traffic": traffic}
     if traffic is not None:
         out["traffic_gbs"] = round(traffic / sec / 1e9, 1)
+        out["traffic_over_algorithmic"] = round(traffic / bytes_, 3)
     if flops / bytes_ < ridge:
         out.update({"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
                     "frac": round(gbs / PEAK["hbm_gbs"], 4)})
@@ -185,14 +191,21 @@ def uneven_inputs(sl, torch, T: int):
     return specs, inputs
 
 
+UNEVEN_TAIL = 40  # FP32 layers at the end of the BF16 schedule of the uneven batch
+
+
 def uneven_report(sl, torch, specs, inputs, prec: str, T: int, ckpt: int, reps: int) -> dict:
     """Uneven multi-problem batch: 64 independent Lasso problems (n in [32, 512],
     m = 4n, N in [128, 8192]), forward + backward with checkpoints every `ckpt`
     layers, tiles autotuned per column-pass bucket, timed as replays of one
-    captured HIP graph."""
+    captured HIP graph. prec: "fp32", "bf16", or "bf16+tail" (BF16 layers and
+    FP32 contractions in the last UNEVEN_TAIL layers: the schedule that meets
+    the 2e-2 objective-gap bar on these converged problems, where BF16 in every
+    layer misses it; tests/test_gpu_uneven_full.py holds both to the oracle)."""
     import numpy as np
     dev = torch.device("cuda:0")
-    b = sl.Batch(inputs, prec=prec, ckpt_every=ckpt)
+    lib_prec = sl.bf16_fp32_tail(UNEVEN_TAIL) if prec == "bf16+tail" else prec
+    b = sl.Batch(inputs, prec=lib_prec, ckpt_every=ckpt)
     b.run()
     torch.cuda.synchronize()
     tuned = b.autotune()
@@ -211,12 +224,29 @@ def uneven_report(sl, torch, specs, inputs, prec: str, T: int, ckpt: int, reps: 
     ms_ = np.array([sp["m"] for sp in specs], np.float64)
     # useful contractions per sample: T forward (T-1 layers + the final G z^T) and T-1 backward
     flops = float(np.sum(2.0 * Ns * ms_ ** 2) * (2 * T - 1))
-    peak = 2.5e15 if prec == "bf16" else 157.3e12
+    # executed: the backward recomputes the interior of every segment but the last
+    nseg = -(-T // ckpt)
+    recomputed = (nseg - 1) * (ckpt - 1) if ckpt > 1 else 0
+    executed = float(np.sum(2.0 * Ns * ms_ ** 2) * (2 * T - 1 + recomputed))
+    if prec == "bf16+tail":
+        # useful time at the peaks of the two precisions, by layer share
+        f_tail = UNEVEN_TAIL / T
+        peak = 1.0 / ((1 - f_tail) / 2.5e15 + f_tail / 157.3e12)
+    else:
+        peak = 2.5e15 if prec == "bf16" else 157.3e12
     out = {"workload": "uneven_64", "problems": len(specs), "T": T, "ckpt_every": ckpt, "prec": prec,
            "total_samples": int(Ns.sum()), "ms_per_step": round(ms, 3),
            "value": round(float(Ns.sum()) * T / (ms * 1e-3), 1), "unit": "sample-layers/s",
            "mfma_tflops": round(flops / (ms * 1e-3) / 1e12, 2), "mfma_frac": round(flops / (ms * 1e-3) / peak, 4),
+           "executed_tflops": round(executed / (ms * 1e-3) / 1e12, 2),
+           "executed_over_useful": round(executed / flops, 3),
            "tuned_variant_by_column_passes": tuned, "timing": "HIP graph replay"}
+    if prec == "bf16+tail":
+        out["schedule"] = f"BF16 layers 0..{T - UNEVEN_TAIL - 1}, FP32 layers {T - UNEVEN_TAIL}..{T - 1}"
+        out["peak_note"] = "mfma_frac against the layer-share-weighted peak of BF16 and FP32"
+    if prec == "bf16":
+        out["objective_gap_note"] = ("misses the 2e-2 objective-gap bar on these converged problems (an expected "
+                                     "failure in tests/test_gpu_uneven_full.py); not an equal-accuracy figure")
     b.close()
     return out
 
@@ -289,6 +319,69 @@ def baselines_report(sl, torch, reps: int) -> dict:
     return out
 
 
+def configs_report(sl, torch, reps: int) -> dict:
+    """The two 64 x 256 Gaussian workloads beside the headline one:
+      fwd_64x256  batched ISTA forward, N = 10 000, T = 40, alpha = 1/L, no tape;
+      grad_64x256 forward + backward, N = 4096, T = 20, alpha = 1/L, every
+                  iterate kept (the learned-step workload).
+    Each in FP32 (the workload's precision) and BF16, with the tile variant
+    picked by slista_autotune for that workload (smaller tiles spread these
+    few samples over more CUs), timed with HIP events over `reps` calls after
+    a warm-up, with the library's per-kernel times from one more call. Useful flops: 2 m^2 per sample and contraction
+    (forward T - 1 layers, plus the final G z^T where the objective or the
+    seed is formed; backward T - 1 layers). At these sizes a call is tens to
+    hundreds of microseconds: launch latency and the last wave of tiles
+    (N / 64 tiles on 256 CUs) bound them, not the MFMA or HBM peaks, so the
+    fractions below are low by construction."""
+    import numpy as np
+    import synth
+    out = {}
+    dev = torch.device("cuda:0")
+    for wl, fb in (("fwd_64x256", False), ("grad_64x256", True)):
+        c = synth.CONFIGS[wl]
+        pb = synth.make_problem(c["n"], c["m"], c["N"], c["p"], c["sigma"], c["lam_frac"], c["seed"])
+        d = sl.Dictionary(torch.tensor(pb.D32(), device=dev))
+        X = torch.tensor(pb.X32(), device=dev)
+        L, _ = d.lipschitz(max_iter=100_000, rtol=1e-12)
+        N, T, m = pb.N, c["T"], pb.m
+        alpha = torch.full((T,), float(np.float32(1.0 / L)), device=dev, dtype=torch.float32)
+        ent = {"workload": wl, "n": pb.n, "m": m, "N": N, "T": T,
+               "pass": "forward+backward" if fb else "forward", "alpha": "1/L"}
+        flops = 2.0 * N * m * m * ((T - 1) + (T if fb else 0))
+        for p in ("fp32", "bf16"):
+            best, tune_ms = sl.autotune(d, X, pb.lam, alpha, prec=p, ckpt_every=1)
+            ws = d.workspace(N, T, p, 1 if fb else 0)
+            if fb:
+                call = lambda: sl.forward_backward(d, X, pb.lam, alpha, prec=p, ckpt_every=1, ws=ws)  # noqa: E731
+            else:
+                call = lambda: sl.forward(d, X, pb.lam, alpha, prec=p, want_f=False, want_loss=False,  # noqa: E731
+                                          ckpt_every=0, ws=ws)
+            for _ in range(3):
+                call()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                call()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            sl.profile_begin()
+            call()
+            torch.cuda.synchronize()
+            prof = sl.profile_end()
+            peak = PEAK["bf16_tflops"] if p == "bf16" else PEAK["fp32_tflops"]
+            tf = flops / (ms * 1e-3) / 1e12
+            ent[p] = {"ms_per_call": round(ms, 4), "value": round(N * T / (ms * 1e-3), 1),
+                      "unit": "sample-layers/s", "useful_tflops": round(tf, 2), "mfma_frac": round(tf / peak, 4),
+                      "bound": "launch latency and tail (see docstring)", "tile_variant": int(best),
+                      "kernels_ms": {k: [v[0], round(v[1], 4)] for k, v in prof.items() if k != "dropped" and v[0] > 0}}
+            del ws
+        out[wl] = ent
+        d.close()
+    return out
+
+
 def lista_report(sl, torch, reps: int, precs) -> dict:
     """Coupled LISTA forward+backward (all parameter gradients, dW included) on
     the 64 x 256 Gaussian workload, N = 10000, T = 40: sample-layers/s and the
@@ -353,8 +446,9 @@ def main() -> int:
     ap.add_argument("--train-iters", type=int, default=30)
     ap.add_argument("--no-lista", action="store_true", help="skip the coupled LISTA report")
     ap.add_argument("--no-baselines", action="store_true", help="skip the FISTA / Oracle-ISTA report")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 64x256 forward and learned-step lines")
     ap.add_argument("--lista-reps", type=int, default=10)
-    ap.add_argument("--uneven-precs", default="bf16,fp32")
+    ap.add_argument("--uneven-precs", default="bf16+tail,bf16,fp32")
     ap.add_argument("--uneven-reps", type=int, default=3)
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -441,6 +535,11 @@ def main() -> int:
         lista = lista_report(sl, torch, args.lista_reps, ("fp32", "bf16"))
         print(f"[bench] lista {lista}", file=sys.stderr, flush=True)
 
+    configs = None
+    if not args.no_configs:
+        configs = configs_report(sl, torch, 20)
+        print(f"[bench] 64x256 workloads {configs}", file=sys.stderr, flush=True)
+
     baselines = None
     if not args.no_baselines:
         baselines = baselines_report(sl, torch, 5)
@@ -477,6 +576,7 @@ def main() -> int:
                               "loss": r["loss"]}
                           for p, r in res.items()},
         "objective_gap": gap,
+        "workloads_64x256": configs,
         "uneven_batch": uneven,
         "training": train,
         "lista": lista,
