@@ -192,6 +192,30 @@ SLISTA_API int slista_forward_scratch(const slista_dict* dict, const float* X, i
                                       const float* alpha, int T, int prec, float* Z, float* F, int f_trace,
                                       float* loss, void* stream);
 
+/* FP64 forward of ISTA (Eq. (2), alpha_t = 1/L) or of Step-LISTA with given
+ * steps (Section 4, Eq. (14)): z^(0) = 0, z^(t+1) = ST(z^(t) - alpha_t D^T (D
+ * z^(t) - x), lambda alpha_t), every quantity in double precision and the
+ * gradient in the factored form of the layer, with the dictionary's FP32
+ * values of D widened exactly. For the small double-precision workloads
+ * (one wave per sample; no MFMA): a reference-grade device path, not the
+ * fast one.
+ *   X     device FP64 [N, n], row-major.
+ *   alpha device FP64 [T].
+ *   Z     device FP64 [N, m]: z^(T).
+ *   F     device FP64: with f_trace, [T + 1, N] (F[t][i] = F_{x_i}(z_i^(t)),
+ *         Eq. (1), from the residual x - D z); else [N] (F of z^(T)); or NULL.
+ *   loss  device FP64 scalar: the mean of F(z^(T)) over the samples
+ *         (Eq. (15) at the output), or NULL. Without F the loss needs a
+ *         workspace of slista_forward_f64_workspace_size bytes (256-byte
+ *         aligned); otherwise ws may be NULL.
+ * Errors: SLISTA_EINVAL for NULL or out-of-range arguments, SLISTA_ENOTSUP
+ * for n > 512 (the lanes hold at most eight residual entries each). Does not
+ * synchronise; does not use the tape record of the FP32/BF16 entry points. */
+SLISTA_API int slista_forward_f64_workspace_size(const slista_dict* dict, int N, size_t* bytes);
+SLISTA_API int slista_forward_f64(const slista_dict* dict, const double* X, int N, double lambda,
+                                  const double* alpha, int T, double* Z, double* F, int f_trace, double* loss,
+                                  void* ws, size_t ws_bytes, void* stream);
+
 /* Lasso cost of given codes, Eq. (1): F[i] = 1/2 ||x_i - D z_i||^2 + lambda ||z_i||_1
  * for Z (device FP32 [N, m]), written to F (device FP32 [N]). The residual is
  * formed in FP32 from the non-zero coordinates of z_i (one wave per sample,

@@ -73,6 +73,9 @@ SIGNATURES = {
     "slista_batch_replay": (_c_int, [_vp, _vp]),
     "slista_batch_destroy": (_c_int, [_vp]),
     "slista_kkt": (_c_int, [_vp, _vp, _c_int, _c_float, _vp, _vp, _vp, _vp]),
+    "slista_forward_f64_workspace_size": (_c_int, [_vp, _c_int, ctypes.POINTER(_size_t)]),
+    "slista_forward_f64": (_c_int, [_vp, _vp, _c_int, _c_double, _vp, _c_int, _vp, _vp, _c_int, _vp, _vp,
+                                    _size_t, _vp]),
     "slista_lambda_max_workspace_size": (_c_int, [_vp, _c_int, ctypes.POINTER(_size_t)]),
     "slista_lambda_max": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _size_t, _vp]),
     "slista_batched_workspace_size": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_size_t)]),

@@ -31,7 +31,8 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-fvisibility=hidden", "-Wall", "-Wno-un
           f"-I{os.path.join(ROOT, 'include')}"]
 
 SOURCES = ["kernels_persist_bf16.hip", "kernels_persist_f32.hip", "kernels_gemm.hip", "kernels_misc.hip",
-           "kernels_lista.hip", "kernels_lista_persist.hip", "kernels_persist.hip", "kernels_check.hip", "api.cpp"]
+           "kernels_lista.hip", "kernels_lista_persist.hip", "kernels_persist.hip", "kernels_check.hip",
+           "kernels_f64.hip", "api.cpp"]
 
 
 def _compile(src: str) -> str:

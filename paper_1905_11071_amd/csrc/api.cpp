@@ -1389,6 +1389,46 @@ int slista_objective(const slista_dict* dict, const float* X, int N, float lambd
   return SLISTA_OK;
 }
 
+int slista_forward_f64_workspace_size(const slista_dict* dict, int N, size_t* bytes) {
+  if (!dict || !bytes) return fail(SLISTA_EINVAL, "dict or bytes is NULL");
+  if (N < 0 || N > kMaxN) return fail(SLISTA_EINVAL, "N=%d outside [0, %d]", N, kMaxN);
+  *bytes = align256((size_t)N * sizeof(double));
+  return SLISTA_OK;
+}
+
+int slista_forward_f64(const slista_dict* dict, const double* X, int N, double lambda, const double* alpha, int T,
+                       double* Z, double* F, int f_trace, double* loss, void* ws, size_t ws_bytes, void* stream) {
+  if (!dict) return fail(SLISTA_EINVAL, "dict is NULL");
+  if (N < 0 || N > kMaxN) return fail(SLISTA_EINVAL, "N=%d outside [0, %d]", N, kMaxN);
+  if (T < 0 || T > kMaxT) return fail(SLISTA_EINVAL, "T=%d outside [0, %d]", T, kMaxT);
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(SLISTA_EINVAL, "lambda must be finite and > 0");
+  if (N > 0 && (!X || !Z)) return fail(SLISTA_EINVAL, "X or Z is NULL");
+  if (T > 0 && !alpha) return fail(SLISTA_EINVAL, "alpha is NULL");
+  if (f_trace && !F) return fail(SLISTA_EINVAL, "f_trace needs F");
+  const slista::Dict& d = dict->d;
+  if (d.n > slista::f64_max_n())
+    return fail(SLISTA_ENOTSUP, "the FP64 forward supports n <= %d (n=%d)", slista::f64_max_n(), d.n);
+  hipStream_t s = (hipStream_t)stream;
+  // the per-sample objectives the loss averages: F itself, the trace's last
+  // row, or the workspace
+  double* Fd = nullptr;
+  if (loss) {
+    if (F) {
+      Fd = f_trace ? F + (size_t)T * N : F;
+    } else if (N > 0) {
+      if (!ws || ((uintptr_t)ws & 255) || ws_bytes < (size_t)N * sizeof(double))
+        return fail(SLISTA_EINVAL, "the loss without F needs a 256-byte aligned workspace of %zu bytes",
+                    align256((size_t)N * sizeof(double)));
+      Fd = (double*)ws;
+    }
+  }
+  if (slista::ista_f64_lds(d.n, d.m_pad) > 160 * 1024)
+    return fail(SLISTA_ENOTSUP, "the FP64 forward's per-wave iterate does not fit in LDS (m_pad=%d)", d.m_pad);
+  LAUNCH(kKFwd, s, slista::launch_ista_f64(d.Dt, d.n, d.m, d.m_pad, X, N, lambda, alpha, T, Z, F, f_trace, Fd, s));
+  if (loss) LAUNCH(kKOther, s, slista::launch_mean_d(Fd, N, loss, s));
+  return SLISTA_OK;
+}
+
 int slista_backward(const slista_dict* dict, const float* X, int N, float lambda, const float* alpha, int T,
                     int prec, const float* dZ, const float* dF, float* dalpha, int ckpt_every, void* ws,
                     size_t ws_bytes, void* stream) {
@@ -2342,10 +2382,9 @@ void plan_release(Plan& pl) {
   pl.cap = nullptr;
 }
 
-std::vector<unsigned char> plan_key(const slista_problem* problems, int P, int T, int prec, int k, void* ws,
-                                    size_t ws_bytes) {
-  std::vector<unsigned char> key(sizeof(slista_problem) * (size_t)P + 3 * sizeof(int) + sizeof(void*) +
-                                 sizeof(size_t));
+void plan_key(std::vector<unsigned char>& key, const slista_problem* problems, int P, int T, int prec, int k,
+              void* ws, size_t ws_bytes) {
+  key.assign(sizeof(slista_problem) * (size_t)P + 3 * sizeof(int) + sizeof(void*) + sizeof(size_t), 0);
   unsigned char* q = key.data();
   std::memcpy(q, problems, sizeof(slista_problem) * (size_t)P);
   q += sizeof(slista_problem) * (size_t)P;
@@ -2355,7 +2394,6 @@ std::vector<unsigned char> plan_key(const slista_problem* problems, int P, int T
   std::memcpy(q, &ws, sizeof ws);
   q += sizeof ws;
   std::memcpy(q, &ws_bytes, sizeof ws_bytes);
-  return key;
 }
 }  // namespace
 
@@ -2375,7 +2413,8 @@ int slista_batched_fwd_bwd(const slista_problem* problems, int P, int T, int pre
   if (!problems || P < 1 || P > 1 << 20) return fail(SLISTA_EINVAL, "need 1 <= P problems");
   if (use_graph && g_prof.on) return fail(SLISTA_EINVAL, "kernel timing must be off with use_graph");
   hipStream_t s = (hipStream_t)stream;
-  std::vector<unsigned char> key = plan_key(problems, P, T, prec, ckpt_every, ws, ws_bytes);
+  std::vector<unsigned char> key;
+  plan_key(key, problems, P, T, prec, ckpt_every, ws, ws_bytes);
   std::lock_guard<std::mutex> lock(g_plan_mu);
   size_t idx = g_plans.size();
   for (size_t i = 0; i < g_plans.size(); ++i)

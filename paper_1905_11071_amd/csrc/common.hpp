@@ -172,6 +172,14 @@ struct BatchSmall {
 hipError_t launch_batch_prep(const BatchSmall* tab, int nprob, int max_N, size_t max_group_elems, hipStream_t s);
 hipError_t launch_batch_loss(const BatchSmall* tab, int nprob, hipStream_t s);
 hipError_t launch_batch_dalpha(const BatchSmall* tab, int nprob, int T, hipStream_t s);
+// FP64 forward (kernels_f64.hip): ISTA / Step-LISTA in double precision, one
+// wave per sample, factored gradient D^T (D z - x); n <= f64_max_n().
+// F: [T + 1][N] trace if f_trace, else F(z^T) [N] (either may be NULL);
+// Fd: F(z^T) [N] (may be NULL).
+int f64_max_n();
+size_t ista_f64_lds(int n, int m_pad);
+hipError_t launch_ista_f64(const float* Dt, int n, int m, int m_pad, const double* X, int N, double lam,
+                           const double* alpha, int T, double* Z, double* F, int f_trace, double* Fd, hipStream_t s);
 // Checks (kernels_check.hip).
 // Per sample, in FP64: the largest violation of the Lasso optimality
 // conditions (Lemma 2.1) by z_i, and F(z_i) (Eq. (1)); n <= kkt_max_n().

@@ -158,6 +158,27 @@ def objective(d: Dictionary, X: torch.Tensor, lam: float, Z: torch.Tensor) -> to
     return F
 
 
+def forward_f64(d: Dictionary, X: torch.Tensor, lam: float, alpha: torch.Tensor, f_trace: bool = False,
+                want_loss: bool = True):
+    """T layers in double precision (slista_forward_f64): X [N, n] and alpha
+    [T] float64 device tensors. Returns (Z [N, m], F ([T+1, N] with f_trace,
+    else [N]), loss (0-d tensor or None)), all float64."""
+    for t, name in ((X, "X"), (alpha, "alpha")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+            raise ValueError(f"{name} must be a float64 CUDA (HIP) tensor")
+    X, alpha = X.contiguous(), alpha.contiguous()
+    if X.dim() != 2 or X.shape[1] != d.n:
+        raise ValueError(f"X has shape {tuple(X.shape)}, expected (N, {d.n})")
+    N, T = int(X.shape[0]), int(alpha.numel())
+    Z = torch.empty(N, d.m, device=d.device, dtype=torch.float64)
+    F = torch.empty((T + 1, N) if f_trace else (N,), device=d.device, dtype=torch.float64)
+    loss = torch.empty((), device=d.device, dtype=torch.float64) if want_loss else None
+    check(lib().slista_forward_f64(d.handle, X.data_ptr(), N, float(lam), alpha.data_ptr(), T, Z.data_ptr(),
+                                   F.data_ptr(), int(f_trace), loss.data_ptr() if loss is not None else None,
+                                   None, 0, _stream(d.device)))
+    return Z, F, loss
+
+
 def kkt(d: Dictionary, X: torch.Tensor, lam: float, Z: torch.Tensor):
     """(kkt, F): per sample, in FP64 on the device, the largest violation of
     the Lasso optimality conditions (Lemma 2.1) by the codes Z, and F(z)."""

@@ -176,3 +176,11 @@ def test_precision_schedule_is_checked_on_the_host(lib):
         # the schedule is parsed before the problems are looked at
         assert lib.slista_batch_create(ctypes.cast(arr, ctypes.c_void_p), 1, T, prec, k, ctypes.byref(out)) == -1
         assert frag in lib.slista_last_error(), (prec, lib.slista_last_error())
+
+
+def test_f64_forward_rejects_bad_arguments(lib):
+    vp = ctypes.c_void_p
+    n = ctypes.c_size_t()
+    assert lib.slista_forward_f64_workspace_size(None, 4, ctypes.byref(n)) == -1
+    st = lib.slista_forward_f64(None, vp(256), 4, 0.1, vp(256), 3, vp(256), None, 0, None, None, 0, None)
+    assert st == -1 and b"dict" in lib.slista_last_error()
