@@ -319,6 +319,43 @@ def baselines_report(sl, torch, reps: int) -> dict:
     return out
 
 
+def ista_f64_report(sl, torch, reps: int) -> dict:
+    """The double-precision ISTA workload ista_10x20 (n = 10, m = 20,
+    N = 1000, T = 100, alpha = 1/L, the objective at every layer):
+    slista_forward_f64, FP64 throughout, timed with HIP events over `reps`
+    calls after a warm-up. Work per sample-layer in the factored form the
+    FP64 path uses: 4 n m flops (D z, then D^T r; zero coordinates of z are
+    skipped, so fewer are executed). A call is one wave per sample through
+    100 dependent layers: latency bounds it, not a peak."""
+    import synth
+    c = synth.CONFIGS["ista_10x20"]
+    pb = synth.make_problem(c["n"], c["m"], c["N"], c["p"], c["sigma"], c["lam_frac"], c["seed"])
+    dev = torch.device("cuda:0")
+    d = sl.Dictionary(torch.tensor(pb.D32(), device=dev))
+    L, _ = d.lipschitz(max_iter=100_000, rtol=1e-12)
+    N, T = pb.N, c["T"]
+    X = torch.tensor(pb.X, device=dev, dtype=torch.float64)
+    alpha = torch.full((T,), 1.0 / L, device=dev, dtype=torch.float64)
+    call = lambda: sl.forward_f64(d, X, pb.lam, alpha, f_trace=True)  # noqa: E731
+    for _ in range(3):
+        call()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        out = call()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = 4.0 * pb.n * pb.m * N * T
+    res = {"workload": "ista_10x20", "n": pb.n, "m": pb.m, "N": N, "T": T, "pass": "forward, F at every layer",
+           "alpha": "1/L", "dtype": "f64", "ms_per_call": round(ms, 4), "value": round(N * T / (ms * 1e-3), 1),
+           "unit": "sample-layers/s", "useful_gflops": round(flops / (ms * 1e-3) / 1e9, 2),
+           "bound": "latency (one wave per sample, 100 dependent layers)", "loss": float(out[2].item())}
+    d.close()
+    return res
+
+
 def configs_report(sl, torch, reps: int) -> dict:
     """The two 64 x 256 Gaussian workloads beside the headline one:
       fwd_64x256  batched ISTA forward, N = 10 000, T = 40, alpha = 1/L, no tape;
@@ -446,7 +483,8 @@ def main() -> int:
     ap.add_argument("--train-iters", type=int, default=30)
     ap.add_argument("--no-lista", action="store_true", help="skip the coupled LISTA report")
     ap.add_argument("--no-baselines", action="store_true", help="skip the FISTA / Oracle-ISTA report")
-    ap.add_argument("--no-configs", action="store_true", help="skip the 64x256 forward and learned-step lines")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 64x256 forward and learned-step lines and the FP64 10x20 ISTA line")
     ap.add_argument("--lista-reps", type=int, default=10)
     ap.add_argument("--uneven-precs", default="bf16+tail,bf16,fp32")
     ap.add_argument("--uneven-reps", type=int, default=3)
@@ -535,10 +573,12 @@ def main() -> int:
         lista = lista_report(sl, torch, args.lista_reps, ("fp32", "bf16"))
         print(f"[bench] lista {lista}", file=sys.stderr, flush=True)
 
-    configs = None
+    configs = ista64 = None
     if not args.no_configs:
         configs = configs_report(sl, torch, 20)
         print(f"[bench] 64x256 workloads {configs}", file=sys.stderr, flush=True)
+        ista64 = ista_f64_report(sl, torch, 20)
+        print(f"[bench] ista_10x20 fp64 {ista64}", file=sys.stderr, flush=True)
 
     baselines = None
     if not args.no_baselines:
@@ -577,6 +617,7 @@ def main() -> int:
                           for p, r in res.items()},
         "objective_gap": gap,
         "workloads_64x256": configs,
+        "workload_ista_10x20": ista64,
         "uneven_batch": uneven,
         "training": train,
         "lista": lista,
