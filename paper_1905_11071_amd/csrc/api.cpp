@@ -1615,6 +1615,8 @@ int slista_oista(const slista_dict* dict, const float* X, int N, float lambda, d
   if (max_power_iter < 1 || max_power_iter > 1000000) return fail(SLISTA_EINVAL, "max_power_iter outside [1, 1e6]");
   if (!(power_rtol >= 0.0) || !std::isfinite(power_rtol)) return fail(SLISTA_EINVAL, "power_rtol must be >= 0");
   if (dict->d.m_pad > 2048) return fail(SLISTA_ENOTSUP, "Oracle-ISTA supports m <= 2048 (m_pad=%d)", dict->d.m_pad);
+  if (slista::support_lipschitz_lds(dict->d.m_pad, dict->d.n) > 160 * 1024)
+    return fail(SLISTA_ENOTSUP, "Oracle-ISTA's per-sample Lanczos does not fit in LDS (n=%d)", dict->d.n);
   if (T < 0 || T > kMaxT) return fail(SLISTA_EINVAL, "T=%d outside [0, %d]", T, kMaxT);
   size_t need_fwd = 0;  // checks N, lambda, prec, X and the workspace alignment (no step sizes here)
   int st = check_common(dict, X, N, lambda, nullptr, 0, prec, 0, ws, ws_bytes, &need_fwd);
@@ -1641,8 +1643,8 @@ int slista_oista(const slista_dict* dict, const float* X, int N, float lambda, d
   LAUNCH(kKOther, s, slista::launch_fill(r.slot(0), (size_t)N * mp, 0.f, s));
   for (int t = 0; t < T; ++t) {
     const float* zt = r.slot(t);
-    LAUNCH(kKOther, s, slista::launch_support_lipschitz(dict->d.G32, dict->d.m, mp, zt, V, L, max_power_iter,
-                                                        power_rtol, N, step, s));
+    LAUNCH(kKOther, s, slista::launch_support_lipschitz(dict->d.G32, dict->d.Dt, dict->d.n, dict->d.m, mp, zt, V, L,
+                                                        max_power_iter, power_rtol, N, step, s));
     slista::GemmArgs g = base_args(r, nullptr, lambda);
     g.A = zt;
     g.Bt = gram_for(*r.d, prec);

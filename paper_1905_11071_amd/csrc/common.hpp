@@ -108,12 +108,14 @@ hipError_t launch_mean_d(const double* Fd, int N, double* out, hipStream_t s);
 hipError_t launch_alpha_step(const float* alpha, const float* g, double eta, int T, float* cand, hipStream_t s);
 // FISTA momentum weights beta[0..T) (FP64 recurrence, one thread).
 hipError_t launch_fista_beta(int T, float* beta, hipStream_t s);
-// Oracle-ISTA: per sample, L_S of the support of z (FP64 power iteration on
-// G restricted to S, warm-started from V) -> step[i] = 1/L_S (1/L if S is
-// empty); then z' = ST(z - a_i R, lam a_i) with a_i = step[i], or 1/L where
-// the row's violation count (sum over col tiles of flags) is nonzero.
-hipError_t launch_support_lipschitz(const float* G32, int m, int mp, const float* Z, float* V, double L,
-                                    int max_iter, double tol, int N, float* step, hipStream_t s);
+// Oracle-ISTA: per sample, L_S of the support of z (FP64 Lanczos on G_SS,
+// or on D_S^T D_S in factored form for large supports; kept while the support
+// is the one recorded in row i of V) -> step[i] = 1/L_S (1/L if S is empty);
+// then z' = ST(z - a_i R, lam a_i) with a_i = step[i], or 1/L where the row's
+// violation count (sum over col tiles of flags) is nonzero.
+size_t support_lipschitz_lds(int m_pad, int n);
+hipError_t launch_support_lipschitz(const float* G32, const float* Dt, int n, int m, int mp, const float* Z, float* V,
+                                    double L, int max_iter, double tol, int N, float* step, hipStream_t s);
 hipError_t launch_oista_update(const float* Z, const float* R, const double* flags, int col_tiles, const float* step,
                                double L, float lam, int N, int mp, float* Zout, float* steps_used, hipStream_t s);
 // Coupled LISTA helpers (kernels_lista.hip).

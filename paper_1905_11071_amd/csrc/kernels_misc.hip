@@ -277,18 +277,22 @@ __global__ void k_fista_beta(int T, float* __restrict__ beta) {
 // S of row i of Z is compacted in index order (a ballot per 64 columns); then
 // Lanczos (three-term recurrence in FP64, no stored basis) from a fixed start
 // vector, a hash of the atom indices, with lanes owning coordinates
-// lane + 64 c. The largest eigenvalue of the Lanczos tridiagonal matrix rises
-// to L_S; it is evaluated every 8 steps (65-point multisection with Sturm
-// counts) and the recurrence stops when two evaluations agree to tol, after
-// min(|S|, max_iter, kLsMaxSteps) steps, or when the Krylov space is
-// exhausted. Supports of at most kLsCache atoms read G_SS from LDS (gathered
-// once), larger ones read G from L2. step[i] = 1/L_S, 1/L for an empty
-// support. One 64-lane workgroup per sample: reductions are fixed-order
-// shuffles and the barriers cost one wave. L_S depends on the support alone
-// (and the run is deterministic), so a sample whose support has not changed
-// since the last call keeps step[i]: row i of V holds that support as a
-// bitmask (one 64-bit word per 64 columns) and, in its last word, a flag
-// that step[i] is valid (V zero-filled before the first layer).
+// lane + 64 c. Supports of at most kLsCache atoms apply G_SS, gathered once
+// into LDS from the FP32 Gram matrix; larger ones apply D_S^T D_S in
+// factored form, r = D_S q (lanes owning rows of D, one coalesced row of D^T
+// per atom), then D_S^T r (lanes owning atoms), in FP64 from D's FP32 values:
+// 2 n |S| per step and no gather of |S|^2 scattered Gram entries. The largest
+// eigenvalue of the Lanczos tridiagonal matrix rises to L_S; it is evaluated
+// every 4 steps (65-point multisection with Sturm counts) and
+// the recurrence stops when two evaluations agree to tol, after min(|S|,
+// max_iter, kLsMaxSteps) steps, or when the Krylov space is exhausted.
+// step[i] = 1/L_S, 1/L for an empty support. One 64-lane workgroup per
+// sample: reductions are fixed-order shuffles and the barriers cost one wave.
+// L_S depends on the support alone (and the run is deterministic), so a
+// sample whose support has not changed since the last call keeps step[i]:
+// row i of V holds that support as a bitmask (one 64-bit word per 64
+// columns) and, in its last word, a flag that step[i] is valid (V
+// zero-filled before the first layer).
 constexpr int kLsLanes = 64;
 constexpr int kLsCache = 64;
 constexpr int kLsMaxSteps = 128;  // Krylov dimension cap
@@ -300,13 +304,14 @@ __device__ __forceinline__ double wave_sum(double x) {
 }
 
 // LDS: q, q_prev, w [mp] doubles each, the tridiagonal (2 kLsMaxSteps
-// doubles), G_SS [kLsCache][kLsCache + 1] floats, support indices [mp] ints.
-__host__ __device__ size_t support_vec_bytes(int mp) {
-  return ((size_t)3 * mp + 2 * kLsMaxSteps) * sizeof(double);
+// doubles), r = D_S q [n_pad] doubles, G_SS [kLsCache][kLsCache + 1] floats,
+// support indices [mp] ints.
+__host__ __device__ size_t support_vec_bytes(int mp, int n) {
+  return ((size_t)3 * mp + 2 * kLsMaxSteps + (size_t)(n + 63) / 64 * 64) * sizeof(double);
 }
 
-size_t support_lipschitz_lds(int mp) {
-  return support_vec_bytes(mp) + (size_t)kLsCache * (kLsCache + 1) * sizeof(float) + (size_t)mp * sizeof(int);
+size_t ls_lds_bytes(int mp, int n) {
+  return support_vec_bytes(mp, n) + (size_t)kLsCache * (kLsCache + 1) * sizeof(float) + (size_t)mp * sizeof(int);
 }
 
 // Number of eigenvalues below x of the symmetric tridiagonal matrix with
@@ -348,18 +353,20 @@ __device__ double tridiag_top(const double* a, const double* b, int k, int lane)
   return hi;
 }
 
-__global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __restrict__ G, int m, int mp,
+__global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __restrict__ G,
+                                                               const float* __restrict__ Dt, int n, int m, int mp,
                                                                const float* __restrict__ Z, float* __restrict__ V,
                                                                double L, int max_iter, double tol,
                                                                float* __restrict__ step) {
   extern __shared__ __attribute__((aligned(16))) char sm[];
   double* q = (double*)sm;                  // [mp] q_j
   double* qp = q + mp;                      // [mp] q_{j-1}
-  double* wv = qp + mp;                     // [mp] G_SS q_j, then the next residual
+  double* wv = qp + mp;                     // [mp] D_S^T D_S q_j, then the next residual
   double* la = wv + mp;                     // [kLsMaxSteps] tridiagonal: diagonal
   double* lb = la + kLsMaxSteps;            // [kLsMaxSteps] off-diagonal (lb[j] couples j-1, j)
-  float* gs = (float*)(sm + support_vec_bytes(mp));  // [kLsCache][kLsCache + 1]
-  int* idx = (int*)(gs + kLsCache * (kLsCache + 1)); // [mp]
+  double* rv = lb + kLsMaxSteps;            // [n_pad] D_S q_j (supports above kLsCache)
+  float* gs = (float*)(sm + support_vec_bytes(mp, n));  // [kLsCache][kLsCache + 1]
+  int* idx = (int*)(gs + kLsCache * (kLsCache + 1));    // [mp]
   const int i = blockIdx.x, lane = threadIdx.x;
   const float* z = Z + (size_t)i * mp;
   unsigned long long* memo = (unsigned long long*)(V + (size_t)i * mp);  // [mp / 2] words
@@ -409,6 +416,18 @@ __global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __r
   if (kmax > kLsMaxSteps) kmax = kLsMaxSteps;
   double beta = 0.0, top = 0.0, prev = -1.0;
   for (int j = 0; j < kmax; ++j) {
+    if (!cached) {
+      // r = D_S q: lane i owns rows i, i + 64, ... of D; row idx[l] of D^T
+      // is contiguous in i, so each step of the loop reads one coalesced row
+      for (int i0 = 0; i0 < n; i0 += kLsLanes) {
+        const int i = i0 + lane;
+        double racc = 0.0;
+        if (i < n)
+          for (int l = 0; l < ns; ++l) racc += (double)Dt[(size_t)idx[l] * n + i] * q[l];
+        rv[i] = racc;  // rv holds n_pad entries, so i < n_pad here
+      }
+      __syncthreads();  // r visible to every lane
+    }
     double pa = 0.0;
     for (int c = lane; c < ns; c += kLsLanes) {
       double sacc = 0.0;
@@ -416,8 +435,9 @@ __global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __r
         const float* grow = gs + c * (kLsCache + 1);
         for (int l = 0; l < ns; ++l) sacc += (double)grow[l] * q[l];
       } else {
-        const float* grow = G + (size_t)idx[c] * mp;
-        for (int l = 0; l < ns; ++l) sacc += (double)grow[idx[l]] * q[l];
+        // (D_S^T r)_c from row idx[c] of D^T
+        const float* drow = Dt + (size_t)idx[c] * n;
+        for (int i = 0; i < n; ++i) sacc += (double)drow[i] * rv[i];
       }
       wv[c] = sacc;
       pa += q[c] * sacc;
@@ -434,7 +454,7 @@ __global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __r
     const int k = j + 1;
     __syncthreads();  // la[j] visible
     const bool last = k == kmax || !(b > 1e-13 * (fabs(alpha) + beta));
-    if (last || (k % 8) == 0) {
+    if (last || (k % 4) == 0) {
       top = tridiag_top(la, lb, k, lane);
       if (last || fabs(top - prev) <= tol * fabs(top)) break;
       prev = top;
@@ -645,15 +665,17 @@ hipError_t launch_alpha_step(const float* alpha, const float* g, double eta, int
   return hipGetLastError();
 }
 
-hipError_t launch_support_lipschitz(const float* G32, int m, int mp, const float* Z, float* V, double L,
-                                    int max_iter, double tol, int N, float* step, hipStream_t s) {
+size_t support_lipschitz_lds(int m_pad, int n) { return ls_lds_bytes(m_pad, n); }
+
+hipError_t launch_support_lipschitz(const float* G32, const float* Dt, int n, int m, int mp, const float* Z, float* V,
+                                    double L, int max_iter, double tol, int N, float* step, hipStream_t s) {
   if (N == 0) return hipSuccess;
-  const size_t lds = support_lipschitz_lds(mp);
+  const size_t lds = ls_lds_bytes(mp, n);
   hipError_t e = hipFuncSetAttribute((const void*)k_support_lipschitz, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_support_lipschitz, dim3(N), dim3(kLsLanes), lds, s, G32, m, mp, Z, V, L, max_iter, tol,
-                     step);
+  hipLaunchKernelGGL(k_support_lipschitz, dim3(N), dim3(kLsLanes), lds, s, G32, Dt, n, m, mp, Z, V, L, max_iter,
+                     tol, step);
   return hipGetLastError();
 }
 

@@ -384,6 +384,31 @@ def test_kernel_families_agree(sl, prec, shape):
     d.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_wide_dictionary_on_the_per_layer_kernels(sl, prec):
+    """m_pad > 2048 (n = 40, m = 2600): past the persistent kernels' column
+    passes the layers run on the per-layer kernels. Codes (FP32: within the
+    forward-error bound), the mean gap and d alpha against the oracle."""
+    pb = synth.make_problem(40, 2600, 150, 0.02, 0.01, 0.1, seed=2600)
+    alpha = synth.perturbed_steps(oracle.lipschitz(pb.D), 5, seed=2601)
+    d = sl.Dictionary(_gpu(pb.D))
+    Z, F, loss, da, _ = sl.forward_backward(d, _gpu(pb.X), pb.lam, _gpu(alpha), prec=prec, ckpt_every=2)
+    torch.cuda.synchronize()
+    Zg, da = Z.cpu().numpy().astype(np.float64), da.cpu().numpy().astype(np.float64)
+    d.close()
+    Zo, Fo, dao, its, _ = oracle.forward_backward(pb.D, pb.X, pb.lam, alpha, dF=np.full(pb.N, 1.0 / pb.N),
+                                                 return_adjoints=True)
+    zs = oracle.lasso_solution(pb.D, pb.X, pb.lam)
+    rel, gg, go = mean_gap_rel_error(pb.D, pb.X, pb.lam, Zg, Zo, zs)
+    err = float(np.max(np.abs(da - dao)) / np.max(np.abs(dao)))
+    zerr = float(np.max(np.abs(Zg - Zo)))
+    _say(f"[{prec}] 40x2600: mean-gap rel err {rel:.2e}, dalpha rel err {err:.2e}, max|dZ| {zerr:.2e}")
+    assert rel <= GAP_TOL[prec]
+    assert err <= DALPHA_TOL[prec]
+    if prec == "fp32":
+        assert zerr <= z_tolerance(pb.D, pb.X, alpha, its)
+
+
 def test_objective_entry_point(sl):
     """slista_objective evaluates Eq. (1) for given codes; compared with the
     oracle's FP64 objective on sparse and dense codes (FP32 residual: the
