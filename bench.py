@@ -56,7 +56,7 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "74b583d40542c14e3782c7d7c46d8bcc5f16288fc97785552527be41e429587f",
+    "sources_sha256": "da7306041829562a6355ed082bdd088c482e259806be1a170e3834d1e2fb0059",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {
