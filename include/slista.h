@@ -26,9 +26,15 @@
  *
  * Conventions (every entry point)
  *  - Pointers named "device" are HIP device pointers owned by the caller; the
- *    library never frees or keeps them beyond the call. Only slista_dict
- *    owns device memory (its Gram matrices), allocated in
- *    slista_dict_create and released in slista_dict_destroy.
+ *    library never frees or keeps them beyond the call (a batch keeps the
+ *    pointers of its problems until it is destroyed). The library owns
+ *    device memory only in a slista_dict (its Gram matrices and D^T,
+ *    allocated in slista_dict_create, released in slista_dict_destroy), in a
+ *    slista_batch (argument tables and work lists, allocated when it is bound,
+ *    released when it is destroyed), in the plans of slista_batched_fwd_bwd
+ *    (released by slista_batched_release), and in the static array of
+ *    slista_forward_scratch. Every other call allocates nothing: workspaces
+ *    come from the caller.
  *  - All matrices are row-major and sample-major: X is [N, n] (row i is x_i),
  *    Z and dZ are [N, m] (row i is z_i), D is [n, m].
  *  - `stream` is a hipStream_t (NULL = the legacy default stream). Work is
@@ -62,7 +68,9 @@ extern "C" {
 typedef enum {
   SLISTA_OK = 0,
   SLISTA_EINVAL = -1,     /* bad argument: size, null pointer, lambda, precision, workspace */
-  SLISTA_ENOMEM = -2,     /* device allocation failed (slista_dict_create only) */
+  SLISTA_ENOMEM = -2,     /* device allocation failed (slista_dict_create), or no workspace
+                             fits the budget (slista_ckpt_for_budget); a batch's table
+                             allocation failing reports SLISTA_EHIP */
   SLISTA_EHIP = -3,       /* a HIP runtime call or kernel launch failed */
   SLISTA_ENOTSUP = -4,    /* valid request this build does not support (e.g. no gfx950 device) */
   SLISTA_ENOTCONV = -5,   /* power iteration reached max_iter before rtol */
