@@ -375,8 +375,10 @@ SLISTA_API int slista_batched_release(void);
  *   2 the persistent kernels where they apply.
  * Both families compute bitwise-identical iterates and step-size gradients,
  * but keep the forward's tape in different layouts (per-layer: row-major;
- * persistent: four rows of a column together), so a slista_backward call
- * must run under the family of the slista_forward call that left its tape.
+ * persistent: four rows of a column together). The tape record (see
+ * slista_backward) includes the family and the tile variants, so a backward
+ * call under other settings than its forward recomputes the tape instead of
+ * reading the other layout.
  * ------------------------------------------------------------------------- */
 #define SLISTA_OPT_KERNEL_FAMILY 1
 /* SLISTA_OPT_PERSIST_VARIANT: tile configuration of the persistent kernels.
