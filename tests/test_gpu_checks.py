@@ -197,6 +197,33 @@ def test_backward_without_a_prior_forward(sl, name):
     d.close()
 
 
+def test_backward_under_another_kernel_family(sl):
+    """A forward under one kernel family leaves its tape in that family's
+    layout; a backward under the other family must not read it (the tape
+    record includes the family) and recomputes: its gradient equals the fused
+    call's of either family."""
+    pb = synth.make_problem(40, 160, 333, 0.08, 0.01, 0.1, seed=93)
+    T, k = 7, 2
+    alpha = synth.perturbed_steps(oracle.lipschitz(pb.D), T, seed=4)
+    d = sl.Dictionary(_gpu(pb.D))
+    X, a = _gpu(pb.X), _gpu(alpha)
+    dF = torch.full((pb.N,), 1.0 / pb.N, device=DEV)
+    try:
+        sl.set_kernel_family("persistent")
+        _, _, _, da_ref, _ = sl.forward_backward(d, X, pb.lam, a, prec="fp32", ckpt_every=k)
+        ws = d.workspace(pb.N, T, "fp32", k)
+        for fwd_fam, bwd_fam in (("persistent", "layer"), ("layer", "persistent")):
+            sl.set_kernel_family(fwd_fam)
+            sl.forward(d, X, pb.lam, a, prec="fp32", ckpt_every=k, ws=ws)
+            sl.set_kernel_family(bwd_fam)
+            da = sl.backward(d, X, pb.lam, a, ws, dF=dF, prec="fp32", ckpt_every=k)
+            ref = da_ref.cpu().numpy()
+            np.testing.assert_allclose(da.cpu().numpy(), ref, rtol=1e-6, atol=1e-12 * np.max(np.abs(ref)))
+    finally:
+        sl.set_kernel_family("auto")
+    d.close()
+
+
 def test_check_finite_flag(sl):
     pb = synth.make_problem(16, 48, 70, 0.1, 0.0, 0.1, seed=14)
     d = sl.Dictionary(_gpu(pb.D))
