@@ -416,8 +416,11 @@ SLISTA_API int slista_set_option(int option, int value);
  *   z^{t+1} = ST(y^t - alpha_t (G y^t - c), lam alpha_t),
  *   y^{t+1} = z^{t+1} + beta_t (z^{t+1} - z^t),
  * beta_t = (tau_t - 1) / tau_{t+1}, tau_0 = 1, tau_{t+1} = (1 + sqrt(1 +
- * 4 tau_t^2)) / 2 (computed on the device). Forward only, per-layer kernels
- * (G y^t on MFMA in the given precision, the update fused). Z [N, m] out;
+ * 4 tau_t^2)) / 2 (computed on the device). Forward only. For m_pad <= 512
+ * (and the automatic or persistent kernel family) one persistent launch
+ * carries each tile's z and y through all layers (tile variants 2 and 4);
+ * otherwise one per-layer launch per layer (G y^t on MFMA in the given
+ * precision, the update fused). Both give bitwise-equal codes. Z [N, m] out;
  * F [N] (F(z^T)) and loss (mean F) out if not NULL. Workspace of
  * slista_fista_workspace_size bytes, 256-byte aligned. Errors as for
  * slista_forward.

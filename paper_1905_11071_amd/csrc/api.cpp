@@ -1551,6 +1551,25 @@ int slista_fista(const slista_dict* dict, const float* X, int N, float lambda, c
   float* ybuf[2] = {(float*)((char*)ws + off[0]), (float*)((char*)ws + off[0] + align256(r.L.zbytes))};
   float* beta = (float*)((char*)ws + off[1]);
   LAUNCH(kKOther, s, slista::launch_fista_beta(T, beta, s));
+  if (kernel_family() != 1 && slista::fista_persist_applies(mp)) {
+    // one persistent launch: each tile carries z and y through all layers;
+    // the first y buffer holds the row-group copy of c it reads
+    float* Cg = ybuf[0];
+    LAUNCH(kKOther, s, slista::launch_row_groups(r.C(), N, mp, Cg, s));
+    slista::PersistArgs a = persist_args(r, prec, alpha, lambda);
+    a.Cg = Cg;
+    a.beta = beta;
+    a.k = 0;
+    a.t_begin = 0;
+    a.t_end = T;
+    a.mode = (F || loss) ? slista::kModeF : 0;
+    a.F = F;
+    a.Fd = r.Fd();
+    a.Zuser = Z;
+    LAUNCH(kKFwd, s, slista::launch_fista_persist(prec, a, s, variant_for(prec, mp, N)));
+    if (loss) LAUNCH(kKOther, s, slista::launch_reduce_loss(r.Fd(), N, loss, s));
+    return SLISTA_OK;
+  }
   // layer 0: y^0 = z^0 = 0, so z^1 = ST(alpha_0 c, lam alpha_0) and y^1 = z^1 (beta_0 = 0)
   LAUNCH(kKOther, s, slista::launch_layer0(r.C(), N, mp, alpha, lambda, r.slot(1), s));
   const float* y = r.slot(1);

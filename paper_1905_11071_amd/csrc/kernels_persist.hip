@@ -106,6 +106,21 @@ hipError_t launch_persist_batched(bool fwd, int prec, int np, int variant, const
                        : launch_persist_batched_f32(fwd, np, variant, tab, work, nwork, max_m_pad, ph, s);
 }
 
+bool fista_persist_applies(int m_pad) { const int np = np_of(m_pad); return np == 1 || np == 2; }
+
+static int fista_variant(int variant) { return variant == 2 ? 2 : 4; }
+
+int fista_persist_rows(int prec, int m_pad, int variant) {
+  return fista_persist_applies(m_pad) ? persist_rows(prec, m_pad, fista_variant(variant)) : 0;
+}
+
+hipError_t launch_fista_persist(int prec, const PersistArgs& a, hipStream_t s, int variant) {
+  if (!fista_persist_applies(a.m_pad) || a.t_begin != 0 || a.k != 0 || (a.N > 0 && (!a.Cg || !a.beta)))
+    return hipErrorInvalidValue;
+  const int np = np_of(a.m_pad), v = fista_variant(variant);
+  return prec == kBF16 ? launch_fista_persist_bf16(np, v, a, s) : launch_fista_persist_f32(np, v, a, s);
+}
+
 hipError_t launch_swizzle(const float* G32, int mp, uint16_t* Gsb, float* Gsf, hipStream_t s) {
   const size_t total = (size_t)mp * mp;
   size_t blocks = (total + 255) / 256;

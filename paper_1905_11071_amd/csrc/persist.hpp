@@ -17,6 +17,7 @@ struct PersistArgs {
   int N, m;
   const float* Cg;    // c = D^T x in row-group order (as the tape), read every layer
   const float* alpha;
+  const float* beta;  // FISTA momentum weights beta_t (FISTA launches only)
   float lam;
   // where z^t lives (see the workspace layout in api.cpp)
   char* ckpt;
@@ -68,6 +69,15 @@ hipError_t launch_persist_batched_bf16(bool fwd, int np, int variant, const Pers
 hipError_t launch_persist_batched_f32(bool fwd, int np, int variant, const PersistArgs* tab, const int2* work,
                                       int nwork, int max_m_pad, const PersistPhase& ph, hipStream_t s);
 hipError_t launch_swizzle(const float* G32, int m_pad, uint16_t* Gsb, float* Gsf, hipStream_t s);
+// FISTA forward through the persistent kernels (variants 2 and 4, m_pad <=
+// 512: the tile carries z and y in registers). a.t_begin = 0, a.k = 0;
+// a.beta holds the momentum weights. Variant 0 or one that does not exist
+// runs variant 4.
+bool fista_persist_applies(int m_pad);
+int fista_persist_rows(int prec, int m_pad, int variant);
+hipError_t launch_fista_persist(int prec, const PersistArgs& a, hipStream_t s, int variant);
+hipError_t launch_fista_persist_bf16(int np, int variant, const PersistArgs& a, hipStream_t s);
+hipError_t launch_fista_persist_f32(int np, int variant, const PersistArgs& a, hipStream_t s);
 // Column-pass bucket of m_pad (1, 2, 4, 8; 0 = not handled).
 int persist_np(int m_pad);
 // One launch over the work list (problem, tile) of problems in bucket np; the

@@ -323,8 +323,14 @@ __device__ __forceinline__ void load_master_tape(float (&zm)[NP][FM][FB][4], con
 // Forward over layers [t_begin, t_end): z^(t+1) = ST(z^t - a_t (G z^t - c), lam a_t),
 // keeping the tape; with TRACE also F(z^t) for each t. Then, if asked, one
 // more contraction G z^(t_end) for F(z^(t_end)) and the backward seed.
-template <int P, int R, int NP, bool TRACE, int PF, int WR, int WC>
+// FISTA: the tile also carries y^t (FISTA's extrapolated point) in
+// registers; the contraction is G y^t, the epilogue z^{t+1} = ST(y^t -
+// alpha_t (G y^t - c), lam alpha_t), y^{t+1} = z^{t+1} + beta_t (z^{t+1} - z^t)
+// (the per-layer FISTA epilogue's expressions), and the LDS tile holds y;
+// the final contraction for F takes z^T. No tape, no trace.
+template <int P, int R, int NP, bool TRACE, int PF, int WR, int WC, bool FISTA = false>
 __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* lds) {
+  static_assert(!(FISTA && TRACE), "FISTA runs without the objective trace");
   constexpr int FM = R / (16 * WR);  // 16-row blocks per wave
   constexpr int FB = 16 / WC;        // 16-column blocks per wave and pass
   const int tid = threadIdx.x, lane = tid & 63;
@@ -345,6 +351,17 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
   const Rsrc rZu = make_rsrc(g.Zuser ? g.Zuser + (size_t)row0 * m : nullptr, g.Zuser ? (size_t)nrows * ustride : 0);
 
   float zm[NP][FM][FB][4];
+  float ym[FISTA ? NP : 1][FM][FB][4];  // FISTA's y^t (z^0 = y^0 = 0; t_begin = 0)
+  if constexpr (FISTA) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int f = 0; f < FB; ++f)
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) ym[p][fm][f][r4] = 0.f;
+  }
   if (g.t_begin == 0) {
 #pragma unroll
     for (int p = 0; p < NP; ++p)
@@ -364,6 +381,7 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
   for (int t = g.t_begin; t < g.t_end; ++t) {
     const float a = g.alpha[t];
     const float lam = g.lam, th = lam * a;
+    const float bt = FISTA ? g.beta[t] : 0.f;
     const bool store = g.k > 0 && (g.store_all || (t + 1) % g.k == 0 || t + 1 == g.T || t + 1 > g.a_last);
     const Rsrc rD = make_rsrc(store ? slot_ptr(g, t + 1) + (size_t)row0 * m_pad : nullptr,
                               store ? tape_bytes(nrows, m_pad) : 0);
@@ -415,7 +433,14 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
             const float c = cg[f][r4];
             const float pv = acc[fm][f][r4];
             if constexpr (TRACE) fs[fm][r4] += 0.5f * z * pv - z * c + lam * fabsf(z);
-            const float zn = soft_thresh(z - a * (pv - c), th);
+            float zn;
+            if constexpr (FISTA) {
+              const float y = ym[p][fm][f][r4];
+              zn = soft_thresh(y - a * (pv - c), th);
+              ym[p][fm][f][r4] = zn + bt * (zn - z);
+            } else {
+              zn = soft_thresh(z - a * (pv - c), th);
+            }
             zm[p][fm][f][r4] = zn;
             if (copy_out && colb + 16 * f < m) bstore(zn, rZu, lou + 64 * f, sou);
           }
@@ -431,7 +456,10 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
     if constexpr (TRACE)
       finish_rows<FM, R, WC>(fs, red, wave, rbase, lane, tid, row0, N, g.xsq, g.Ftrace + (size_t)t * N, nullptr);
     __syncthreads();
-    master_to_lds<P, FM, FB, NP, WC>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
+    if constexpr (FISTA)
+      master_to_lds<P, FM, FB, NP, WC>(ym, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
+    else
+      master_to_lds<P, FM, FB, NP, WC>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
     __syncthreads();
   }
 
@@ -454,6 +482,11 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
     }
   }
   if (!(g.mode & (kModeF | kModeSeed))) return;
+  if constexpr (FISTA) {
+    // the LDS tile holds y^T; F takes z^T (every wave is past the last barrier)
+    master_to_lds<P, FM, FB, NP, WC>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
+    __syncthreads();
+  }
   // final contraction: F(z^(t_end)) and / or the seed of the backward pass
   const bool want_f = (g.mode & kModeF) != 0;
   const bool seed = (g.mode & kModeSeed) != 0;
@@ -637,6 +670,12 @@ __global__ __launch_bounds__(64 * WC * WR, OCC) void fwd_persist(PersistArgs g) 
 }
 
 template <int P, int R, int NP, int PF, int OCC, int WR, int WC>
+__global__ __launch_bounds__(64 * WC * WR, OCC) void fista_persist(PersistArgs g) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  fwd_body<P, R, NP, false, PF, WR, WC, true>(g, blockIdx.x, lds);
+}
+
+template <int P, int R, int NP, int PF, int OCC, int WR, int WC>
 __global__ __launch_bounds__(64 * WC * WR, OCC) void bwd_persist(PersistArgs g) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   bwd_body<P, R, NP, PF, WR, WC>(g, blockIdx.x, lds);
@@ -702,6 +741,18 @@ hipError_t launch_pair(bool fwd, const PersistArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((fwd_persist<P, R, NP, true, PF, OCC, WR, WC>), dim3(tiles), block, lds, s, a);
   else
     hipLaunchKernelGGL((fwd_persist<P, R, NP, false, PF, OCC, WR, WC>), dim3(tiles), block, lds, s, a);
+  return hipGetLastError();
+}
+
+template <int P, int R, int NP, int PF, int OCC, int WR = 1, int WC = 4>
+hipError_t launch_fista(const PersistArgs& a, hipStream_t s) {
+  const int tiles = (a.N + R - 1) / R;
+  if (tiles == 0) return hipSuccess;
+  const size_t lds = tile_lds<P, R, WC>(a.m_pad);
+  hipError_t e = hipFuncSetAttribute((const void*)fista_persist<P, R, NP, PF, OCC, WR, WC>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((fista_persist<P, R, NP, PF, OCC, WR, WC>), dim3(tiles), dim3(64 * WC * WR), lds, s, a);
   return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
-"""FISTA (slista_fista, per-layer kernels) against the FP64 oracle's FISTA.
-The momentum makes the iteration non-contractive, so the codes are compared
-through the objective: the relative error of the mean gap (1e-5 FP32, 2e-2
-BF16) and per-sample objective values."""
+"""FISTA (slista_fista: persistent kernels for m_pad <= 512, per-layer
+kernels above) against the FP64 oracle's FISTA. The momentum makes the
+iteration non-contractive, so the codes are compared through the objective:
+the relative error of the mean gap (1e-5 FP32, 2e-2 BF16) and per-sample
+objective values. The two kernel families give bitwise-equal codes."""
 import sys
 
 import numpy as np
@@ -83,4 +84,34 @@ def test_fista_edge_cases(sl):
     Zf, _, _ = sl.fista(d, _gpu(pb.X), pb.lam, _gpu(a))              # two layers: FISTA = ISTA
     Zi, _, _, _ = sl.forward(d, _gpu(pb.X), pb.lam, _gpu(a))
     assert np.array_equal(Zf.cpu().numpy(), Zi.cpu().numpy())
+    d.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("shape", [(50, 200, 1037, 15), (64, 256, 3000, 12), (80, 448, 515, 9)])
+def test_fista_kernel_families_agree(sl, prec, shape):
+    """The persistent FISTA kernel (tile variants 2 and 4; one and two column
+    passes, ragged N) and the per-layer one use the same K order and epilogue
+    expressions: z^T bitwise equal, F equal up to the grouping of its sums."""
+    n, m, N, T = shape
+    pb = synth.make_problem(n, m, N, 0.05, 0.01, 0.1, seed=700 + m)
+    alpha = synth.perturbed_steps(oracle.lipschitz(pb.D), T, seed=701)
+    d = sl.Dictionary(_gpu(pb.D))
+    X, a = _gpu(pb.X), _gpu(alpha)
+    out = {}
+    try:
+        for fam, variants in (("layer", (0,)), ("persistent", (2, 4))):
+            sl.set_kernel_family(fam)
+            for v in variants:
+                sl.set_tile_variant(v)
+                Z, F, loss = sl.fista(d, X, pb.lam, a, prec=prec)
+                out[(fam, v)] = (Z.cpu().numpy(), F.cpu().numpy(), float(loss.item()))
+    finally:
+        sl.set_tile_variant(0)
+        sl.set_kernel_family("auto")
+    Zr, Fr, lr = out[("layer", 0)]
+    for key, (Z, F, loss) in out.items():
+        assert np.array_equal(Z, Zr), key
+        np.testing.assert_allclose(F, Fr, rtol=1e-5, atol=1e-7)
+        assert abs(loss - lr) <= 1e-5 * abs(lr), key
     d.close()
