@@ -56,14 +56,14 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "da7306041829562a6355ed082bdd088c482e259806be1a170e3834d1e2fb0059",
+    "sources_sha256": "7885b204814cd7d954b2764eb7d4948c8baadaaee60a90d6791da085ff1e2ae2",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {
-        ("bf16", "forward_layer"): (8333298.6875 * 2 + 13650688) * 1024,
-        ("bf16", "backward_layer"): (7728264.9375 * 2 + 10060.59375) * 1024,
-        ("fp32", "forward_layer"): (14679313.1875 * 2 + 13634496.9375) * 1024,
-        ("fp32", "backward_layer"): (13997890.0 * 2 + 3248.46875) * 1024,
+        ("bf16", "forward_layer"): (8333159.625 * 2 + 13650688.875) * 1024,
+        ("bf16", "backward_layer"): (7897020.3125 * 2 + 10037.6875) * 1024,
+        ("fp32", "forward_layer"): (14733277.9375 * 2 + 13634259.875) * 1024,
+        ("fp32", "backward_layer"): (13370312.1875 * 2 + 3253.40625) * 1024,
     },
 }
 
