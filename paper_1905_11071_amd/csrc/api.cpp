@@ -50,7 +50,9 @@ struct slista_batch {
     int variant[2] = {0, 0}, nwork[2] = {0, 0};
     std::vector<int> problems;
     size_t work_off[2] = {0, 0};        // index of the bucket's first work item
-    size_t small_off = 0;               // index of its first entry in d_small
+    size_t small_off = 0;               // index of its first entry in d_small (and d_corr)
+    size_t tstart_off = 0;              // index of its tile-start prefix sums in d_tstart
+    int corr_tiles = 0;                 // correlation-product tiles of its problems
     int max_N = 0;                      // largest N of its problems
     size_t max_group_elems = 0;         // largest row-group copy of c (float4 count)
   };
@@ -62,6 +64,8 @@ struct slista_batch {
   int2* d_work = nullptr;
   size_t work_cap = 0;                  // entries d_work holds
   slista::BatchSmall* d_small = nullptr;  // [P] small-kernel table, bucket by bucket
+  slista::GemmArgs* d_corr = nullptr;     // [P] correlation-product arguments, same order
+  int* d_tstart = nullptr;                // per bucket: tile-start prefix sums
   char* ws = nullptr;
   size_t ws_bytes = 0;
   hipGraph_t graph = nullptr;
@@ -466,8 +470,8 @@ int fwd_layer(const Run& r, int prec, const float* alpha, float lam, int t, doub
   return SLISTA_OK;
 }
 
-// c = D^T x for every sample (row-major).
-int prep_corr(const Run& r, const float* X) {
+// Arguments of the correlation product c = D^T x for every sample (row-major).
+slista::GemmArgs corr_args(const Run& r, const float* X) {
   slista::GemmArgs g;
   std::memset(&g, 0, sizeof g);
   g.A = X;
@@ -480,6 +484,11 @@ int prep_corr(const Run& r, const float* X) {
   g.Out = r.C();
   g.ldz = r.d->m_pad;
   slista::gemm_grid(r.N, r.d->m_pad, g);
+  return g;
+}
+
+int prep_corr(const Run& r, const float* X) {
+  const slista::GemmArgs g = corr_args(r, X);
   LAUNCH(kKCorr, r.s, slista::launch_gemm(slista::kF32, slista::kEpiCorr, true, g, r.s));
   return SLISTA_OK;
 }
@@ -2005,6 +2014,8 @@ static int batch_upload_work(slista_batch* b, hipStream_t s) {
   }
   HIP_TRY(hipMemcpyAsync(b->d_work, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, s));
   std::vector<slista::BatchSmall> small;
+  std::vector<slista::GemmArgs> corr;
+  std::vector<int> tstart;
   if (b->ws) {
     // the small kernels' table: buffers of the bound workspace and the
     // step-gradient partial counts of the current tile rows
@@ -2012,11 +2023,16 @@ static int batch_upload_work(slista_batch* b, hipStream_t s) {
     const int p_lo = sc.at(0), p_hi = sc.at(b->T > 0 ? b->T - 1 : 0);
     for (auto& bk : b->buckets) {
       bk.small_off = small.size();
+      bk.tstart_off = tstart.size();
+      bk.corr_tiles = 0;
       bk.max_N = 0;
       bk.max_group_elems = 0;
       for (int p : bk.problems) {
         const slista_problem& q = b->probs[p];
         Run r = batch_run_of(b, p, s);
+        corr.push_back(corr_args(r, q.X));
+        tstart.push_back(bk.corr_tiles);
+        bk.corr_tiles += corr.back().row_tiles * corr.back().col_tiles;
         const int tiles_lo = (q.N + b->rows[p_lo][p] - 1) / b->rows[p_lo][p];
         const int tiles_hi = (q.N + b->rows[p_hi][p] - 1) / b->rows[p_hi][p];
         slista::BatchSmall e;
@@ -2041,10 +2057,16 @@ static int batch_upload_work(slista_batch* b, hipStream_t s) {
         bk.max_N = std::max(bk.max_N, q.N);
         if (e.Cg) bk.max_group_elems = std::max(bk.max_group_elems, (size_t)(q.N + 3) / 4 * e.mp);
       }
+      tstart.push_back(bk.corr_tiles);
     }
     if (!b->d_small) HIP_TRY(hipMalloc(&b->d_small, sizeof(slista::BatchSmall) * std::max(b->P, 1)));
+    if (!b->d_corr) HIP_TRY(hipMalloc(&b->d_corr, sizeof(slista::GemmArgs) * std::max(b->P, 1)));
+    if (!b->d_tstart) HIP_TRY(hipMalloc(&b->d_tstart, sizeof(int) * (b->P + b->buckets.size())));
     HIP_TRY(hipMemcpyAsync(b->d_small, small.data(), sizeof(slista::BatchSmall) * small.size(),
                            hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b->d_corr, corr.data(), sizeof(slista::GemmArgs) * corr.size(), hipMemcpyHostToDevice,
+                           s));
+    HIP_TRY(hipMemcpyAsync(b->d_tstart, tstart.data(), sizeof(int) * tstart.size(), hipMemcpyHostToDevice, s));
   }
   HIP_TRY(hipStreamSynchronize(s));
   return SLISTA_OK;
@@ -2171,10 +2193,10 @@ static int batch_run_bucket(slista_batch* b, size_t bi, hipStream_t s) {
   int st;
   const slista::BatchSmall* small = b->d_small + bk.small_off;
   const int nprob = (int)bk.problems.size();
-  // c per problem (one correlation product each), then the norms and the
-  // row-group copies of every problem in one launch
-  for (int p : bk.problems)
-    if ((st = prep_corr(batch_run_of(b, p, s), b->probs[p].X)) != SLISTA_OK) return st;
+  // c of every problem (one grouped correlation launch), then the norms and
+  // the row-group copies of every problem in one launch
+  LAUNCH(kKCorr, s, slista::launch_corr_grouped(b->d_corr + bk.small_off, b->d_tstart + bk.tstart_off, nprob,
+                                                bk.corr_tiles, s));
   LAUNCH(kKOther, s, slista::launch_batch_prep(small, nprob, bk.max_N, bk.max_group_elems, s));
   auto phase = [&](bool fwd, int pr, slista::PersistPhase ph) -> int {
     LAUNCH(fwd ? kKFwd : kKBwd, s,
@@ -2319,6 +2341,8 @@ int slista_batch_destroy(slista_batch* b) {
   (void)hipFree(b->d_args[1]);
   (void)hipFree(b->d_work);
   (void)hipFree(b->d_small);
+  (void)hipFree(b->d_corr);
+  (void)hipFree(b->d_tstart);
   for (hipStream_t q : b->side) (void)hipStreamDestroy(q);
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
   delete b;

@@ -82,6 +82,11 @@ struct GemmArgs {
 
 // Launchers (kernels_gemm.hip)
 hipError_t launch_gemm(int prec, int epi, bool safe, const GemmArgs& a, hipStream_t s);
+// c = X D for several problems in one launch (FP32, bounds-checked like the
+// single-problem correlation product): tab[p] as prep fills it for problem p,
+// tile_start[0 .. nprob] the prefix sums of their tile counts (device).
+hipError_t launch_corr_grouped(const GemmArgs* tab, const int* tile_start, int nprob, int total_tiles,
+                               hipStream_t s);
 void gemm_grid(int rows, int ncols, GemmArgs& a);  // fills the tile counts
 
 // Launchers (kernels_misc.hip)

@@ -162,20 +162,9 @@ __device__ __forceinline__ float soft_thresh(float u, float th) {
   return au > 0.f ? copysignf(au, u) : 0.f;
 }
 
+// One output tile of a fused contraction (the tile index already mapped).
 template <int P, int EPI, bool SAFE>
-__global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) char smem[2 * STAGE_BYTES];
-  if constexpr (EPI == kEpiSplit) {  // K chunk of one batch entry of a split contraction
-    const size_t y = blockIdx.y, bi = y / g.ksplit, sp = y - bi * g.ksplit;
-    g.A += bi * g.a_batch + sp * g.a_split;
-    g.Bt = (const float*)g.Bt + bi * g.b_batch + sp * g.b_split;
-    g.Out += y * g.out_split;
-  }
-  const int b = blockIdx.x;
-  // split contractions launch exactly their tiles in x, so that the (tile,
-  // chunk) workgroups spread over all XCDs; the others order tiles XCD-contiguously
-  const int tile = EPI == kEpiSplit ? b : (b & 7) * g.tiles_per_xcd + (b >> 3);
-  if (tile >= g.row_tiles * g.col_tiles) return;
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tile, char* smem) {
   const int rt = tile / g.col_tiles, ct = tile - rt * g.col_tiles;
   const int row0 = rt * BM, col0 = ct * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -312,6 +301,42 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
 }
 
 template <int P, int EPI, bool SAFE>
+__global__ __launch_bounds__(NTHREADS) void gemm_fused(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) char smem[2 * STAGE_BYTES];
+  if constexpr (EPI == kEpiSplit) {  // K chunk of one batch entry of a split contraction
+    const size_t y = blockIdx.y, bi = y / g.ksplit, sp = y - bi * g.ksplit;
+    g.A += bi * g.a_batch + sp * g.a_split;
+    g.Bt = (const float*)g.Bt + bi * g.b_batch + sp * g.b_split;
+    g.Out += y * g.out_split;
+  }
+  const int b = blockIdx.x;
+  // split contractions launch exactly their tiles in x, so that the (tile,
+  // chunk) workgroups spread over all XCDs; the others order tiles XCD-contiguously
+  const int tile = EPI == kEpiSplit ? b : (b & 7) * g.tiles_per_xcd + (b >> 3);
+  if (tile >= g.row_tiles * g.col_tiles) return;
+  gemm_tile<P, EPI, SAFE>(g, tile, smem);
+}
+
+// Correlation products c = X D of several problems in one launch: workgroup
+// b takes tile b - tile_start[p] of problem p, where tile_start (nprob + 1
+// prefix sums of the problems' tile counts) brackets b. Each tile runs
+// gemm_tile exactly as a single-problem launch would.
+__global__ __launch_bounds__(NTHREADS) void gemm_corr_grouped(const GemmArgs* __restrict__ tab,
+                                                              const int* __restrict__ tile_start, int nprob) {
+  __shared__ __attribute__((aligned(16))) char smem[2 * STAGE_BYTES];
+  const int b = blockIdx.x;
+  int lo = 0, hi = nprob;  // largest p with tile_start[p] <= b
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (tile_start[mid] <= b) lo = mid; else hi = mid;
+  }
+  const GemmArgs g = tab[lo];
+  const int tile = b - tile_start[lo];
+  if (tile >= g.row_tiles * g.col_tiles) return;
+  gemm_tile<kF32, kEpiCorr, true>(g, tile, smem);
+}
+
+template <int P, int EPI, bool SAFE>
 hipError_t launch_one(const GemmArgs& a, hipStream_t s) {
   const int grid = EPI == kEpiSplit ? a.row_tiles * a.col_tiles : 8 * a.tiles_per_xcd;
   const int splits = EPI == kEpiSplit ? a.ksplit * (a.nbatch > 0 ? a.nbatch : 1) : 1;
@@ -327,6 +352,13 @@ void gemm_grid(int rows, int ncols, GemmArgs& a) {
   a.col_tiles = (ncols + BN - 1) / BN;
   const int total = a.row_tiles * a.col_tiles;
   a.tiles_per_xcd = (total + 7) / 8;
+}
+
+hipError_t launch_corr_grouped(const GemmArgs* tab, const int* tile_start, int nprob, int total_tiles,
+                               hipStream_t s) {
+  if (nprob == 0 || total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(gemm_corr_grouped, dim3(total_tiles), dim3(NTHREADS), 0, s, tab, tile_start, nprob);
+  return hipGetLastError();
 }
 
 hipError_t launch_gemm(int prec, int epi, bool safe, const GemmArgs& a, hipStream_t s) {
