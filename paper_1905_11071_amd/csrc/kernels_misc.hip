@@ -303,15 +303,19 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
-// LDS: q, q_prev, w [mp] doubles each, the tridiagonal (2 kLsMaxSteps
-// doubles), r = D_S q [n_pad] doubles, G_SS [kLsCache][kLsCache + 1] floats,
-// support indices [mp] ints.
-__host__ __device__ size_t support_vec_bytes(int mp, int n) {
-  return ((size_t)3 * mp + 2 * kLsMaxSteps + (size_t)(n + 63) / 64 * 64) * sizeof(double);
+// Two launches per call split the samples by support size, so that each
+// sizes its LDS for its own path (the large-support one needs no G_SS cache
+// and so keeps more workgroups per CU). LDS: q, q_prev, w [mp] doubles each,
+// the tridiagonal (2 kLsMaxSteps doubles), then r = D_S q [n_pad] doubles
+// (large supports) or G_SS [kLsCache][kLsCache + 1] floats (small ones), and
+// the support indices [mp] ints.
+__host__ __device__ size_t support_vec_bytes(int mp, int n, bool large) {
+  return ((size_t)3 * mp + 2 * kLsMaxSteps + (large ? (size_t)(n + 63) / 64 * 64 : 0)) * sizeof(double);
 }
 
-size_t ls_lds_bytes(int mp, int n) {
-  return support_vec_bytes(mp, n) + (size_t)kLsCache * (kLsCache + 1) * sizeof(float) + (size_t)mp * sizeof(int);
+__host__ __device__ size_t ls_lds_bytes(int mp, int n, bool large) {
+  return support_vec_bytes(mp, n, large) + (large ? 0 : (size_t)kLsCache * (kLsCache + 1) * sizeof(float)) +
+         (size_t)mp * sizeof(int);
 }
 
 // Number of eigenvalues below x of the symmetric tridiagonal matrix with
@@ -353,6 +357,10 @@ __device__ double tridiag_top(const double* a, const double* b, int k, int lane)
   return hi;
 }
 
+// LARGE: this launch handles the samples whose support holds more than
+// kLsCache atoms (factored form); otherwise those with at most kLsCache
+// (G_SS cached in LDS), including empty supports.
+template <bool LARGE>
 __global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __restrict__ G,
                                                                const float* __restrict__ Dt, int n, int m, int mp,
                                                                const float* __restrict__ Z, float* __restrict__ V,
@@ -364,9 +372,9 @@ __global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __r
   double* wv = qp + mp;                     // [mp] D_S^T D_S q_j, then the next residual
   double* la = wv + mp;                     // [kLsMaxSteps] tridiagonal: diagonal
   double* lb = la + kLsMaxSteps;            // [kLsMaxSteps] off-diagonal (lb[j] couples j-1, j)
-  double* rv = lb + kLsMaxSteps;            // [n_pad] D_S q_j (supports above kLsCache)
-  float* gs = (float*)(sm + support_vec_bytes(mp, n));  // [kLsCache][kLsCache + 1]
-  int* idx = (int*)(gs + kLsCache * (kLsCache + 1));    // [mp]
+  double* rv = lb + kLsMaxSteps;            // [n_pad] D_S q_j (LARGE)
+  float* gs = (float*)(sm + support_vec_bytes(mp, n, LARGE));  // [kLsCache][kLsCache + 1] (not LARGE)
+  int* idx = (int*)(sm + ls_lds_bytes(mp, n, LARGE) - (size_t)mp * sizeof(int));  // [mp]
   const int i = blockIdx.x, lane = threadIdx.x;
   const float* z = Z + (size_t)i * mp;
   unsigned long long* memo = (unsigned long long*)(V + (size_t)i * mp);  // [mp / 2] words
@@ -382,6 +390,7 @@ __global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __r
     same = same && memo[j0 / kLsLanes] == ball;
   }
   __syncthreads();
+  if ((ns > kLsCache) != LARGE) return;  // the other launch's sample
   if (same) return;  // the support of the last call: step[i] holds its 1/L_S
   // record this support (every lane holds every ballot; lane 0 writes them)
   {
@@ -397,7 +406,7 @@ __global__ __launch_bounds__(kLsLanes) void k_support_lipschitz(const float* __r
     if (lane == 0) step[i] = (float)(1.0 / L);
     return;
   }
-  const bool cached = ns <= kLsCache;
+  constexpr bool cached = !LARGE;
   if (cached)
     for (int e = lane; e < ns * ns; e += kLsLanes) {
       const int r = e / ns, c = e - r * ns;
@@ -665,17 +674,25 @@ hipError_t launch_alpha_step(const float* alpha, const float* g, double eta, int
   return hipGetLastError();
 }
 
-size_t support_lipschitz_lds(int m_pad, int n) { return ls_lds_bytes(m_pad, n); }
+size_t support_lipschitz_lds(int m_pad, int n) {
+  const size_t a = ls_lds_bytes(m_pad, n, true), b = ls_lds_bytes(m_pad, n, false);
+  return a > b ? a : b;
+}
 
 hipError_t launch_support_lipschitz(const float* G32, const float* Dt, int n, int m, int mp, const float* Z, float* V,
                                     double L, int max_iter, double tol, int N, float* step, hipStream_t s) {
   if (N == 0) return hipSuccess;
-  const size_t lds = ls_lds_bytes(mp, n);
-  hipError_t e = hipFuncSetAttribute((const void*)k_support_lipschitz, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
+  const size_t lds_l = ls_lds_bytes(mp, n, true), lds_s = ls_lds_bytes(mp, n, false);
+  hipError_t e = hipFuncSetAttribute((const void*)k_support_lipschitz<true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_l);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_support_lipschitz, dim3(N), dim3(kLsLanes), lds, s, G32, Dt, n, m, mp, Z, V, L, max_iter,
-                     tol, step);
+  e = hipFuncSetAttribute((const void*)k_support_lipschitz<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds_s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_support_lipschitz<true>, dim3(N), dim3(kLsLanes), lds_l, s, G32, Dt, n, m, mp, Z, V, L,
+                     max_iter, tol, step);
+  hipLaunchKernelGGL(k_support_lipschitz<false>, dim3(N), dim3(kLsLanes), lds_s, s, G32, Dt, n, m, mp, Z, V, L,
+                     max_iter, tol, step);
   return hipGetLastError();
 }
 
