@@ -56,7 +56,7 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "7885b204814cd7d954b2764eb7d4948c8baadaaee60a90d6791da085ff1e2ae2",
+    "sources_sha256": "2f9745a8fc1812b24693d3bcf41cd426d4b583660ae76d0a9933629cebdfc135",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {
