@@ -72,7 +72,7 @@ typedef enum {
                              fits the budget (slista_ckpt_for_budget); a batch's table
                              allocation failing reports SLISTA_EHIP */
   SLISTA_EHIP = -3,       /* a HIP runtime call or kernel launch failed */
-  SLISTA_ENOTSUP = -4,    /* valid request this build does not support (e.g. no gfx950 device) */
+  SLISTA_ENOTSUP = -4,    /* valid request the library does not support (e.g. no gfx950 device) */
   SLISTA_ENOTCONV = -5,   /* power iteration reached max_iter before rtol */
   SLISTA_ENONFINITE = -6  /* the finite-value check found NaN or Inf (SLISTA_OPT_CHECK_FINITE) */
 } slista_status;
