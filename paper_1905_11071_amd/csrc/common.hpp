@@ -14,6 +14,25 @@ constexpr int kPadM = 64;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// ST(u, th) = sign(u) max(|u| - th, 0) (Section 1, after Eq. (2)), written
+// as u - clamp(u, -th, th): one median-of-three and one subtraction. For
+// every finite u this is the same FP32 value as the sign / max form (both
+// round only |u| - th, and rounding to nearest is symmetric); a NaN u gives
+// NaN.
+__device__ __forceinline__ float soft_threshold(float u, float th) {
+  return u - __builtin_amdgcn_fmed3f(u, -th, th);
+}
+
+// A wave-uniform float, materialised in a scalar register: a product such as
+// the threshold lam alpha_t is rounded once there and cannot be contracted
+// into a later subtraction (a fused |u| - lam alpha_t would round
+// differently, element by element, from kernel to kernel).
+__device__ __forceinline__ float uniform_f32(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
 
 enum Prec : int { kF32 = 0, kBF16 = 1 };
 

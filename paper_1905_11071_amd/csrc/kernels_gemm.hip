@@ -101,8 +101,9 @@ __device__ __forceinline__ void load_stage(StageRegs<P>& st, const GemmArgs& g, 
   }
 }
 
-template <int P>
-__device__ __forceinline__ void store_stage(const StageRegs<P>& st, char* buf, int tid) {
+// SCALE: the BF16 A operand is sc z (the folded forward layer, sc = -alpha_t).
+template <int P, bool SCALE = false>
+__device__ __forceinline__ void store_stage(const StageRegs<P>& st, char* buf, int tid, float sc = 1.f) {
   const int q = tid & 7, r = tid >> 3;
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
@@ -110,7 +111,11 @@ __device__ __forceinline__ void store_stage(const StageRegs<P>& st, char* buf, i
     if constexpr (P == kF32) {
       *(float4*)(buf + off) = st.a[p];
     } else {
-      const float4 lo = st.a[2 * p], hi = st.a[2 * p + 1];
+      float4 lo = st.a[2 * p], hi = st.a[2 * p + 1];
+      if constexpr (SCALE) {
+        lo = make_float4(sc * lo.x, sc * lo.y, sc * lo.z, sc * lo.w);
+        hi = make_float4(sc * hi.x, sc * hi.y, sc * hi.z, sc * hi.w);
+      }
       *(uint4*)(buf + off) = make_uint4(pack_bf16x2(lo.x, lo.y), pack_bf16x2(lo.z, lo.w),
                                         pack_bf16x2(hi.x, hi.y), pack_bf16x2(hi.z, hi.w));
     }
@@ -156,12 +161,6 @@ __device__ __forceinline__ void compute_stage(const char* buf, f32x4 (&acc)[4][4
 
 __device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
 
-// ST(u, th) = sign(u) max(|u| - th, 0) (Section 1, after Eq. (2)).
-__device__ __forceinline__ float soft_thresh(float u, float th) {
-  const float au = fabsf(u) - th;
-  return au > 0.f ? copysignf(au, u) : 0.f;
-}
-
 // One output tile of a fused contraction (the tile index already mapped).
 template <int P, int EPI, bool SAFE>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tile, char* smem) {
@@ -171,30 +170,44 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tile, char* sme
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 15, lg = lane >> 4;
 
+  const float a = (EPI == kEpiCorr) ? 0.f : g.alpha ? g.alpha[g.t] : 0.f;
+  // The BF16 forward layer folds the step into the operand, as the
+  // persistent kernels do: A = BF16(-a z^t), the accumulators start from z^t
+  // (so they end as z^t - a G z^t), and the epilogue adds a c.
+  constexpr bool FOLD = EPI == kEpiFwd && P == kBF16;
   f32x4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (FOLD) {
+        const int col = col0 + wn * 64 + j * 16 + lr;
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+          const int row = row0 + wm * 64 + i * 16 + 4 * lg + r4;
+          if (row < g.rows && col < g.ncols) acc[i][j][r4] = g.Zt[(size_t)row * g.ldz + col];
+        }
+      }
+    }
 
   constexpr int KS = KStep<P>::KS;
   const int nk = (g.K + KS - 1) / KS;
   StageRegs<P> st;
   load_stage<P, SAFE>(st, g, row0, col0, 0, tid);
-  store_stage<P>(st, smem, tid);
+  store_stage<P, FOLD>(st, smem, tid, -a);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const bool more = kt + 1 < nk;
     if (more) load_stage<P, SAFE>(st, g, row0, col0, (kt + 1) * KS, tid);
     compute_stage<P>(smem + (kt & 1) * STAGE_BYTES, acc, wm, wn, lr, lg);
-    if (more) store_stage<P>(st, smem + ((kt + 1) & 1) * STAGE_BYTES, tid);
+    if (more) store_stage<P, FOLD>(st, smem + ((kt + 1) & 1) * STAGE_BYTES, tid, -a);
     __syncthreads();
   }
 
   // ------------------------------------------------------------ epilogue
-  const float a = (EPI == kEpiCorr) ? 0.f : g.alpha ? g.alpha[g.t] : 0.f;
   const float lam = g.lam;
-  const float th = lam * a;
+  const float th = uniform_f32(lam * a);
   const float bt = (EPI == kEpiFista) ? g.beta[g.t] : 0.f;
   const float lth = (EPI == kEpiLista) ? lam * g.beta[g.t] : 0.f;  // LISTA threshold lam beta_t
   double fs[4][4];
@@ -225,7 +238,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tile, char* sme
           g.Out[idx] = r;
           if (g.fpart) fs[fm][r4] += 0.5 * (double)r * (double)r;
         } else if constexpr (EPI == kEpiLista) {
-          const float zn = soft_thresh(g.Zt[idx] - a * p, lth);
+          const float zn = soft_threshold(g.Zt[idx] - a * p, lth);
           g.Out[idx] = zn;
           if (g.fpart) fs[fm][r4] += (double)lam * fabs((double)zn);
         } else if constexpr (EPI == kEpiListaQ) {
@@ -237,8 +250,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tile, char* sme
           g.Out[idx] = (zt != 0.f) ? v - a * p : 0.f;
         } else if constexpr (EPI == kEpiFwd) {
           const float z = g.Zt[idx], c = g.C[idx];
-          g.Out[idx] = soft_thresh(z - a * (p - c), th);
-          if (g.fpart) fs[fm][r4] += (double)(0.5f * z * p - z * c + lam * fabsf(z));
+          if constexpr (FOLD) {
+            // p = z - a G z
+            g.Out[idx] = soft_threshold(fmaf(a, c, p), th);
+            if (g.fpart) fs[fm][r4] += (double)(0.5f * z * ((z - p) / a) - z * c + lam * fabsf(z));
+          } else {
+            g.Out[idx] = soft_threshold(z - a * (p - c), th);
+            if (g.fpart) fs[fm][r4] += (double)(0.5f * z * p - z * c + lam * fabsf(z));
+          }
         } else if constexpr (EPI == kEpiFinal) {
           const float z = g.Zt[idx], c = g.C[idx];
           fs[fm][r4] += (double)(0.5f * z * p - z * c + lam * fabsf(z));
@@ -255,7 +274,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tile, char* sme
         } else if constexpr (EPI == kEpiFista) {
           // A = y^t (Zt: its FP32 copy), Zt1 = z^t
           const float y = g.Zt[idx], zo = g.Zt1[idx], c = g.C[idx];
-          const float zn = soft_thresh(y - a * (p - c), th);
+          const float zn = soft_threshold(y - a * (p - c), th);
           g.Out[idx] = zn;
           g.Out2[idx] = zn + bt * (zn - zo);
         } else {  // kEpiBwd

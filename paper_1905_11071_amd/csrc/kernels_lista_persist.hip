@@ -50,10 +50,6 @@ template <> struct LElem<kBF16> { static constexpr int bytes = 2; };
 
 __device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
 
-__device__ __forceinline__ float soft_thresh(float u, float th) {
-  const float au = fabsf(u) - th;
-  return au > 0.f ? copysignf(au, u) : 0.f;
-}
 
 // Store one element into an operand tile in LDS (FP32, or BF16 rounded to nearest even).
 template <int P>
@@ -283,7 +279,7 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
                 z = *(const float*)(zA + row * zrowb + col * 4);
               else
                 z = zM[row * m_pad + col];
-              const float zn = soft_thresh(z - al * acc[g][rb][r4], th);
+              const float zn = soft_threshold(z - al * acc[g][rb][r4], th);
               if constexpr (P != kF32) zM[row * m_pad + col] = zn;
               put_op<P>(zA, zrowb, row, col, zn);
               word |= (uint32_t)((z != 0.f ? 1u : 0u) | (zn > 0.f ? 2u : 0u) | (zn < 0.f ? 4u : 0u)) << (8 * r4);

@@ -159,10 +159,10 @@ __global__ void k_layer0(const float4* __restrict__ C, size_t n4, const float* _
     const float4 c = C[i];
     float4 z;
     float u;
-    u = 0.f - a * (0.f - c.x); z.x = fabsf(u) - th > 0.f ? copysignf(fabsf(u) - th, u) : 0.f;
-    u = 0.f - a * (0.f - c.y); z.y = fabsf(u) - th > 0.f ? copysignf(fabsf(u) - th, u) : 0.f;
-    u = 0.f - a * (0.f - c.z); z.z = fabsf(u) - th > 0.f ? copysignf(fabsf(u) - th, u) : 0.f;
-    u = 0.f - a * (0.f - c.w); z.w = fabsf(u) - th > 0.f ? copysignf(fabsf(u) - th, u) : 0.f;
+    u = 0.f - a * (0.f - c.x); z.x = soft_threshold(u, th);
+    u = 0.f - a * (0.f - c.y); z.y = soft_threshold(u, th);
+    u = 0.f - a * (0.f - c.z); z.z = soft_threshold(u, th);
+    u = 0.f - a * (0.f - c.w); z.w = soft_threshold(u, th);
     Z1[i] = z;
   }
 }
@@ -492,7 +492,7 @@ __global__ void k_oista_update(const float* __restrict__ Z, const float* __restr
     for (int ct = 0; ct < col_tiles; ++ct) viol += flags[(size_t)ct * N + i];
     const float a = viol == 0.0 ? step[i] : (float)(1.0 / L);
     const float u = Z[e] - a * R[e], th = lam * a;
-    Zout[e] = fabsf(u) - th > 0.f ? copysignf(fabsf(u) - th, u) : 0.f;
+    Zout[e] = soft_threshold(u, th);
     if (steps_used && e == (size_t)i * mp) steps_used[i] = a;
   }
 }

@@ -40,10 +40,6 @@ template <> struct Elem<kBF16> { static constexpr int bytes = 2; };
 template <int P>
 __host__ __device__ constexpr int tile_rowb(int m_pad) { return m_pad * Elem<P>::bytes + 32; }
 
-__device__ __forceinline__ float soft_thresh(float u, float th) {
-  const float au = fabsf(u) - th;
-  return au > 0.f ? copysignf(au, u) : 0.f;
-}
 __device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
 
 // Raw buffer descriptors (CDNA): a uniform base and byte range in SGPRs, so
@@ -174,8 +170,9 @@ struct KSteps<P, FM, FB, PF, U, U> {
 
 // acc[fm][f] = sum_k A[16 fm + row][k] G[k][16 FB slab + 16 f + col] over
 // the whole K range, A from the LDS tile, G fragments from global memory
-// issued PF - 1 K steps ahead (PF = 2, 3 or 4).
-template <int P, int FM, int FB, int PF>
+// issued PF - 1 K steps ahead (PF = 2, 3 or 4). KEEP: the sums start from
+// the values acc already holds instead of 0.
+template <int P, int FM, int FB, int PF, bool KEEP = false>
 __device__ __forceinline__ void contract(const PersistArgs& g, const char* lds, int rowb, int slab, int lane,
                                          f32x4 (&acc)[FM][FB]) {
   const int lr = lane & 15, lg = lane >> 4;
@@ -183,10 +180,12 @@ __device__ __forceinline__ void contract(const PersistArgs& g, const char* lds, 
   // the FB * KC fragments of this slab: FB KC KiB starting at fragment (FB slab, 0)
   const Rsrc rg = make_rsrc((const char*)g.Gsw + (size_t)(FB * slab) * KC * 1024, (size_t)FB * KC * 1024);
   const int lo = lane * 16;
+  if constexpr (!KEEP) {
 #pragma unroll
-  for (int fm = 0; fm < FM; ++fm)
+    for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
-    for (int f = 0; f < FB; ++f) acc[fm][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int f = 0; f < FB; ++f) acc[fm][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
   uint4 bq[PF][FB];
 #pragma unroll
   for (int i = 0; i < PF - 1; ++i)
@@ -206,10 +205,13 @@ __device__ __forceinline__ void contract(const PersistArgs& g, const char* lds, 
   if (KF < KC) KSteps<P, FM, FB, PF, 0, U>::tail(rg, lo, KC, arow, rowb, KF, bq, av, acc);
 }
 
-// Master registers -> LDS tile (the next contraction's A operand).
-template <int P, int FM, int FB, int NP, int WC>
-__device__ __forceinline__ void master_to_lds(const float (&zm)[NP][FM][FB][4], char* lds, int rowb, int npass,
-                                              int m_pad, int wave, int lane) {
+// Master registers -> LDS tile (the next contraction's A operand). BF16
+// tiles take sc z rounded to BF16 (sc = -alpha_t where the step is folded
+// into the operand, else 1); FP32 tiles take z itself. zm: float[4] or
+// f32x4 elements, [NP][FM][FB].
+template <int P, int FM, int FB, int NP, int WC, typename M>
+__device__ __forceinline__ void master_to_lds(const M& zm, char* lds, int rowb, int npass, int m_pad, int wave,
+                                              int lane, float sc = 1.f) {
   const int lr = lane & 15, lg = lane >> 4;
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
@@ -218,16 +220,23 @@ __device__ __forceinline__ void master_to_lds(const float (&zm)[NP][FM][FB][4], 
 #pragma unroll
       for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
-        for (int f = 0; f < FB; ++f)
+        for (int f = 0; f < FB; ++f) {
+          const int col = 16 * FB * slab + 16 * f + lr;
+          char* dst = lds + (16 * fm + 4 * lg) * rowb + col * Elem<P>::bytes;
+          if constexpr (P == kF32) {
 #pragma unroll
-          for (int r4 = 0; r4 < 4; ++r4) {
-            const int row = 16 * fm + 4 * lg + r4, col = 16 * FB * slab + 16 * f + lr;
-            char* dst = lds + row * rowb + col * Elem<P>::bytes;
-            if constexpr (P == kF32)
-              *(float*)dst = zm[p][fm][f][r4];
-            else
-              *(__bf16*)dst = (__bf16)zm[p][fm][f][r4];
+            for (int r4 = 0; r4 < 4; ++r4) *(float*)(dst + r4 * rowb) = zm[p][fm][f][r4];
+          } else {
+            // rows r4 and r4 + 1 converted by one packed instruction
+#pragma unroll
+            for (int r2 = 0; r2 < 4; r2 += 2) {
+              const f32x2 v = {sc * zm[p][fm][f][r2], sc * zm[p][fm][f][r2 + 1]};
+              const bf16x2 b = __builtin_convertvector(v, bf16x2);
+              *(__bf16*)(dst + r2 * rowb) = b[0];
+              *(__bf16*)(dst + (r2 + 1) * rowb) = b[1];
+            }
           }
+        }
     }
   }
 }
@@ -292,9 +301,9 @@ __device__ __forceinline__ void load_master(float (&zm)[NP][FM][FB][4], const fl
 // Loads this wave's FM row blocks (from row0) of a kept iterate (tape order)
 // into the master registers; 4-row groups past N read as 0 (and the rows
 // past N inside the last group hold 0 on the tape).
-template <int FM, int FB, int NP, int WC>
-__device__ __forceinline__ void load_master_tape(float (&zm)[NP][FM][FB][4], const float* src, int row0, int N,
-                                                 int m_pad, int npass, int wave, int lane) {
+template <int FM, int FB, int NP, int WC, typename M>
+__device__ __forceinline__ void load_master_tape(M& zm, const float* src, int row0, int N, int m_pad, int npass,
+                                                 int wave, int lane) {
   const int lr = lane & 15, lg = lane >> 4;
   constexpr int R = FM * 16;
   const int nrows = (N - row0) < R ? (N - row0) : R;
@@ -320,149 +329,190 @@ __device__ __forceinline__ void load_master_tape(float (&zm)[NP][FM][FB][4], con
   }
 }
 
-// Forward over layers [t_begin, t_end): z^(t+1) = ST(z^t - a_t (G z^t - c), lam a_t),
-// keeping the tape; with TRACE also F(z^t) for each t. Then, if asked, one
-// more contraction G z^(t_end) for F(z^(t_end)) and the backward seed.
-// FISTA: the tile also carries y^t (FISTA's extrapolated point) in
-// registers; the contraction is G y^t, the epilogue z^{t+1} = ST(y^t -
-// alpha_t (G y^t - c), lam alpha_t), y^{t+1} = z^{t+1} + beta_t (z^{t+1} - z^t)
-// (the per-layer FISTA epilogue's expressions), and the LDS tile holds y;
-// the final contraction for F takes z^T. No tape, no trace.
-template <int P, int R, int NP, bool TRACE, int PF, int WR, int WC, bool FISTA = false>
-__device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* lds) {
-  static_assert(!(FISTA && TRACE), "FISTA runs without the objective trace");
-  constexpr int FM = R / (16 * WR);  // 16-row blocks per wave
-  constexpr int FB = 16 / WC;        // 16-column blocks per wave and pass
+// z^T of this wave's rows (from row0, in the master layout) into the caller's
+// [N][m] buffer: rows below N, columns below m.
+template <int FM, int FB, int NP, int WC, typename M>
+__device__ __forceinline__ void store_user(const M& zm, const PersistArgs& g, int row0, int wave, int lane) {
+  const int lr = lane & 15, lg = lane >> 4;
+  const int m = g.m, m_pad = g.m_pad, npass = (m_pad + 255) / 256;
+  const int nrows = (g.N - row0) < 16 * FM ? (g.N - row0) : 16 * FM;
+  const Rsrc rZu = make_rsrc(g.Zuser + (size_t)row0 * m, (size_t)nrows * m * 4);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int slab = WC * p + wave;
+    if (!(p < npass && slab * 16 * FB < m_pad)) continue;
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) {
+        const int row = 16 * fm + 4 * lg + r4;
+        if (row >= nrows) continue;
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+          const int col = 16 * FB * slab + 16 * f + lr;
+          if (col < m) bstore(zm[p][fm][f][r4], rZu, (row * m + col) * 4, 0);
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward layers with the step folded into the A operand (BF16 tiles).
+//
+// The LDS tile holds BF16(-alpha_t z^t) and the accumulators start from the
+// FP32 master z^t, so one contraction leaves z^t - alpha_t G z^t in them and
+// the epilogue only adds alpha_t c before the threshold:
+//   z^{t+1} = ST(acc + alpha_t c, lam alpha_t),  acc = z^t + G BF16(-alpha_t z^t).
+// This is the layer of Eq. (14) with the product alpha_t (G z^t) formed
+// from the BF16 operand -alpha_t z^t rather than from alpha_t times G BF16(z^t):
+// the operand's rounding (2^-9 relative) dominates either way. Without the
+// objective trace the accumulators are the master iterate itself, so a wave
+// can hold the accumulators of all its column passes at once and run them
+// in one contraction that reads each A fragment from LDS once per K step
+// instead of once per pass and K step.
+
+// Column passes of this wave (a prefix of 0 .. NP-1): pass p is active while
+// p < npass and its slab starts below m_pad.
+template <int FB, int NP, int WC>
+__device__ __forceinline__ int wave_passes(int m_pad, int wave) {
+  const int npass = (m_pad + 255) / 256;
+  int na = 0;
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+    if (p < npass && (WC * p + wave) * 16 * FB < m_pad) na = p + 1;
+  return na;
+}
+
+// One K step over passes P0 .. P0 + NA - 1: prefetch the G fragments of step
+// kc + PF - 1 and the A fragments of step kc + 1 (clamped to the last step),
+// then NA FM FB MFMAs into the master accumulators. goff[q]: byte offset of
+// pass q's first fragment (a pass past the wave's last active one reads the
+// last active pass's fragments: valid memory, and its accumulators are not
+// used).
+template <int FM, int FB, int NP, int P0, int NA, int PF, int J>
+__device__ __forceinline__ void kf_step(const Rsrc& rg, const int (&goff)[NA], int lo, int KC, const char* arow,
+                                        int rowb, int kc, uint4 (&bq)[PF][NA][FB], uint4 (&av)[2][FM],
+                                        f32x4 (&am)[NP][FM][FB]) {
+  const int nk = min(kc + PF - 1, KC - 1);
+#pragma unroll
+  for (int q = 0; q < NA; ++q)
+#pragma unroll
+    for (int f = 0; f < FB; ++f)
+      bq[(J + PF - 1) % PF][q][f] = __builtin_bit_cast(
+          uint4, __builtin_amdgcn_raw_buffer_load_b128(rg, lo, goff[q] + (f * KC + nk) * 1024, 0));
+  const int na = min(kc + 1, KC - 1);
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm) av[(J & 1) ^ 1][fm] = *(const uint4*)(arow + fm * 16 * rowb + na * 64);
+#pragma unroll
+  for (int q = 0; q < NA; ++q)
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int f = 0; f < FB; ++f)
+        am[P0 + q][fm][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[J & 1][fm]),
+                                                                    __builtin_bit_cast(bf16x8, bq[J % PF][q][f]),
+                                                                    am[P0 + q][fm][f], 0, 0, 0);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int FM, int FB, int NP, int P0, int NA, int PF, int J, int U>
+struct KFSteps {
+  static __device__ __forceinline__ void run(const Rsrc& rg, const int (&goff)[NA], int lo, int KC, const char* arow,
+                                             int rowb, int kc0, uint4 (&bq)[PF][NA][FB], uint4 (&av)[2][FM],
+                                             f32x4 (&am)[NP][FM][FB]) {
+    kf_step<FM, FB, NP, P0, NA, PF, J>(rg, goff, lo, KC, arow, rowb, kc0 + J, bq, av, am);
+    KFSteps<FM, FB, NP, P0, NA, PF, J + 1, U>::run(rg, goff, lo, KC, arow, rowb, kc0, bq, av, am);
+  }
+  static __device__ __forceinline__ void tail(const Rsrc& rg, const int (&goff)[NA], int lo, int KC,
+                                              const char* arow, int rowb, int kc0, uint4 (&bq)[PF][NA][FB],
+                                              uint4 (&av)[2][FM], f32x4 (&am)[NP][FM][FB]) {
+    if (kc0 + J < KC) {
+      kf_step<FM, FB, NP, P0, NA, PF, J>(rg, goff, lo, KC, arow, rowb, kc0 + J, bq, av, am);
+      KFSteps<FM, FB, NP, P0, NA, PF, J + 1, U>::tail(rg, goff, lo, KC, arow, rowb, kc0, bq, av, am);
+    }
+  }
+};
+template <int FM, int FB, int NP, int P0, int NA, int PF, int U>
+struct KFSteps<FM, FB, NP, P0, NA, PF, U, U> {
+  static __device__ __forceinline__ void run(const Rsrc&, const int (&)[NA], int, int, const char*, int, int,
+                                             uint4 (&)[PF][NA][FB], uint4 (&)[2][FM], f32x4 (&)[NP][FM][FB]) {}
+  static __device__ __forceinline__ void tail(const Rsrc&, const int (&)[NA], int, int, const char*, int, int,
+                                              uint4 (&)[PF][NA][FB], uint4 (&)[2][FM], f32x4 (&)[NP][FM][FB]) {}
+};
+
+// am[p] += A G_slab(p) for the passes p = P0 .. P0 + NA - 1 of this wave,
+// over the whole K range; na (>= 1, wave-uniform) of them are active. The
+// fragments of slab WC p + wave are (FB (WC p + wave) + f, kc), 1 KiB each
+// at (FB (WC p + wave) + f) KC + kc KiB.
+template <int FM, int FB, int NP, int WC, int P0, int NA, int PF>
+__device__ __forceinline__ void contract_fused(const PersistArgs& g, const char* lds, int rowb, int wave, int lane,
+                                               int na, f32x4 (&am)[NP][FM][FB]) {
+  const int lr = lane & 15, lg = lane >> 4;
+  const int KC = g.KC;
+  const Rsrc rg = make_rsrc((const char*)g.Gsw + (size_t)(FB * (WC * P0 + wave)) * KC * 1024,
+                            (size_t)(WC * FB * (na - 1) + FB) * KC * 1024);
+  int goff[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) goff[q] = (q < na ? q : na - 1) * WC * FB * KC * 1024;
+  const int lo = lane * 16;
+  uint4 bq[PF][NA][FB];
+#pragma unroll
+  for (int i = 0; i < PF - 1; ++i)
+#pragma unroll
+    for (int q = 0; q < NA; ++q)
+#pragma unroll
+      for (int f = 0; f < FB; ++f)
+        bq[i][q][f] = __builtin_bit_cast(
+            uint4, __builtin_amdgcn_raw_buffer_load_b128(rg, lo, goff[q] + (f * KC + min(i, KC - 1)) * 1024, 0));
+  const char* arow = lds + lr * rowb + 16 * lg;
+  uint4 av[2][FM];
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm) av[0][fm] = *(const uint4*)(arow + fm * 16 * rowb);
+  // U steps per iteration, a multiple of PF and of 2 (step kc uses bq[kc % PF], av[kc & 1])
+  constexpr int U = PF == 3 ? 6 : (PF == 4 ? 4 : 2);
+  const int KF = KC - KC % U;
+  for (int kc0 = 0; kc0 < KF; kc0 += U)
+    KFSteps<FM, FB, NP, P0, NA, PF, 0, U>::run(rg, goff, lo, KC, arow, rowb, kc0, bq, av, am);
+  if (KF < KC) KFSteps<FM, FB, NP, P0, NA, PF, 0, U>::tail(rg, goff, lo, KC, arow, rowb, KF, bq, av, am);
+}
+
+// The passes of a wave in groups of NG (the G prefetch registers of a group,
+// PF NG FB uint4, bound NG): group P0, then P0 + NG, ...; a group with no
+// active pass is skipped.
+template <int FM, int FB, int NP, int WC, int NG, int PF, int P0>
+struct GroupLoop {
+  static __device__ __forceinline__ void run(const PersistArgs& g, const char* lds, int rowb, int wave, int lane,
+                                             int na_w, f32x4 (&am)[NP][FM][FB]) {
+    if constexpr (P0 < NP) {
+      constexpr int NA = (NP - P0) < NG ? (NP - P0) : NG;
+      if (na_w > P0) contract_fused<FM, FB, NP, WC, P0, NA, PF>(g, lds, rowb, wave, lane, na_w - P0, am);
+      GroupLoop<FM, FB, NP, WC, NG, PF, P0 + NG>::run(g, lds, rowb, wave, lane, na_w, am);
+    }
+  }
+};
+
+// After the layers of a forward launch: z^(t_end) for a launch that
+// continues the network, then, if asked, one more contraction G z^(t_end)
+// for F(z^(t_end)) and the backward seed. The LDS tile holds z^(t_end) in
+// the contraction's precision (unscaled); zm: float[4] or f32x4 elements.
+template <int P, int R, int NP, int PF, int WR, int WC, typename M>
+__device__ __forceinline__ void fwd_tail(const PersistArgs& g, int tile, char* lds, const M& zm) {
+  constexpr int FM = R / (16 * WR);
+  constexpr int FB = 16 / WC;
   const int tid = threadIdx.x, lane = tid & 63;
-  // wave-uniform, and known to be: descriptors built from it stay in SGPRs
   const unsigned wid = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wave = (int)(wid % WC);              // column wave: slab WC p + wave of pass p
-  const int rbase = (int)(wid / WC) * 16 * FM;   // first tile row of this wave
+  const int wave = (int)(wid % WC);
+  const int rbase = (int)(wid / WC) * 16 * FM;
   const int lr = lane & 15, lg = lane >> 4;
   const int row0 = tile * R;
   const int m_pad = g.m_pad, N = g.N, m = g.m;
   const int rowb = tile_rowb<P>(m_pad);
   const int npass = (m_pad + 255) / 256;
   const int nrows = (N - row0) < R ? (N - row0) : R;
-  const int rstride = m_pad * 4;      // bytes per row of the [N][m_pad] buffers
-  const int ustride = m * 4;          // bytes per row of the caller's [N][m] buffers
+  const int rstride = m_pad * 4;
+  const int ustride = m * 4;
   float* red = (float*)(lds + R * rowb);
   const Rsrc rCg = make_rsrc(g.Cg + (size_t)row0 * m_pad, tape_bytes(nrows, m_pad));
-  const Rsrc rZu = make_rsrc(g.Zuser ? g.Zuser + (size_t)row0 * m : nullptr, g.Zuser ? (size_t)nrows * ustride : 0);
-
-  float zm[NP][FM][FB][4];
-  float ym[FISTA ? NP : 1][FM][FB][4];  // FISTA's y^t (z^0 = y^0 = 0; t_begin = 0)
-  if constexpr (FISTA) {
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int f = 0; f < FB; ++f)
-#pragma unroll
-          for (int r4 = 0; r4 < 4; ++r4) ym[p][fm][f][r4] = 0.f;
-  }
-  if (g.t_begin == 0) {
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int f = 0; f < FB; ++f)
-#pragma unroll
-          for (int r4 = 0; r4 < 4; ++r4) zm[p][fm][f][r4] = 0.f;
-  } else {
-    load_master_tape<FM, FB, NP, WC>(zm, g.zload ? g.zload : slot_ptr(g, g.t_begin), row0 + rbase, N, m_pad, npass,
-                                     wave, lane);
-  }
-  master_to_lds<P, FM, FB, NP, WC>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
-  __syncthreads();
-
-  for (int t = g.t_begin; t < g.t_end; ++t) {
-    const float a = g.alpha[t];
-    const float lam = g.lam, th = lam * a;
-    const float bt = FISTA ? g.beta[t] : 0.f;
-    const bool store = g.k > 0 && (g.store_all || (t + 1) % g.k == 0 || t + 1 == g.T || t + 1 > g.a_last);
-    const Rsrc rD = make_rsrc(store ? slot_ptr(g, t + 1) + (size_t)row0 * m_pad : nullptr,
-                              store ? tape_bytes(nrows, m_pad) : 0);
-    const bool copy_out = (t + 1 == g.T) && g.Zuser;
-    float fs[FM][4];
-    if constexpr (TRACE) {
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) fs[fm][r4] = 0.f;
-    }
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const int slab = WC * p + wave;
-      if (!(p < npass && slab * 16 * FB < m_pad)) continue;
-      f32x4 acc[FM][FB];
-      if (t > 0) {
-        contract<P, FM, FB, PF>(g, lds + rbase * rowb, rowb, slab, lane, acc);
-      } else {
-#pragma unroll
-        for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-          for (int f = 0; f < FB; ++f) acc[fm][f] = f32x4{0.f, 0.f, 0.f, 0.f};
-      }
-      const int colb = 16 * FB * slab + lr;            // column of block f = 0
-      const int lou = (4 * lg * m + colb) * 4;         // per-lane offset, [N][m] buffers
-      const int lt = (lg * m_pad + colb) * 16;         // per-lane offset, tape order
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm) {
-        // c of this lane's four rows, one 16-byte load per column block;
-        // rows past N keep z = 0 (their c is stored as 0, and G z is 0)
-        const bool grp = rbase + 16 * fm + 4 * lg < nrows;
-        float cg[FB][4];
-#pragma unroll
-        for (int f = 0; f < FB; ++f) {
-          const float4 q = grp ? bload4(rCg, lt + 256 * f, (rbase + 16 * fm) * rstride) : make_float4(0.f, 0.f, 0.f, 0.f);
-          cg[f][0] = q.x;
-          cg[f][1] = q.y;
-          cg[f][2] = q.z;
-          cg[f][3] = q.w;
-        }
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          if (rbase + 16 * fm + 4 * lg + r4 >= nrows) continue;
-          const int sou = (rbase + 16 * fm + r4) * ustride;
-#pragma unroll
-          for (int f = 0; f < FB; ++f) {
-            const float z = zm[p][fm][f][r4];
-            const float c = cg[f][r4];
-            const float pv = acc[fm][f][r4];
-            if constexpr (TRACE) fs[fm][r4] += 0.5f * z * pv - z * c + lam * fabsf(z);
-            float zn;
-            if constexpr (FISTA) {
-              const float y = ym[p][fm][f][r4];
-              zn = soft_thresh(y - a * (pv - c), th);
-              ym[p][fm][f][r4] = zn + bt * (zn - z);
-            } else {
-              zn = soft_thresh(z - a * (pv - c), th);
-            }
-            zm[p][fm][f][r4] = zn;
-            if (copy_out && colb + 16 * f < m) bstore(zn, rZu, lou + 64 * f, sou);
-          }
-        }
-        if (store && rbase + 16 * fm + 4 * lg < nrows) {
-#pragma unroll
-          for (int f = 0; f < FB; ++f)
-            bstore4(make_float4(zm[p][fm][f][0], zm[p][fm][f][1], zm[p][fm][f][2], zm[p][fm][f][3]), rD,
-                    lt + 256 * f, (rbase + 16 * fm) * rstride);
-        }
-      }
-    }
-    if constexpr (TRACE)
-      finish_rows<FM, R, WC>(fs, red, wave, rbase, lane, tid, row0, N, g.xsq, g.Ftrace + (size_t)t * N, nullptr);
-    __syncthreads();
-    if constexpr (FISTA)
-      master_to_lds<P, FM, FB, NP, WC>(ym, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
-    else
-      master_to_lds<P, FM, FB, NP, WC>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
-    __syncthreads();
-  }
-
   if (g.zsave) {
     // z^(t_end) for a launch that continues the network (tape order)
     const Rsrc rS = make_rsrc(g.zsave + (size_t)row0 * m_pad, tape_bytes(nrows, m_pad));
@@ -482,11 +532,6 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
     }
   }
   if (!(g.mode & (kModeF | kModeSeed))) return;
-  if constexpr (FISTA) {
-    // the LDS tile holds y^T; F takes z^T (every wave is past the last barrier)
-    master_to_lds<P, FM, FB, NP, WC>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
-    __syncthreads();
-  }
   // final contraction: F(z^(t_end)) and / or the seed of the backward pass
   const bool want_f = (g.mode & kModeF) != 0;
   const bool seed = (g.mode & kModeSeed) != 0;
@@ -543,6 +588,278 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
   }
   if (want_f) finish_rows<FM, R, WC>(fs, red, wave, rbase, lane, tid, row0, N, g.xsq, g.F, g.Fd);
 }
+
+// Forward layers [t_begin, t_end) of a BF16 tile without the objective
+// trace: the folded layer above, all column passes of a wave in groups of
+// NG per contraction (NG FB <= 8 keeps the prefetched G fragments at 32
+// registers per stage), G fragments one K step ahead.
+template <int P, int R, int NP, int PF, int WR, int WC>
+__device__ __forceinline__ void fwd_body_fused(const PersistArgs& g, int tile, char* lds) {
+  static_assert(P == kBF16, "the folded layer runs on BF16 tiles");
+  constexpr int FM = R / (16 * WR);
+  constexpr int FB = 16 / WC;
+  constexpr int NG = (8 / FB) < NP ? (8 / FB) : NP;
+  constexpr int PFF = 2;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const unsigned wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wave = (int)(wid % WC);
+  const int rbase = (int)(wid / WC) * 16 * FM;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int row0 = tile * R;
+  const int m_pad = g.m_pad, N = g.N, m = g.m;
+  const int rowb = tile_rowb<P>(m_pad);
+  const int npass = (m_pad + 255) / 256;
+  const int nrows = (N - row0) < R ? (N - row0) : R;
+  const int rstride = m_pad * 4;
+  const int ustride = m * 4;
+  const int na_w = wave_passes<FB, NP, WC>(m_pad, wave);
+  const Rsrc rCg = make_rsrc(g.Cg + (size_t)row0 * m_pad, tape_bytes(nrows, m_pad));
+
+  f32x4 am[NP][FM][FB];  // the master iterate, and the contraction's accumulators
+  if (g.t_begin == 0) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int f = 0; f < FB; ++f) am[p][fm][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+  } else {
+    load_master_tape<FM, FB, NP, WC>(am, g.zload ? g.zload : slot_ptr(g, g.t_begin), row0 + rbase, N, m_pad, npass,
+                                     wave, lane);
+  }
+  master_to_lds<P, FM, FB, NP, WC>(am, lds + rbase * rowb, rowb, npass, m_pad, wave, lane,
+                                   g.t_begin < g.t_end ? -g.alpha[g.t_begin] : 1.f);
+  __syncthreads();
+
+  for (int t = g.t_begin; t < g.t_end; ++t) {
+    const float a = g.alpha[t];
+    const float th = uniform_f32(g.lam * a);
+    const bool store = g.k > 0 && (g.store_all || (t + 1) % g.k == 0 || t + 1 == g.T || t + 1 > g.a_last);
+    const Rsrc rD = make_rsrc(store ? slot_ptr(g, t + 1) + (size_t)row0 * m_pad : nullptr,
+                              store ? tape_bytes(nrows, m_pad) : 0);
+    // z^0 = 0: layer 0 has nothing to contract
+    if (t > 0) GroupLoop<FM, FB, NP, WC, NG, PFF, 0>::run(g, lds + rbase * rowb, rowb, wave, lane, na_w, am);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      if (p >= na_w) {
+        // a pass past the wave's last one: its accumulators took other fragments
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+          for (int f = 0; f < FB; ++f) am[p][fm][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+        continue;
+      }
+      const int colb = 16 * FB * (WC * p + wave) + lr;  // column of block f = 0
+      const int lt = (lg * m_pad + colb) * 16;           // per-lane offset, tape order
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm) {
+        // rows past N keep z = 0 (their c is stored as 0, and G z is 0)
+        const bool grp = rbase + 16 * fm + 4 * lg < nrows;
+        float cg[FB][4];
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+          const float4 q = grp ? bload4(rCg, lt + 256 * f, (rbase + 16 * fm) * rstride) : make_float4(0.f, 0.f, 0.f, 0.f);
+          cg[f][0] = q.x;
+          cg[f][1] = q.y;
+          cg[f][2] = q.z;
+          cg[f][3] = q.w;
+        }
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4)
+#pragma unroll
+          for (int f = 0; f < FB; ++f) am[p][fm][f][r4] = soft_threshold(fmaf(a, cg[f][r4], am[p][fm][f][r4]), th);
+        if (store && grp) {
+#pragma unroll
+          for (int f = 0; f < FB; ++f)
+            bstore4(make_float4(am[p][fm][f][0], am[p][fm][f][1], am[p][fm][f][2], am[p][fm][f][3]), rD,
+                    lt + 256 * f, (rbase + 16 * fm) * rstride);
+        }
+      }
+    }
+    __syncthreads();
+    master_to_lds<P, FM, FB, NP, WC>(am, lds + rbase * rowb, rowb, npass, m_pad, wave, lane,
+                                     t + 1 < g.t_end ? -g.alpha[t + 1] : 1.f);
+    __syncthreads();
+  }
+  if (g.Zuser && g.t_begin < g.t_end && g.t_end == g.T) store_user<FM, FB, NP, WC>(am, g, row0 + rbase, wave, lane);
+  fwd_tail<P, R, NP, PF, WR, WC>(g, tile, lds, am);
+}
+
+// Forward over layers [t_begin, t_end): z^(t+1) = ST(z^t - a_t (G z^t - c), lam a_t),
+// keeping the tape; with TRACE also F(z^t) for each t. Then fwd_tail. One
+// contraction per column pass, the master iterate in its own registers;
+// BF16 tiles without the trace run fwd_body_fused instead.
+// FISTA: the tile also carries y^t (FISTA's extrapolated point) in
+// registers; the contraction is G y^t, the epilogue z^{t+1} = ST(y^t -
+// alpha_t (G y^t - c), lam alpha_t), y^{t+1} = z^{t+1} + beta_t (z^{t+1} - z^t)
+// (the per-layer FISTA epilogue's expressions), and the LDS tile holds y;
+// the final contraction for F takes z^T. No tape, no trace.
+template <int P, int R, int NP, bool TRACE, int PF, int WR, int WC, bool FISTA = false>
+__device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* lds) {
+  static_assert(!(FISTA && TRACE), "FISTA runs without the objective trace");
+  // the fused layer loop where its accumulators (the whole master) fit in
+  // 128 registers per lane next to the operands of a K step
+  if constexpr (P == kBF16 && !TRACE && !FISTA && NP * (R / (16 * WR)) * (16 / WC) * 4 <= 128) {
+    fwd_body_fused<P, R, NP, PF, WR, WC>(g, tile, lds);
+    return;
+  } else {
+  // BF16 Step-LISTA / ISTA layers use the folded form (see fwd_body_fused);
+  // FP32 layers and FISTA form z - alpha_t (P - c) from P = G z.
+  constexpr bool FOLD = P == kBF16 && !FISTA;
+  constexpr int FM = R / (16 * WR);  // 16-row blocks per wave
+  constexpr int FB = 16 / WC;        // 16-column blocks per wave and pass
+  const int tid = threadIdx.x, lane = tid & 63;
+  // wave-uniform, and known to be: descriptors built from it stay in SGPRs
+  const unsigned wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wave = (int)(wid % WC);              // column wave: slab WC p + wave of pass p
+  const int rbase = (int)(wid / WC) * 16 * FM;   // first tile row of this wave
+  const int lr = lane & 15, lg = lane >> 4;
+  const int row0 = tile * R;
+  const int m_pad = g.m_pad, N = g.N, m = g.m;
+  const int rowb = tile_rowb<P>(m_pad);
+  const int npass = (m_pad + 255) / 256;
+  const int nrows = (N - row0) < R ? (N - row0) : R;
+  const int rstride = m_pad * 4;      // bytes per row of the [N][m_pad] buffers
+  const int ustride = m * 4;          // bytes per row of the caller's [N][m] buffers
+  float* red = (float*)(lds + R * rowb);
+  const Rsrc rCg = make_rsrc(g.Cg + (size_t)row0 * m_pad, tape_bytes(nrows, m_pad));
+
+  float zm[NP][FM][FB][4];
+  float ym[FISTA ? NP : 1][FM][FB][4];  // FISTA's y^t (z^0 = y^0 = 0; t_begin = 0)
+  if constexpr (FISTA) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int f = 0; f < FB; ++f)
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) ym[p][fm][f][r4] = 0.f;
+  }
+  if (g.t_begin == 0) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int f = 0; f < FB; ++f)
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) zm[p][fm][f][r4] = 0.f;
+  } else {
+    load_master_tape<FM, FB, NP, WC>(zm, g.zload ? g.zload : slot_ptr(g, g.t_begin), row0 + rbase, N, m_pad, npass,
+                                     wave, lane);
+  }
+  master_to_lds<P, FM, FB, NP, WC>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane,
+                                   FOLD && g.t_begin < g.t_end ? -g.alpha[g.t_begin] : 1.f);
+  __syncthreads();
+
+  for (int t = g.t_begin; t < g.t_end; ++t) {
+    const float a = g.alpha[t];
+    const float lam = g.lam, th = uniform_f32(lam * a);
+    const float bt = FISTA ? g.beta[t] : 0.f;
+    const bool store = g.k > 0 && (g.store_all || (t + 1) % g.k == 0 || t + 1 == g.T || t + 1 > g.a_last);
+    const Rsrc rD = make_rsrc(store ? slot_ptr(g, t + 1) + (size_t)row0 * m_pad : nullptr,
+                              store ? tape_bytes(nrows, m_pad) : 0);
+    float fs[FM][4];
+    if constexpr (TRACE) {
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) fs[fm][r4] = 0.f;
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int slab = WC * p + wave;
+      if (!(p < npass && slab * 16 * FB < m_pad)) continue;
+      f32x4 acc[FM][FB];
+      if constexpr (FOLD) {
+        // the accumulators start from z^t
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+          for (int f = 0; f < FB; ++f)
+            acc[fm][f] = f32x4{zm[p][fm][f][0], zm[p][fm][f][1], zm[p][fm][f][2], zm[p][fm][f][3]};
+        if (t > 0) contract<P, FM, FB, PF, true>(g, lds + rbase * rowb, rowb, slab, lane, acc);
+      } else if (t > 0) {
+        contract<P, FM, FB, PF>(g, lds + rbase * rowb, rowb, slab, lane, acc);
+      } else {
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+          for (int f = 0; f < FB; ++f) acc[fm][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      const int colb = 16 * FB * slab + lr;            // column of block f = 0
+      const int lt = (lg * m_pad + colb) * 16;         // per-lane offset, tape order
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm) {
+        // c of this lane's four rows, one 16-byte load per column block;
+        // rows past N keep z = 0 (their c is stored as 0, and G z is 0)
+        const bool grp = rbase + 16 * fm + 4 * lg < nrows;
+        float cg[FB][4];
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+          const float4 q = grp ? bload4(rCg, lt + 256 * f, (rbase + 16 * fm) * rstride) : make_float4(0.f, 0.f, 0.f, 0.f);
+          cg[f][0] = q.x;
+          cg[f][1] = q.y;
+          cg[f][2] = q.z;
+          cg[f][3] = q.w;
+        }
+        // (rows past N: every term is 0, and their objective partials are not used)
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+#pragma unroll
+          for (int f = 0; f < FB; ++f) {
+            const float z = zm[p][fm][f][r4];
+            const float c = cg[f][r4];
+            float zn;
+            if constexpr (FOLD) {
+              // acc = z - a G z: G z = (z - acc) / a for the objective
+              const float q = acc[fm][f][r4];
+              if constexpr (TRACE) fs[fm][r4] += 0.5f * z * ((z - q) / a) - z * c + lam * fabsf(z);
+              zn = soft_threshold(fmaf(a, c, q), th);
+            } else if constexpr (FISTA) {
+              const float pv = acc[fm][f][r4];
+              const float y = ym[p][fm][f][r4];
+              zn = soft_threshold(y - a * (pv - c), th);
+              ym[p][fm][f][r4] = zn + bt * (zn - z);
+            } else {
+              const float pv = acc[fm][f][r4];
+              if constexpr (TRACE) fs[fm][r4] += 0.5f * z * pv - z * c + lam * fabsf(z);
+              zn = soft_threshold(z - a * (pv - c), th);
+            }
+            zm[p][fm][f][r4] = zn;
+          }
+        }
+        if (store && rbase + 16 * fm + 4 * lg < nrows) {
+#pragma unroll
+          for (int f = 0; f < FB; ++f)
+            bstore4(make_float4(zm[p][fm][f][0], zm[p][fm][f][1], zm[p][fm][f][2], zm[p][fm][f][3]), rD,
+                    lt + 256 * f, (rbase + 16 * fm) * rstride);
+        }
+      }
+    }
+    if constexpr (TRACE)
+      finish_rows<FM, R, WC>(fs, red, wave, rbase, lane, tid, row0, N, g.xsq, g.Ftrace + (size_t)t * N, nullptr);
+    __syncthreads();
+    if constexpr (FISTA)
+      master_to_lds<P, FM, FB, NP, WC>(ym, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
+    else
+      master_to_lds<P, FM, FB, NP, WC>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane,
+                                       FOLD && t + 1 < g.t_end ? -g.alpha[t + 1] : 1.f);
+    __syncthreads();
+  }
+  if (g.Zuser && g.t_begin < g.t_end && g.t_end == g.T) store_user<FM, FB, NP, WC>(zm, g, row0 + rbase, wave, lane);
+  if constexpr (FISTA) {
+    // the LDS tile holds y^T; F takes z^T (every wave is past the last barrier)
+    if (g.mode & (kModeF | kModeSeed)) {
+      master_to_lds<P, FM, FB, NP, WC>(zm, lds + rbase * rowb, rowb, npass, m_pad, wave, lane);
+      __syncthreads();
+    }
+  }
+  fwd_tail<P, R, NP, PF, WR, WC>(g, tile, lds, zm);
+  }
+}
+
 
 template <int P, int R, int NP, int PF, int WR, int WC>
 __device__ __forceinline__ void bwd_body(const PersistArgs& g, int tile, char* lds) {
