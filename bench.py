@@ -56,14 +56,14 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "2f9745a8fc1812b24693d3bcf41cd426d4b583660ae76d0a9933629cebdfc135",
+    "sources_sha256": "5f8f186f36c959c007727e462d93f7b67dac83f15d96db2c73edcdc394824754",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {
-        ("bf16", "forward_layer"): (8333159.625 * 2 + 13650688.875) * 1024,
-        ("bf16", "backward_layer"): (7897020.3125 * 2 + 10037.6875) * 1024,
-        ("fp32", "forward_layer"): (14733277.9375 * 2 + 13634259.875) * 1024,
-        ("fp32", "backward_layer"): (13370312.1875 * 2 + 3253.40625) * 1024,
+        ("bf16", "forward_layer"): (8452049.5 * 2 + 13632267.0625) * 1024,
+        ("bf16", "backward_layer"): (7698737.6875 * 2 + 1888.71875) * 1024,
+        ("fp32", "forward_layer"): (13337728.0625 * 2 + 13633682.125) * 1024,
+        ("fp32", "backward_layer"): (13265840.9375 * 2 + 3247.0625) * 1024,
     },
 }
 
