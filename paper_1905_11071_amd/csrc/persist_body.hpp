@@ -926,13 +926,21 @@ __device__ __forceinline__ void bwd_body(const PersistArgs& g, int tile, char* l
       if (t >= 1) contract<P, FM, FB, PF>(g, lds + rbase * rowb, rowb, slab, lane, acc);
       const int lt = (lg * m_pad + 16 * FB * slab + lr) * 16;
       if (t >= 1) {
+        // z^t of the pass, every load issued before the first is used; row
+        // groups past N read as 0 (v is 0 there too, so they add nothing)
+        float4 zq[FM][FB];
 #pragma unroll
         for (int fm = 0; fm < FM; ++fm) {
-          // rows past N: v = 0 and z^t = 0 (on the tape), so they add nothing
-          if (rbase + 16 * fm + 4 * lg >= nrows) continue;
+          const bool grp = rbase + 16 * fm + 4 * lg < nrows;
+#pragma unroll
+          for (int f = 0; f < FB; ++f)
+            zq[fm][f] = grp ? bload4(rz0, lt + 256 * f, (rbase + 16 * fm) * rstride) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm) {
 #pragma unroll
           for (int f = 0; f < FB; ++f) {
-            const float4 z4 = bload4(rz0, lt + 256 * f, (rbase + 16 * fm) * rstride);
+            const float4 z4 = zq[fm][f];
             const float zz[4] = {z4.x, z4.y, z4.z, z4.w};
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
