@@ -56,14 +56,14 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "5f8f186f36c959c007727e462d93f7b67dac83f15d96db2c73edcdc394824754",
+    "sources_sha256": "35b9ddaa7a7108ad81857b685791e5248f2bb660157744a9ab3c96c1920c81a0",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {
-        ("bf16", "forward_layer"): (8452049.5 * 2 + 13632267.0625) * 1024,
-        ("bf16", "backward_layer"): (7698737.6875 * 2 + 1888.71875) * 1024,
-        ("fp32", "forward_layer"): (13337728.0625 * 2 + 13633682.125) * 1024,
-        ("fp32", "backward_layer"): (13265840.9375 * 2 + 3247.0625) * 1024,
+        ("bf16", "forward_layer"): (8492612.1875 * 2 + 13632259.75) * 1024,
+        ("bf16", "backward_layer"): (7919832.0 * 2 + 1824.71875) * 1024,
+        ("fp32", "forward_layer"): (14408729.375 * 2 + 13633971.5625) * 1024,
+        ("fp32", "backward_layer"): (13107978.125 * 2 + 3210.90625) * 1024,
     },
 }
 
