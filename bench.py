@@ -56,7 +56,7 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "35b9ddaa7a7108ad81857b685791e5248f2bb660157744a9ab3c96c1920c81a0",
+    "sources_sha256": "6b08d7855f6f70838af26896170ef80b66837deff0902c9a52e5df95769607de",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {

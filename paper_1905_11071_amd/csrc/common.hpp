@@ -19,9 +19,9 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 // ST(u, th) = sign(u) max(|u| - th, 0) (Section 1, after Eq. (2)), written
 // as u - clamp(u, -th, th): one median-of-three and one subtraction. For
-// every finite u this is the same FP32 value as the sign / max form (both
-// round only |u| - th, and rounding to nearest is symmetric); a NaN u gives
-// NaN.
+// every finite u and th > 0 this is the same FP32 value as the sign / max
+// form (both round only |u| - th, and rounding to nearest is symmetric); a
+// NaN u gives NaN.
 __device__ __forceinline__ float soft_threshold(float u, float th) {
   return u - __builtin_amdgcn_fmed3f(u, -th, th);
 }

@@ -352,8 +352,9 @@ def test_full_size_256x1024(sl, full_prec_problem, prec):
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 # N covers every remainder mod 4 (the persistent kernels keep the tape and c
 # in four-row groups; the last group of a ragged N is part padding)
+# m = 600 (m_pad 640): the four-pass kernels with the last pass partly past m_pad
 @pytest.mark.parametrize("shape", [(50, 200, 1037, 9), (64, 256, 3000, 12), (80, 448, 515, 6), (96, 1024, 702, 7),
-                                   (40, 1100, 300, 5)])
+                                   (40, 600, 333, 5), (40, 1100, 300, 5)])
 def test_kernel_families_agree(sl, prec, shape):
     """The persistent kernels (a workgroup carries a sample tile through all
     layers; four tile variants) and the per-layer kernels use the same K
