@@ -204,9 +204,10 @@ struct Layout {
 Layout make_layout(const slista::Dict& d, int N, int T, int k, bool groups = true) {
   Layout L;
   L.k = k;
-  // N rounded up to whole 4-row groups: the persistent kernels keep the
+  // N rounded up to whole 64-row tiles: the persistent kernels keep the
   // iterates in the accumulator's row order (four rows of a column together)
-  L.zbytes = (size_t)((N + 3) / 4 * 4) * d.m_pad * sizeof(float);
+  // and load every row group of a tile unconditionally
+  L.zbytes = (size_t)slista::tape_rows(N) * d.m_pad * sizeof(float);
   const int row_tiles = (N + kTileRows - 1) / kTileRows;
   L.col_tiles = (d.m_pad + kTileCols - 1) / kTileCols;
   int P = row_tiles * L.col_tiles;
@@ -2055,7 +2056,7 @@ static int batch_upload_work(slista_batch* b, hipStream_t s) {
         e.dalpha = q.dalpha;
         small.push_back(e);
         bk.max_N = std::max(bk.max_N, q.N);
-        if (e.Cg) bk.max_group_elems = std::max(bk.max_group_elems, (size_t)(q.N + 3) / 4 * e.mp);
+        if (e.Cg) bk.max_group_elems = std::max(bk.max_group_elems, (size_t)slista::tape_rows(q.N) / 4 * e.mp);
       }
       tstart.push_back(bk.corr_tiles);
     }

@@ -12,6 +12,13 @@ namespace slista {
 // because their rows and columns of G and their correlations are 0.
 constexpr int kPadM = 64;
 
+// The tape slots and the row-group copy of c hold N rounded up to whole
+// 64-row tiles (the largest persistent tile), so every tile's loads stay
+// inside them; the rows past N hold 0 in c and are never read as data from
+// the tape.
+constexpr int kTapeRowAlign = 64;
+__host__ __device__ inline int tape_rows(int N) { return (N + kTapeRowAlign - 1) / kTapeRowAlign * kTapeRowAlign; }
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));

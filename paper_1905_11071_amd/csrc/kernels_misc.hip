@@ -188,12 +188,13 @@ __global__ void k_fill(float* __restrict__ p, size_t count, float v) {
 // One thread per (group, column): coalesced reads of four rows, coalesced
 // 16-byte writes.
 __device__ void row_groups(const float* __restrict__ A, int N, int ld, float4* __restrict__ out) {
-  const size_t ng = (size_t)(N + 3) / 4, total = ng * ld;
+  // every group of the tape_rows(N) rows: zeros past N
+  const size_t ng = (size_t)tape_rows(N) / 4, total = ng * ld;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
     const size_t q = e / ld;
     const int j = (int)(e - q * ld), i = (int)(4 * q);
     float4 v;
-    v.x = A[(size_t)i * ld + j];
+    v.x = i < N ? A[(size_t)i * ld + j] : 0.f;
     v.y = i + 1 < N ? A[(size_t)(i + 1) * ld + j] : 0.f;
     v.z = i + 2 < N ? A[(size_t)(i + 2) * ld + j] : 0.f;
     v.w = i + 3 < N ? A[(size_t)(i + 3) * ld + j] : 0.f;
@@ -639,7 +640,7 @@ hipError_t launch_copy_out(const float* Zs, int N, int ldz, int m, float* Z, hip
 }
 
 hipError_t launch_row_groups(const float* A, int N, int ld, float* out, hipStream_t s) {
-  const size_t total = (size_t)(N + 3) / 4 * ld;
+  const size_t total = (size_t)tape_rows(N) / 4 * ld;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_row_groups, dim3(grid_for(total, 256 * 4)), dim3(256), 0, s, A, N, ld, (float4*)out);
   return hipGetLastError();

@@ -613,7 +613,8 @@ __device__ __forceinline__ void fwd_body_fused(const PersistArgs& g, int tile, c
   const int rstride = m_pad * 4;
   const int ustride = m * 4;
   const int na_w = wave_passes<FB, NP, WC>(m_pad, wave);
-  const Rsrc rCg = make_rsrc(g.Cg + (size_t)row0 * m_pad, tape_bytes(nrows, m_pad));
+  // all R rows of the tile: c is stored for tape_rows(N) rows, zeros past N
+  const Rsrc rCg = make_rsrc(g.Cg + (size_t)row0 * m_pad, tape_bytes(R, m_pad));
 
   f32x4 am[NP][FM][FB];  // the master iterate, and the contraction's accumulators
   if (g.t_begin == 0) {
@@ -651,24 +652,23 @@ __device__ __forceinline__ void fwd_body_fused(const PersistArgs& g, int tile, c
       }
       const int colb = 16 * FB * (WC * p + wave) + lr;  // column of block f = 0
       const int lt = (lg * m_pad + colb) * 16;           // per-lane offset, tape order
+      // c of the pass: every load issued before the first use (rows past N
+      // read the zeros stored there, and G z is 0 for them, so z stays 0)
+      float4 cq[FM][FB];
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int f = 0; f < FB; ++f) cq[fm][f] = bload4(rCg, lt + 256 * f, (rbase + 16 * fm) * rstride);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int fm = 0; fm < FM; ++fm) {
-        // rows past N keep z = 0 (their c is stored as 0, and G z is 0)
-        const bool grp = rbase + 16 * fm + 4 * lg < nrows;
-        float cg[FB][4];
 #pragma unroll
         for (int f = 0; f < FB; ++f) {
-          const float4 q = grp ? bload4(rCg, lt + 256 * f, (rbase + 16 * fm) * rstride) : make_float4(0.f, 0.f, 0.f, 0.f);
-          cg[f][0] = q.x;
-          cg[f][1] = q.y;
-          cg[f][2] = q.z;
-          cg[f][3] = q.w;
+          const float cv[4] = {cq[fm][f].x, cq[fm][f].y, cq[fm][f].z, cq[fm][f].w};
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) am[p][fm][f][r4] = soft_threshold(fmaf(a, cv[r4], am[p][fm][f][r4]), th);
         }
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4)
-#pragma unroll
-          for (int f = 0; f < FB; ++f) am[p][fm][f][r4] = soft_threshold(fmaf(a, cg[f][r4], am[p][fm][f][r4]), th);
-        if (store && grp) {
+        if (store && rbase + 16 * fm + 4 * lg < nrows) {
 #pragma unroll
           for (int f = 0; f < FB; ++f)
             bstore4(make_float4(am[p][fm][f][0], am[p][fm][f][1], am[p][fm][f][2], am[p][fm][f][3]), rD,
@@ -722,7 +722,8 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
   const int rstride = m_pad * 4;      // bytes per row of the [N][m_pad] buffers
   const int ustride = m * 4;          // bytes per row of the caller's [N][m] buffers
   float* red = (float*)(lds + R * rowb);
-  const Rsrc rCg = make_rsrc(g.Cg + (size_t)row0 * m_pad, tape_bytes(nrows, m_pad));
+  // all R rows of the tile: c is stored for tape_rows(N) rows, zeros past N
+  const Rsrc rCg = make_rsrc(g.Cg + (size_t)row0 * m_pad, tape_bytes(R, m_pad));
 
   float zm[NP][FM][FB][4];
   float ym[FISTA ? NP : 1][FM][FB][4];  // FISTA's y^t (z^0 = y^0 = 0; t_begin = 0)
@@ -798,7 +799,7 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
         float cg[FB][4];
 #pragma unroll
         for (int f = 0; f < FB; ++f) {
-          const float4 q = grp ? bload4(rCg, lt + 256 * f, (rbase + 16 * fm) * rstride) : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float4 q = bload4(rCg, lt + 256 * f, (rbase + 16 * fm) * rstride);
           cg[f][0] = q.x;
           cg[f][1] = q.y;
           cg[f][2] = q.z;
@@ -837,6 +838,8 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
                     lt + 256 * f, (rbase + 16 * fm) * rstride);
         }
       }
+      // keep the next pass's loads after this pass (registers)
+      __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (TRACE)
       finish_rows<FM, R, WC>(fs, red, wave, rbase, lane, tid, row0, N, g.xsq, g.Ftrace + (size_t)t * N, nullptr);
@@ -914,8 +917,10 @@ __device__ __forceinline__ void bwd_body(const PersistArgs& g, int tile, char* l
 
   for (int t = g.t_hi; t >= g.t_lo; --t) {
     const float a = g.alpha[t];
+    // all R rows of the tile (a slot holds tape_rows(N) rows; groups past N
+    // are not written, so their loads are discarded below)
     const Rsrc rz0 = make_rsrc(t >= 1 ? slot_ptr(g, t) + (size_t)row0 * m_pad : nullptr,
-                               t >= 1 ? tape_bytes(nrows, m_pad) : 0);
+                               t >= 1 ? tape_bytes(R, m_pad) : 0);
     double dsum = -s2;
     s2 = 0.0;
 #pragma unroll
@@ -927,15 +932,18 @@ __device__ __forceinline__ void bwd_body(const PersistArgs& g, int tile, char* l
       const int lt = (lg * m_pad + 16 * FB * slab + lr) * 16;
       if (t >= 1) {
         // z^t of the pass, every load issued before the first is used; row
-        // groups past N read as 0 (v is 0 there too, so they add nothing)
+        // groups past N are taken as 0 (v is 0 there too, so they add nothing)
         float4 zq[FM][FB];
 #pragma unroll
-        for (int fm = 0; fm < FM; ++fm) {
-          const bool grp = rbase + 16 * fm + 4 * lg < nrows;
+        for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
-          for (int f = 0; f < FB; ++f)
-            zq[fm][f] = grp ? bload4(rz0, lt + 256 * f, (rbase + 16 * fm) * rstride) : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
+          for (int f = 0; f < FB; ++f) zq[fm][f] = bload4(rz0, lt + 256 * f, (rbase + 16 * fm) * rstride);
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+          if (rbase + 16 * fm + 4 * lg >= nrows) {
+#pragma unroll
+            for (int f = 0; f < FB; ++f) zq[fm][f] = make_float4(0.f, 0.f, 0.f, 0.f);
+          }
 #pragma unroll
         for (int fm = 0; fm < FM; ++fm) {
 #pragma unroll
