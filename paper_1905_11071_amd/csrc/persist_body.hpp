@@ -637,7 +637,7 @@ __device__ __forceinline__ void fwd_body_fused(const PersistArgs& g, int tile, c
     const float th = uniform_f32(g.lam * a);
     const bool store = g.k > 0 && (g.store_all || (t + 1) % g.k == 0 || t + 1 == g.T || t + 1 > g.a_last);
     const Rsrc rD = make_rsrc(store ? slot_ptr(g, t + 1) + (size_t)row0 * m_pad : nullptr,
-                              store ? tape_bytes(nrows, m_pad) : 0);
+                              store ? tape_bytes(R, m_pad) : 0);
     // z^0 = 0: layer 0 has nothing to contract
     if (t > 0) GroupLoop<FM, FB, NP, WC, NG, PFF, 0>::run(g, lds + rbase * rowb, rowb, wave, lane, na_w, am);
 #pragma unroll
@@ -668,7 +668,8 @@ __device__ __forceinline__ void fwd_body_fused(const PersistArgs& g, int tile, c
 #pragma unroll
           for (int r4 = 0; r4 < 4; ++r4) am[p][fm][f][r4] = soft_threshold(fmaf(a, cv[r4], am[p][fm][f][r4]), th);
         }
-        if (store && rbase + 16 * fm + 4 * lg < nrows) {
+        // whole tile: the rows past N hold 0 and land in the slot's padding
+        if (store) {
 #pragma unroll
           for (int f = 0; f < FB; ++f)
             bstore4(make_float4(am[p][fm][f][0], am[p][fm][f][1], am[p][fm][f][2], am[p][fm][f][3]), rD,
@@ -760,7 +761,7 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
     const float bt = FISTA ? g.beta[t] : 0.f;
     const bool store = g.k > 0 && (g.store_all || (t + 1) % g.k == 0 || t + 1 == g.T || t + 1 > g.a_last);
     const Rsrc rD = make_rsrc(store ? slot_ptr(g, t + 1) + (size_t)row0 * m_pad : nullptr,
-                              store ? tape_bytes(nrows, m_pad) : 0);
+                              store ? tape_bytes(R, m_pad) : 0);
     float fs[FM][4];
     if constexpr (TRACE) {
 #pragma unroll
@@ -831,7 +832,8 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
             zm[p][fm][f][r4] = zn;
           }
         }
-        if (store && rbase + 16 * fm + 4 * lg < nrows) {
+        // whole tile: the rows past N hold 0 and land in the slot's padding
+        if (store) {
 #pragma unroll
           for (int f = 0; f < FB; ++f)
             bstore4(make_float4(zm[p][fm][f][0], zm[p][fm][f][1], zm[p][fm][f][2], zm[p][fm][f][3]), rD,
