@@ -56,14 +56,14 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "6b08d7855f6f70838af26896170ef80b66837deff0902c9a52e5df95769607de",
+    "sources_sha256": "4b35dfe1e145bdfaefbf261e0d2c09d5b5b62146c6d137cb41424f465d72ca46",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {
-        ("bf16", "forward_layer"): (8492612.1875 * 2 + 13632259.75) * 1024,
-        ("bf16", "backward_layer"): (7919832.0 * 2 + 1824.71875) * 1024,
-        ("fp32", "forward_layer"): (14408729.375 * 2 + 13633971.5625) * 1024,
-        ("fp32", "backward_layer"): (13107978.125 * 2 + 3210.90625) * 1024,
+        ("bf16", "forward_layer"): (8593231.1875 * 2 + 13632287.3125) * 1024,
+        ("bf16", "backward_layer"): (8315042.3125 * 2 + 9811.59375) * 1024,
+        ("fp32", "forward_layer"): (13239599.9375 * 2 + 13632346.5625) * 1024,
+        ("fp32", "backward_layer"): (13107342.4375 * 2 + 3201.65625) * 1024,
     },
 }
 
