@@ -48,9 +48,6 @@ constexpr int GB = 4, UB = 2;
 template <int P> struct LElem { static constexpr int bytes = 4; };
 template <> struct LElem<kBF16> { static constexpr int bytes = 2; };
 
-__device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
-
-
 // Store one element into an operand tile in LDS (FP32, or BF16 rounded to nearest even).
 template <int P>
 __device__ __forceinline__ void put_op(char* tile, int rowb, int row, int col, float v) {
