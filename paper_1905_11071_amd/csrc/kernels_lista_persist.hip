@@ -57,6 +57,12 @@ __device__ __forceinline__ void put_op(char* tile, int rowb, int row, int col, f
     *(uint16_t*)(tile + row * rowb + col * 2) = __builtin_bit_cast(uint16_t, (__bf16)v);
 }
 
+// The FP32 master iterate of the BF16 kernels is read and written only by the
+// lane whose accumulators hold the element, so it is kept in accumulator
+// order: the four rows 4q .. 4q+3 of one column are one 16-byte word, and a
+// lane's epilogue moves them with one LDS access instead of four.
+__device__ __forceinline__ int master_at(int row, int col, int m_pad) { return ((row >> 2) * m_pad + col) * 4 + (row & 3); }
+
 template <int P>
 __device__ __forceinline__ f32x4 mma(const uint4& a, const uint4& b, f32x4 c) {
   if constexpr (P == kF32) {
@@ -179,7 +185,7 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
   char* zA = lds;                                         // z^t, operand precision
   char* rA = zA + RB * zrowb;                             // r^t, operand precision
   float* xs = (float*)(rA + RB * rrowb);                  // x, FP32
-  float* zM = xs + RB * n_pad;                            // z^t FP32 master (BF16 mode)
+  float* zM = xs + RB * n_pad;                            // z^t FP32 master (BF16 mode, master_at order)
   double* red = (double*)(zM + (P == kF32 ? 0 : RB * m_pad));  // [NW][RB]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lg = lane >> 4;
@@ -268,6 +274,10 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
 #pragma unroll
           for (int rb = 0; rb < 2; ++rb) {
             uint32_t word = 0;
+            float4* zq = (float4*)(zM + master_at(rb * 16 + 4 * lg, col, m_pad));
+            float4 zm = make_float4(0.f, 0.f, 0.f, 0.f);
+            float zs[4];
+            if constexpr (P != kF32) zm = *zq;
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
               const int row = rb * 16 + 4 * lg + r4;
@@ -275,14 +285,15 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
               if constexpr (P == kF32)
                 z = *(const float*)(zA + row * zrowb + col * 4);
               else
-                z = zM[row * m_pad + col];
+                z = r4 == 0 ? zm.x : r4 == 1 ? zm.y : r4 == 2 ? zm.z : zm.w;
               const float zn = soft_threshold(z - al * acc[g][rb][r4], th);
-              if constexpr (P != kF32) zM[row * m_pad + col] = zn;
+              zs[r4] = zn;
               put_op<P>(zA, zrowb, row, col, zn);
               word |= (uint32_t)((z != 0.f ? 1u : 0u) | (zn > 0.f ? 2u : 0u) | (zn < 0.f ? 4u : 0u)) << (8 * r4);
               if (zT && row0 + row < N) zT[(size_t)(row0 + row) * m_pad + col] = zn;
               if (want_l1) fl[rb][r4] += (double)a.lam * fabs((double)zn);
             }
+            if constexpr (P != kF32) *zq = make_float4(zs[0], zs[1], zs[2], zs[3]);
             if (codes) codes[(size_t)((row0 + rb * 16) / 4 + lg) * m_pad + col] = word;
           }
         }
@@ -304,7 +315,7 @@ __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
   const int vrowb = m_pad * E + 16, qrowb = n_pad * E + 16;
   char* vA = lds;                                   // v^t, operand precision
   char* qA = vA + RB * vrowb;                       // W_t v, operand precision
-  float* vM = (float*)(qA + RB * qrowb);            // v^t FP32 master (BF16 mode)
+  float* vM = (float*)(qA + RB * qrowb);            // v^t FP32 master (BF16 mode, master_at order)
   double* red = (double*)(vM + (P == kF32 ? 0 : RB * m_pad));  // [2][NW]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lg = lane >> 4;
@@ -316,7 +327,7 @@ __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
       const int r = e / m_pad, c = e - r * m_pad;
       const float v = row0 + r < N ? a.vseed[(size_t)(row0 + r) * m_pad + c] : 0.f;
       put_op<P>(vA, vrowb, r, c, v);
-      if constexpr (P != kF32) vM[e] = v;
+      if constexpr (P != kF32) vM[master_at(r, c, m_pad)] = v;
     }
     float* vt = a.vtape + (size_t)(T - 1) * vlayer;
     for (int e = tid; e < RB * a.m; e += NT) {
@@ -395,6 +406,9 @@ __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
 #pragma unroll
           for (int rb = 0; rb < 2; ++rb) {
             float vv[4];
+            float4* vq = (float4*)(vM + master_at(rb * 16 + 4 * lg, col, m_pad));
+            float4 vm = make_float4(0.f, 0.f, 0.f, 0.f);
+            if constexpr (P != kF32) vm = *vq;
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
               const int row = rb * 16 + 4 * lg + r4;
@@ -402,15 +416,15 @@ __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
               if constexpr (P == kF32)
                 v = *(const float*)(vA + row * vrowb + col * 4);
               else
-                v = vM[row * m_pad + col];
+                v = r4 == 0 ? vm.x : r4 == 1 ? vm.y : r4 == 2 ? vm.z : vm.w;
               const uint32_t code = cw[g][rb] >> (8 * r4);
               const float sg = (code & 2u) ? 1.f : ((code & 4u) ? -1.f : 0.f);
               db += (double)v * (double)sg;
               const float vn = (code & 1u) ? v - al * acc[g][rb][r4] : 0.f;
               vv[r4] = vn;
-              if constexpr (P != kF32) vM[row * m_pad + col] = vn;
               put_op<P>(vA, vrowb, row, col, vn);
             }
+            if constexpr (P != kF32) *vq = make_float4(vv[0], vv[1], vv[2], vv[3]);
             if (vt && col < a.m) {
               const int i = row0 + rb * 16 + 4 * lg;
               *(float4*)(vt + (size_t)(i / Kc) * a.m * Kc + (size_t)col * Kc + i % Kc) =
