@@ -235,8 +235,14 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
               const float r = acc[g][rb][r4] - xs[row * n_pad + col];
               rv[r4] = r;
               put_op<P>(rA, rrowb, row, col, r);
-              if (rT && row0 + row < N) rT[(size_t)(row0 + row) * n_pad + col] = r;
               if (want_f) fr[rb][r4] += 0.5 * (double)r * (double)r;
+            }
+            if (rT) {  // after the last layer only
+#pragma unroll
+              for (int r4 = 0; r4 < 4; ++r4) {
+                const int i = row0 + rb * 16 + 4 * lg + r4;
+                if (i < N) rT[(size_t)i * n_pad + col] = rv[r4];
+              }
             }
             if (rtape && col < a.n) {  // 4 consecutive samples of one chunk (rows >= N hold 0)
               const int i = row0 + rb * 16 + 4 * lg;
@@ -290,10 +296,16 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
               zs[r4] = zn;
               put_op<P>(zA, zrowb, row, col, zn);
               word |= (uint32_t)((z != 0.f ? 1u : 0u) | (zn > 0.f ? 2u : 0u) | (zn < 0.f ? 4u : 0u)) << (8 * r4);
-              if (zT && row0 + row < N) zT[(size_t)(row0 + row) * m_pad + col] = zn;
               if (want_l1) fl[rb][r4] += (double)a.lam * fabs((double)zn);
             }
             if constexpr (P != kF32) *zq = make_float4(zs[0], zs[1], zs[2], zs[3]);
+            if (zT) {  // last layer only: one uniform branch, not a masked store per element
+#pragma unroll
+              for (int r4 = 0; r4 < 4; ++r4) {
+                const int i = row0 + rb * 16 + 4 * lg + r4;
+                if (i < N) zT[(size_t)i * m_pad + col] = zs[r4];
+              }
+            }
             if (codes) codes[(size_t)((row0 + rb * 16) / 4 + lg) * m_pad + col] = word;
           }
         }
