@@ -57,10 +57,11 @@ __device__ __forceinline__ void put_op(char* tile, int rowb, int row, int col, f
     *(uint16_t*)(tile + row * rowb + col * 2) = __builtin_bit_cast(uint16_t, (__bf16)v);
 }
 
-// The FP32 master iterate of the BF16 kernels is read and written only by the
-// lane whose accumulators hold the element, so it is kept in accumulator
-// order: the four rows 4q .. 4q+3 of one column are one 16-byte word, and a
-// lane's epilogue moves them with one LDS access instead of four.
+// The FP32 master iterate of the BF16 kernels (and the forward's copy of x) is
+// read and written only by the lane whose accumulators hold the element, so it
+// is kept in accumulator order: the four rows 4q .. 4q+3 of one column are one
+// 16-byte word, and a lane's epilogue moves them with one LDS access instead of
+// four.
 __device__ __forceinline__ int master_at(int row, int col, int m_pad) { return ((row >> 2) * m_pad + col) * 4 + (row & 3); }
 
 template <int P>
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
   const int zrowb = m_pad * E + 16, rrowb = n_pad * E + 16;
   char* zA = lds;                                         // z^t, operand precision
   char* rA = zA + RB * zrowb;                             // r^t, operand precision
-  float* xs = (float*)(rA + RB * rrowb);                  // x, FP32
+  float* xs = (float*)(rA + RB * rrowb);                  // x, FP32 (master_at order over n_pad)
   float* zM = xs + RB * n_pad;                            // z^t FP32 master (BF16 mode, master_at order)
   double* red = (double*)(zM + (P == kF32 ? 0 : RB * m_pad));  // [NW][RB]
 
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
   const int row0 = blockIdx.x * RB;
   for (int e = tid; e < RB * n_pad; e += NT) {
     const int r = e / n_pad, c = e - r * n_pad;
-    xs[e] = row0 + r < N ? a.Xp[(size_t)(row0 + r) * n_pad + c] : 0.f;
+    xs[master_at(r, c, n_pad)] = row0 + r < N ? a.Xp[(size_t)(row0 + r) * n_pad + c] : 0.f;
   }
   for (int e = tid; e < RB * m_pad; e += NT) {
     const int r = e / m_pad, c = e - r * m_pad;
@@ -229,10 +230,11 @@ __global__ __launch_bounds__(NT, 2) void lista_fwd_persist(ListaPersistArgs a) {
 #pragma unroll
           for (int rb = 0; rb < 2; ++rb) {
             float rv[4];
+            const float4 xq = *(const float4*)(xs + master_at(rb * 16 + 4 * lg, col, n_pad));
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
               const int row = rb * 16 + 4 * lg + r4;
-              const float r = acc[g][rb][r4] - xs[row * n_pad + col];
+              const float r = acc[g][rb][r4] - (r4 == 0 ? xq.x : r4 == 1 ? xq.y : r4 == 2 ? xq.z : xq.w);
               rv[r4] = r;
               put_op<P>(rA, rrowb, row, col, r);
               if (want_f) fr[rb][r4] += 0.5 * (double)r * (double)r;
