@@ -365,6 +365,17 @@ __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
       const float* R = a.rtape + (size_t)t * rlayer;
       const char* W = (const char*)a.Wr + (size_t)t * n_pad * m_pad * E;
       for (int c0 = wave; c0 < ncbA; c0 += 4 * GA) {
+        float4 rv[GA][2];  // R^t of 4 consecutive samples (0 for rows >= N), in flight during the contraction
+#pragma unroll
+        for (int g = 0; g < GA; ++g)
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb) {
+            const int col = (c0 + 4 * g) * 16 + lr;
+            const int i = row0 + rb * 16 + 4 * lg;
+            rv[g][rb] = c0 + 4 * g < ncbA && col < a.n
+                            ? *(const float4*)(R + (size_t)(i / Kc) * a.n * Kc + (size_t)col * Kc + i % Kc)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
         f32x4 acc[GA][2];
         if (c0 != wave) load_b(preA, W, (size_t)m_pad * E, 0, nkA, c0, ncbA, lr, lg);
         contract<P, GA, UA>(vA, vrowb, W, (size_t)m_pad * E, nkA, c0, ncbA, acc, preA, lr, lg);
@@ -376,12 +387,7 @@ __global__ __launch_bounds__(NT, 2) void lista_bwd_persist(ListaPersistArgs a) {
           const int col = cb * 16 + lr;
 #pragma unroll
           for (int rb = 0; rb < 2; ++rb) {
-            float4 rv = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (col < a.n) {  // R^t of 4 consecutive samples (0 for rows >= N)
-              const int i = row0 + rb * 16 + 4 * lg;
-              rv = *(const float4*)(R + (size_t)(i / Kc) * a.n * Kc + (size_t)col * Kc + i % Kc);
-            }
-            const float rr[4] = {rv.x, rv.y, rv.z, rv.w};
+            const float rr[4] = {rv[g][rb].x, rv[g][rb].y, rv[g][rb].z, rv[g][rb].w};
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
               const int row = rb * 16 + 4 * lg + r4;
